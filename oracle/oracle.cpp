@@ -1,0 +1,660 @@
+/*
+ * CPU oracle of the MrHash fusion hot path -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Plain C++17, FP64 values, a std::map keyed by integer block coordinates, no threads, no SIMD.
+ * Built with -ffp-contract=off so every expression below is evaluated exactly as written: the
+ * discrete decisions (block keys, traversal cells, pixel indices, the -tau gate, the query lattice
+ * index) follow one fixed sequence of IEEE-754 double operations, and multiplications by inverses
+ * computed once stand in for divisions wherever a decision depends on them.
+ *
+ * Per frame the steps follow the paper's pipeline order (Sec. 3, system overview figure):
+ *   1. points from the sensor (Sec. 3.1),
+ *   2. allocation of every block a measurement segment crosses, by a DDA walk (Sec. 3.2),
+ *   3. TSDF / weight / Welford update of the voxels (Eq. 1 or Eq. 2, then Eq. 3 and Eq. 5),
+ *   4. block mean variance and the merging criterion (Sec. 3.2.1, Eq. 6).
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <vector>
+
+namespace {
+
+using Key = std::array<int32_t, 3>;
+
+/* Block coordinates must stay within +-(2^20 - 2) so that every cell a walk may reach fits a
+ * 21-bit signed field. A point whose segment end cells leave that range is dropped. */
+constexpr int64_t kKeyLimit = (int64_t(1) << 20) - 2;
+
+struct Block {
+    int level = 0;
+    std::vector<double> D, S2;   /* running mean (Eq. 3) and sum of squared deviations (Eq. 5) */
+    std::vector<uint64_t> W;     /* integer weight, w_k = 1 per observation (Sec. 3.1) */
+    bool touched = false;        /* some voxel was updated in the current frame */
+};
+
+struct NearEvent {
+    Key key;
+    int64_t frame;
+    double margin;
+};
+
+struct Map {
+    orc_config cfg;
+    double B = 0, invB = 0;      /* constant metric block edge (Sec. 3.2) and its inverse */
+    double nu[4] = {0}, inv_nu[4] = {0};
+    std::map<Key, Block> blocks;
+    orc_stats last{};
+    std::vector<NearEvent> near;
+    int64_t frame = 0;
+};
+
+int side(int level) { return 8 >> level; }
+
+void new_block(Block& b, int level) {
+    const int m = side(level);
+    b.level = level;
+    b.D.assign(size_t(m) * m * m, 0.0);
+    b.S2.assign(size_t(m) * m * m, 0.0);
+    b.W.assign(size_t(m) * m * m, 0);
+    b.touched = false;
+}
+
+struct Pose {
+    double R[3][3];
+    double t[3];
+    explicit Pose(const double* T) {
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) R[r][c] = T[4 * r + c];
+            t[r] = T[4 * r + 3];
+        }
+    }
+    /* world <- sensor: ((R00 x + R01 y) + R02 z) + t0 */
+    void apply(const double p[3], double out[3]) const {
+        for (int r = 0; r < 3; ++r) out[r] = ((R[r][0] * p[0] + R[r][1] * p[1]) + R[r][2] * p[2]) + t[r];
+    }
+    /* sensor <- world for a point: R^T (x - t) */
+    void inverse(const double x[3], double out[3]) const {
+        const double d0 = x[0] - t[0], d1 = x[1] - t[1], d2 = x[2] - t[2];
+        for (int r = 0; r < 3; ++r) out[r] = (R[0][r] * d0 + R[1][r] * d1) + R[2][r] * d2;
+    }
+};
+
+/* Unit direction from the sensor origin o to the world point p (Eq. 1, n-hat). */
+void unit_dir(const double p[3], const double o[3], double n[3]) {
+    const double v0 = p[0] - o[0], v1 = p[1] - o[1], v2 = p[2] - o[2];
+    const double inv = 1.0 / std::sqrt((v0 * v0 + v1 * v1) + v2 * v2);
+    n[0] = v0 * inv;
+    n[1] = v1 * inv;
+    n[2] = v2 * inv;
+}
+
+/*
+ * Amanatides-Woo traversal (the DDA of Sec. 3.1 / 3.2) of the segment a -> e over the lattice of
+ * cubic cells of edge 1 / inv_cell.  Cells are half-open; the walk starts in the cell holding a,
+ * steps across the nearest boundary (lowest axis first on ties), and stops once the next boundary
+ * lies beyond e.  Each boundary parameter is evaluated afresh from the cell index, not accumulated.
+ */
+void block_walk(const double a[3], const double e[3], double inv_cell, std::vector<std::array<int64_t, 3>>& out) {
+    double A[3], E[3], invD[3], tmax[3];
+    int64_t c[3];
+    int st[3];
+    int64_t guard = 3;
+    for (int k = 0; k < 3; ++k) {
+        A[k] = a[k] * inv_cell;
+        E[k] = e[k] * inv_cell;
+        c[k] = (int64_t)std::floor(A[k]);
+        const double dv = E[k] - A[k];
+        guard += std::llabs((int64_t)std::floor(E[k]) - c[k]);
+        if (dv > 0.0) {
+            st[k] = 1;
+            invD[k] = 1.0 / dv;
+            tmax[k] = ((double)(c[k] + 1) - A[k]) * invD[k];
+        } else if (dv < 0.0) {
+            st[k] = -1;
+            invD[k] = 1.0 / dv;
+            tmax[k] = ((double)c[k] - A[k]) * invD[k];
+        } else {
+            st[k] = 0;
+            invD[k] = 0.0;
+            tmax[k] = std::numeric_limits<double>::infinity();
+        }
+    }
+    out.push_back({c[0], c[1], c[2]});
+    for (int64_t s = 0; s < guard; ++s) {
+        int k = 0;
+        if (tmax[1] < tmax[k]) k = 1;
+        if (tmax[2] < tmax[k]) k = 2;
+        if (!(tmax[k] <= 1.0)) break;
+        c[k] += st[k];
+        tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - A[k]) * invD[k];
+        out.push_back({c[0], c[1], c[2]});
+    }
+}
+
+/*
+ * The same traversal restricted to one block: the segment is clipped to the block's box, the walk
+ * starts in the (clamped) cell holding the clipped entry point and continues on the block's own
+ * lattice of m^3 voxels until it leaves the block or passes the clipped exit parameter.
+ */
+void voxel_walk(const double a[3], const double e[3], const Key& b, double B, double inv_nu, int m,
+                std::vector<std::array<int, 3>>& out) {
+    double Al[3], Dl[3], invD[3], tmax[3];
+    int st[3], c[3];
+    double tin = 0.0, tout = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        const double ob = (double)b[k] * B;
+        Al[k] = (a[k] - ob) * inv_nu;
+        const double El = (e[k] - ob) * inv_nu;
+        Dl[k] = El - Al[k];
+        if (Dl[k] != 0.0) {
+            invD[k] = 1.0 / Dl[k];
+            const double nearb = Dl[k] > 0.0 ? 0.0 : (double)m;
+            const double farb = Dl[k] > 0.0 ? (double)m : 0.0;
+            const double t0 = (nearb - Al[k]) * invD[k];
+            const double t1 = (farb - Al[k]) * invD[k];
+            if (t0 > tin) tin = t0;
+            if (t1 < tout) tout = t1;
+            st[k] = Dl[k] > 0.0 ? 1 : -1;
+        } else {
+            invD[k] = 0.0;
+            st[k] = 0;
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        const double P = Al[k] + tin * Dl[k];
+        double f = std::floor(P);
+        if (f < 0.0) f = 0.0;
+        if (f > (double)(m - 1)) f = (double)(m - 1);
+        c[k] = (int)f;
+        tmax[k] = st[k] != 0 ? ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k]
+                             : std::numeric_limits<double>::infinity();
+    }
+    out.push_back({c[0], c[1], c[2]});
+    for (int s = 0; s < 3 * m; ++s) {
+        int k = 0;
+        if (tmax[1] < tmax[k]) k = 1;
+        if (tmax[2] < tmax[k]) k = 2;
+        if (!(tmax[k] <= tout)) break;
+        c[k] += st[k];
+        if (c[k] < 0 || c[k] >= m) break;
+        tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k];
+        out.push_back({c[0], c[1], c[2]});
+    }
+}
+
+bool in_key_range(const double a[3], const double e[3], double invB) {
+    for (int k = 0; k < 3; ++k) {
+        const double fa = std::floor(a[k] * invB), fe = std::floor(e[k] * invB);
+        if (!(std::fabs(fa) <= (double)kKeyLimit && std::fabs(fe) <= (double)kKeyLimit)) return false;
+    }
+    return true;
+}
+
+/* Allocate every block the segment crosses at the finest level (Sec. 3.2.1: blocks start fine). */
+void allocate(Map& m, const double a[3], const double e[3]) {
+    std::vector<std::array<int64_t, 3>> cells;
+    block_walk(a, e, m.invB, cells);
+    for (const auto& c : cells) {
+        const Key k{(int32_t)c[0], (int32_t)c[1], (int32_t)c[2]};
+        auto it = m.blocks.find(k);
+        if (it == m.blocks.end()) {
+            new_block(m.blocks[k], 0);
+            m.last.new_blocks++;
+        }
+    }
+}
+
+/* Voxel centre: block origin b * B plus (i + 1/2) voxel edges of the block's level. */
+void voxel_centre(const Map& m, const Key& b, int level, int i, int j, int k, double c[3]) {
+    const double nu = m.nu[level];
+    c[0] = (double)b[0] * m.B + ((double)i + 0.5) * nu;
+    c[1] = (double)b[1] * m.B + ((double)j + 0.5) * nu;
+    c[2] = (double)b[2] * m.B + ((double)k + 0.5) * nu;
+}
+
+/* Eq. 3 with w_k = 1 and the Welford recurrence of Eq. 5, in incremental form. */
+void observe(Block& blk, int idx, double d) {
+    const uint64_t W = blk.W[idx] + 1;
+    const double Dold = blk.D[idx];
+    const double Dnew = Dold + (d - Dold) / (double)W;
+    blk.S2[idx] = blk.S2[idx] + (d - Dold) * (d - Dnew);
+    blk.D[idx] = Dnew;
+    blk.W[idx] = W;
+    blk.touched = true;
+}
+
+/*
+ * Merging criterion (Sec. 3.2.1): the block mean of the voxel variances sigma^2 = S2 / W (Eq. 6),
+ * over voxels with at least min_obs observations, is compared with the threshold; a block below it
+ * is re-sampled one level coarser.  Pooling of the 2x2x2 children of each coarse voxel keeps the
+ * total weight and the weighted TSDF sum, and adds up the children's S2.
+ */
+void merge_block(Map& m, Block& blk) {
+    const int n = blk.level, mf = side(n), mc = mf / 2;
+    std::vector<double> D(size_t(mc) * mc * mc), S2(size_t(mc) * mc * mc);
+    std::vector<uint64_t> W(size_t(mc) * mc * mc);
+    for (int K = 0; K < mc; ++K)
+        for (int J = 0; J < mc; ++J)
+            for (int I = 0; I < mc; ++I) {
+                uint64_t w = 0;
+                double sd = 0.0, s2 = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            const int f = (2 * I + a) + mf * ((2 * J + b) + mf * (2 * K + c));
+                            if (blk.W[f] == 0) continue;
+                            w += blk.W[f];
+                            sd += (double)blk.W[f] * blk.D[f];
+                            s2 += blk.S2[f];
+                        }
+                const int o = I + mc * (J + mc * K);
+                W[o] = w;
+                D[o] = w > 0 ? sd / (double)w : 0.0;
+                S2[o] = w > 0 ? s2 : 0.0;
+            }
+    blk.level = n + 1;
+    blk.D.swap(D);
+    blk.W.swap(W);
+    blk.S2.swap(S2);
+    (void)m;
+}
+
+void variance_and_merge(Map& m) {
+    const double thr = m.cfg.var_thr;
+    for (auto& kv : m.blocks) {
+        Block& blk = kv.second;
+        if (!blk.touched) continue;
+        blk.touched = false;
+        if (blk.level >= m.cfg.levels - 1) continue;
+        double sum = 0.0;
+        int64_t cnt = 0;
+        for (size_t v = 0; v < blk.W.size(); ++v) {
+            if (blk.W[v] >= (uint64_t)m.cfg.min_obs) {
+                sum += blk.S2[v] / (double)blk.W[v];
+                cnt++;
+            }
+        }
+        if (cnt == 0) continue;
+        const double mv = sum / (double)cnt;
+        const double margin = std::fabs(mv - thr) / thr;
+        if (margin < 1e-3) {
+            m.near.push_back({kv.first, m.frame, margin});
+            m.last.near_threshold++;
+        }
+        if (mv < thr) {
+            m.last.merges[blk.level]++;
+            merge_block(m, blk);
+        }
+    }
+}
+
+bool depth_ok(double d, double max_depth) { return std::isfinite(d) && d > 0.0 && d <= max_depth; }
+
+int64_t floor_div(int64_t c, int64_t m) { return c >= 0 ? c / m : -((-c + m - 1) / m); }
+
+const Block* find(const Map& m, int64_t x, int64_t y, int64_t z) {
+    if (std::llabs(x) > kKeyLimit + 2 || std::llabs(y) > kKeyLimit + 2 || std::llabs(z) > kKeyLimit + 2) return nullptr;
+    auto it = m.blocks.find(Key{(int32_t)x, (int32_t)y, (int32_t)z});
+    return it == m.blocks.end() ? nullptr : &it->second;
+}
+
+/*
+ * Multi-resolution trilinear interpolation (Sec. 3.4): the point's own block fixes the lattice
+ * (its level n); the 8 surrounding level-n lattice points are read from whichever voxel, at any
+ * level, contains them; corners in absent blocks or with W = 0 drop out and the remaining
+ * trilinear weights are renormalised.
+ */
+struct QueryOut {
+    bool valid = false;
+    double sdf = 0.0;
+    double grad[3] = {0, 0, 0};
+};
+
+QueryOut query_one(const Map& m, const double x[3], bool strict) {
+    QueryOut q;
+    int64_t bk[3];
+    for (int k = 0; k < 3; ++k) {
+        const double f = std::floor(x[k] * m.invB);
+        if (!(std::fabs(f) <= (double)kKeyLimit)) return q;
+        bk[k] = (int64_t)f;
+    }
+    const Block* home = find(m, bk[0], bk[1], bk[2]);
+    if (!home) return q;
+    const int n = home->level;
+    int64_t i0[3];
+    double f[3];
+    for (int k = 0; k < 3; ++k) {
+        const double g = x[k] * m.inv_nu[n] - 0.5;
+        const double fl = std::floor(g);
+        i0[k] = (int64_t)fl;
+        f[k] = g - fl;
+    }
+    const int64_t mn = side(n);
+    double wsum = 0.0, num = 0.0;
+    double cw[8], cd[8];
+    bool cv[8];
+    int nvalid = 0;
+    bool any_pos = false;
+    for (int c = 0; c < 8; ++c) {
+        const int dl[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        int64_t cell[3], cb[3];
+        for (int k = 0; k < 3; ++k) {
+            cell[k] = i0[k] + dl[k];
+            cb[k] = floor_div(cell[k], mn);
+        }
+        cw[c] = (dl[0] ? f[0] : 1.0 - f[0]) * (dl[1] ? f[1] : 1.0 - f[1]) * (dl[2] ? f[2] : 1.0 - f[2]);
+        cv[c] = false;
+        cd[c] = 0.0;
+        const Block* blk = find(m, cb[0], cb[1], cb[2]);
+        if (!blk) continue;
+        const int n2 = blk->level, m2 = side(n2);
+        int idx[3];
+        for (int k = 0; k < 3; ++k) {
+            /* lattice point (cell + 1/2) nu_n expressed in half finest voxels, relative to the block */
+            const int64_t p2 = cell[k] * (int64_t(2) << n) + (int64_t(1) << n);
+            const int64_t local2 = p2 - 16 * cb[k];
+            idx[k] = (int)(local2 / (int64_t(2) << n2));
+        }
+        const int v = idx[0] + m2 * (idx[1] + m2 * idx[2]);
+        if (blk->W[v] == 0) continue;
+        cv[c] = true;
+        cd[c] = blk->D[v];
+        nvalid++;
+        wsum += cw[c];
+        num += cw[c] * cd[c];
+        if (cw[c] > 0.0) any_pos = true;
+    }
+    if (strict ? nvalid < 8 : !any_pos) return q;
+    q.valid = true;
+    q.sdf = num / wsum;
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            if (!cv[c]) continue;
+            const int dl[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+            double dw = dl[a] ? 1.0 : -1.0;
+            for (int b = 0; b < 3; ++b)
+                if (b != a) dw *= dl[b] ? f[b] : 1.0 - f[b];
+            s += dw * (cd[c] - q.sdf);
+        }
+        q.grad[a] = s / wsum * m.inv_nu[n];
+    }
+    return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+void* orc_create(const orc_config* cfg) {
+    if (!cfg || cfg->levels < 1 || cfg->levels > 4 || !(cfg->voxel > 0.0)) return nullptr;
+    Map* m = new Map();
+    m->cfg = *cfg;
+    m->B = 8.0 * cfg->voxel;
+    m->invB = 1.0 / m->B;
+    for (int n = 0; n < 4; ++n) {
+        m->nu[n] = cfg->voxel * (double)(1 << n);
+        m->inv_nu[n] = 1.0 / m->nu[n];
+    }
+    return m;
+}
+
+void orc_destroy(void* map) { delete static_cast<Map*>(map); }
+
+int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t height,
+                        const double K[4], const double T_ws[16]) {
+    Map& m = *static_cast<Map*>(map);
+    m.last = orc_stats{};
+    const Pose P(T_ws);
+    const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+    const double ifx = 1.0 / fx, ify = 1.0 / fy;
+    const double tau = m.cfg.tau;
+
+    /* 1-2: back-project every valid pixel and allocate the blocks its band [p - tau n, p + tau n]
+     * crosses. */
+    for (int v = 0; v < height; ++v)
+        for (int u = 0; u < width; ++u) {
+            const double d = (double)depth[(int64_t)v * width + u];
+            if (!depth_ok(d, m.cfg.max_depth)) continue;
+            m.last.valid_points++;
+            const double ps[3] = {(((double)u - cx) * ifx) * d, (((double)v - cy) * ify) * d, d};
+            double pw[3], n[3];
+            P.apply(ps, pw);
+            unit_dir(pw, P.t, n);
+            const double a[3] = {pw[0] - tau * n[0], pw[1] - tau * n[1], pw[2] - tau * n[2]};
+            const double e[3] = {pw[0] + tau * n[0], pw[1] + tau * n[1], pw[2] + tau * n[2]};
+            if (!in_key_range(a, e, m.invB)) {
+                m.last.dropped_points++;
+                continue;
+            }
+            allocate(m, a, e);
+        }
+
+    /* 3: projective update of every voxel of every allocated block, at the block's level (Eq. 2). */
+    for (auto& kv : m.blocks) {
+        const Key& b = kv.first;
+        Block& blk = kv.second;
+        const int mm = side(blk.level);
+        for (int k = 0; k < mm; ++k)
+            for (int j = 0; j < mm; ++j)
+                for (int i = 0; i < mm; ++i) {
+                    double c[3], x[3];
+                    voxel_centre(m, b, blk.level, i, j, k, c);
+                    P.inverse(c, x);
+                    if (!(x[2] > 0.0)) continue;
+                    const double iz = 1.0 / x[2];
+                    const double uu = (fx * (x[0] * iz)) + cx;
+                    const double vv = (fy * (x[1] * iz)) + cy;
+                    const double fu = std::floor(uu + 0.5), fv = std::floor(vv + 0.5);
+                    if (!(fu >= 0.0 && fu <= (double)(width - 1) && fv >= 0.0 && fv <= (double)(height - 1)))
+                        continue;
+                    const double d = (double)depth[(int64_t)fv * width + (int64_t)fu];
+                    if (!depth_ok(d, m.cfg.max_depth)) continue;
+                    double raw;
+                    if (m.cfg.form == 0) {
+                        /* measured range along the voxel's ray minus the voxel's range ||x|| */
+                        const double nx = std::sqrt((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]);
+                        raw = nx * ((d * iz) - 1.0);
+                    } else {
+                        raw = d - x[2];
+                    }
+                    if (raw < -tau) continue; /* occluded beyond the truncation band */
+                    const double obs = raw < tau ? raw : tau;
+                    observe(blk, i + mm * (j + mm * k), obs);
+                    m.last.observations++;
+                }
+    }
+
+    /* 4: variance and merging criterion. */
+    variance_and_merge(m);
+    m.frame++;
+    return 0;
+}
+
+int orc_integrate_points(void* map, const float* xyz, int64_t n, const double T_ws[16]) {
+    Map& m = *static_cast<Map*>(map);
+    m.last = orc_stats{};
+    const Pose P(T_ws);
+    const double tau = m.cfg.tau;
+    const double r2lo = m.cfg.min_range * m.cfg.min_range;
+    const double r2hi = m.cfg.max_range * m.cfg.max_range;
+
+    struct Seg {
+        double a[3], e[3], p[3], n[3];
+    };
+    std::vector<Seg> segs;
+    segs.reserve((size_t)n);
+    /* 1-2: valid points and allocation along each segment. */
+    for (int64_t i = 0; i < n; ++i) {
+        const double ps[3] = {(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
+        if (!(std::isfinite(ps[0]) && std::isfinite(ps[1]) && std::isfinite(ps[2]))) continue;
+        const double r2 = (ps[0] * ps[0] + ps[1] * ps[1]) + ps[2] * ps[2];
+        if (!(r2 >= r2lo && r2 <= r2hi)) continue;
+        m.last.valid_points++;
+        Seg s;
+        P.apply(ps, s.p);
+        unit_dir(s.p, P.t, s.n);
+        for (int k = 0; k < 3; ++k) {
+            s.a[k] = m.cfg.carve ? P.t[k] : s.p[k] - tau * s.n[k];
+            s.e[k] = s.p[k] + tau * s.n[k];
+        }
+        if (!in_key_range(s.a, s.e, m.invB)) {
+            m.last.dropped_points++;
+            continue;
+        }
+        allocate(m, s.a, s.e);
+        segs.push_back(s);
+    }
+
+    /* 3: every voxel a ray crosses, at its block's level, receives clip((p - x) . n, -tau, tau)
+     * (Eq. 1); observations are applied in point order, then in walk order along each ray. */
+    std::vector<std::array<int64_t, 3>> cells;
+    std::vector<std::array<int, 3>> vox;
+    for (const Seg& s : segs) {
+        cells.clear();
+        block_walk(s.a, s.e, m.invB, cells);
+        for (const auto& c : cells) {
+            const Key b{(int32_t)c[0], (int32_t)c[1], (int32_t)c[2]};
+            Block& blk = m.blocks.at(b);
+            const int mm = side(blk.level);
+            vox.clear();
+            voxel_walk(s.a, s.e, b, m.B, m.inv_nu[blk.level], mm, vox);
+            for (const auto& v : vox) {
+                double x[3];
+                voxel_centre(m, b, blk.level, v[0], v[1], v[2], x);
+                const double sd = ((s.p[0] - x[0]) * s.n[0] + (s.p[1] - x[1]) * s.n[1]) + (s.p[2] - x[2]) * s.n[2];
+                const double obs = sd < -tau ? -tau : (sd > tau ? tau : sd);
+                observe(blk, v[0] + mm * (v[1] + mm * v[2]), obs);
+                m.last.observations++;
+            }
+        }
+    }
+
+    /* 4: variance and merging criterion. */
+    variance_and_merge(m);
+    m.frame++;
+    return 0;
+}
+
+void orc_last_stats(const void* map, orc_stats* out) { *out = static_cast<const Map*>(map)->last; }
+
+int64_t orc_num_blocks(const void* map) { return (int64_t) static_cast<const Map*>(map)->blocks.size(); }
+
+int64_t orc_num_voxels(const void* map) {
+    int64_t s = 0;
+    for (const auto& kv : static_cast<const Map*>(map)->blocks) s += (int64_t)kv.second.W.size();
+    return s;
+}
+
+void orc_extract(const void* map, int32_t* keys, uint8_t* levels, int64_t* offsets, double* D,
+                 uint32_t* W, double* S2) {
+    const Map& m = *static_cast<const Map*>(map);
+    int64_t i = 0, off = 0;
+    if (offsets) offsets[0] = 0;
+    for (const auto& kv : m.blocks) {
+        const Block& b = kv.second;
+        if (keys) {
+            keys[3 * i] = kv.first[0];
+            keys[3 * i + 1] = kv.first[1];
+            keys[3 * i + 2] = kv.first[2];
+        }
+        if (levels) levels[i] = (uint8_t)b.level;
+        for (size_t v = 0; v < b.W.size(); ++v) {
+            if (D) D[off + (int64_t)v] = b.D[v];
+            if (W) W[off + (int64_t)v] = (uint32_t)b.W[v];
+            if (S2) S2[off + (int64_t)v] = b.S2[v];
+        }
+        off += (int64_t)b.W.size();
+        ++i;
+        if (offsets) offsets[i] = off;
+    }
+}
+
+int64_t orc_near_threshold(const void* map, int32_t* keys, int64_t* frames, double* margins, int64_t cap) {
+    const Map& m = *static_cast<const Map*>(map);
+    const int64_t n = (int64_t)m.near.size();
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        if (keys) {
+            keys[3 * i] = m.near[i].key[0];
+            keys[3 * i + 1] = m.near[i].key[1];
+            keys[3 * i + 2] = m.near[i].key[2];
+        }
+        if (frames) frames[i] = m.near[i].frame;
+        if (margins) margins[i] = m.near[i].margin;
+    }
+    return n;
+}
+
+void orc_query(const void* map, const float* pts, int64_t n, const double* T, int32_t strict,
+               double* sdf, uint8_t* valid, double* grad_world) {
+    const Map& m = *static_cast<const Map*>(map);
+    static const double I4[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    const Pose P(T ? T : I4);
+    for (int64_t i = 0; i < n; ++i) {
+        const double p[3] = {(double)pts[3 * i], (double)pts[3 * i + 1], (double)pts[3 * i + 2]};
+        double x[3];
+        if (T) P.apply(p, x);
+        else x[0] = p[0], x[1] = p[1], x[2] = p[2];
+        const QueryOut q = query_one(m, x, strict != 0);
+        if (sdf) sdf[i] = q.sdf;
+        if (valid) valid[i] = q.valid ? 1 : 0;
+        if (grad_world)
+            for (int k = 0; k < 3; ++k) grad_world[3 * i + k] = q.grad[k];
+    }
+}
+
+void orc_query_backward(const void* map, const float* pts, int64_t n, const double* T, int32_t strict,
+                        const double* grad_sdf, double* grad_pts, double grad_pose[6]) {
+    const Map& m = *static_cast<const Map*>(map);
+    static const double I4[16] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    const Pose P(T ? T : I4);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        const double p[3] = {(double)pts[3 * i], (double)pts[3 * i + 1], (double)pts[3 * i + 2]};
+        double x[3];
+        if (T) P.apply(p, x);
+        else x[0] = p[0], x[1] = p[1], x[2] = p[2];
+        const QueryOut q = query_one(m, x, strict != 0);
+        double g[3] = {0, 0, 0};
+        if (q.valid)
+            for (int k = 0; k < 3; ++k) g[k] = grad_sdf[i] * q.grad[k];
+        /* dL/dp = R^T g; left perturbation x' = x + rho + phi x x gives dL/drho = g, dL/dphi = x x g */
+        for (int r = 0; r < 3; ++r)
+            grad_pts[3 * i + r] = (P.R[0][r] * g[0] + P.R[1][r] * g[1]) + P.R[2][r] * g[2];
+        acc[0] += g[0];
+        acc[1] += g[1];
+        acc[2] += g[2];
+        acc[3] += x[1] * g[2] - x[2] * g[1];
+        acc[4] += x[2] * g[0] - x[0] * g[2];
+        acc[5] += x[0] * g[1] - x[1] * g[0];
+    }
+    for (int k = 0; k < 6; ++k) grad_pose[k] = acc[k];
+}
+
+int64_t orc_block_dda(const double a[3], const double e[3], double inv_cell, int64_t* cells, int64_t cap) {
+    std::vector<std::array<int64_t, 3>> out;
+    block_walk(a, e, inv_cell, out);
+    const int64_t n = (int64_t)out.size();
+    for (int64_t i = 0; i < n && i < cap; ++i)
+        for (int k = 0; k < 3; ++k) cells[3 * i + k] = out[i][k];
+    return n;
+}
+
+int64_t orc_voxel_dda(const double a[3], const double e[3], const int32_t block[3], double block_edge,
+                      double inv_voxel, int32_t m, int32_t* cells, int64_t cap) {
+    std::vector<std::array<int, 3>> out;
+    voxel_walk(a, e, Key{block[0], block[1], block[2]}, block_edge, inv_voxel, m, out);
+    const int64_t n = (int64_t)out.size();
+    for (int64_t i = 0; i < n && i < cap; ++i)
+        for (int k = 0; k < 3; ++k) cells[3 * i + k] = out[i][k];
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+/*
+ * CPU oracle of the MrHash fusion hot path (arXiv 2511.21459) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow FP64 implementation of what the per-frame fusion computes, written from the
+ * paper's text (Sec. 3, 3.1, 3.2, 3.2.1, 3.4; Eq. 1-3, 5, 6).  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code, header, table or
+ * helper with the HIP library; the two are written independently from the same definitions.
+ *
+ * Parity status of each entry point (what pins it against something other than itself) is
+ * listed beside it.  "parity unpinned" marks a function whose result the paper fixes only up to
+ * a reading we chose, with invariants as the only check.
+ */
+#ifndef MRH_ORACLE_H
+#define MRH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_config {
+    double voxel;       /* finest voxel edge nu_0 (m); block edge is 8 * voxel */
+    int32_t levels;     /* number of resolution levels L, 1..4 (level n holds (8>>n)^3 voxels) */
+    int32_t min_obs;    /* voxels with W >= min_obs enter the block mean variance */
+    double tau;         /* truncation distance (m) */
+    double var_thr;     /* merge when the block mean variance is below this (m^2) */
+    double max_depth;   /* RGB-D: valid depth is (0, max_depth] */
+    double min_range;   /* LiDAR: valid range is [min_range, max_range] */
+    double max_range;
+    int32_t carve;      /* LiDAR: 1 = segment [o, p + tau n], 0 = band [p - tau n, p + tau n] */
+    int32_t form;       /* RGB-D signed distance: 0 = range along the voxel ray, 1 = z difference */
+} orc_config;
+
+typedef struct orc_stats {
+    int64_t valid_points;
+    int64_t new_blocks;
+    int64_t observations;      /* voxel updates applied (one per voxel per observation) */
+    int64_t dropped_points;    /* valid points whose segment left the key range */
+    int64_t merges[4];         /* merges out of level n this frame */
+    int64_t near_threshold;    /* merge decisions with |mv - thr| / thr < 1e-3 this frame */
+} orc_stats;
+
+void* orc_create(const orc_config* cfg);
+void orc_destroy(void* map);
+
+/* RGB-D projective fusion of one z-depth frame (Eq. 2, 3, 5).  depth is row-major H x W. */
+int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t height,
+                        const double K[4], const double T_ws[16]);
+
+/* LiDAR ray fusion of one scan of n sensor-frame points (Eq. 1, 3, 5). */
+int orc_integrate_points(void* map, const float* xyz, int64_t n, const double T_ws[16]);
+
+void orc_last_stats(const void* map, orc_stats* out);
+int64_t orc_num_blocks(const void* map);
+int64_t orc_num_voxels(const void* map);
+
+/* Blocks in ascending (x, y, z) key order.  offsets has num_blocks + 1 entries; D/W/S2 hold the
+ * voxels of block i at [offsets[i], offsets[i+1]), x fastest.  Any output may be NULL. */
+void orc_extract(const void* map, int32_t* keys, uint8_t* levels, int64_t* offsets,
+                 double* D, uint32_t* W, double* S2);
+
+/* Merge decisions taken within 1e-3 relative of the threshold so far: per event the block key,
+ * the frame index and the relative margin.  Returns the total count; fills at most cap. */
+int64_t orc_near_threshold(const void* map, int32_t* keys, int64_t* frames, double* margins,
+                           int64_t cap);
+
+/* Trilinear SDF query (Sec. 3.4): T may be NULL (identity).  strict = 1 requires all 8 corners. */
+void orc_query(const void* map, const float* pts, int64_t n, const double* T, int32_t strict,
+               double* sdf, uint8_t* valid, double* grad_world);
+
+/* Adjoint of orc_query: grad_pts = dL/dp (n x 3), grad_pose = dL/dxi for a left perturbation
+ * xi = (rho, phi) of T (6 values). */
+void orc_query_backward(const void* map, const float* pts, int64_t n, const double* T,
+                        int32_t strict, const double* grad_sdf, double* grad_pts,
+                        double grad_pose[6]);
+
+/* The traversals, exposed for brute-force pins.  Return the number of cells written (<= cap). */
+int64_t orc_block_dda(const double a[3], const double e[3], double inv_cell, int64_t* cells,
+                      int64_t cap);
+int64_t orc_voxel_dda(const double a[3], const double e[3], const int32_t block[3], double block_edge,
+                      double inv_voxel, int32_t m, int32_t* cells, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
