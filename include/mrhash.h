@@ -1,0 +1,195 @@
+/*
+ * mrhash -- MI355X (gfx950) fusion of depth frames and LiDAR scans into a spatially hashed,
+ * variance-adaptive multi-resolution TSDF voxel-block map (MrHash, arXiv 2511.21459).
+ *
+ * C ABI.  Every function is extern "C", never throws, and returns an mrh_status (0 = success,
+ * negative = error) unless stated otherwise.  Arguments are plain host or device pointers and
+ * sizes; "device" pointers must be device memory of the GPU the map was created on (for example
+ * the data pointer of a torch tensor on that GPU).  The caller owns every buffer it passes in;
+ * the library owns the map's own device memory and releases it in mrh_map_destroy.  No call
+ * keeps a caller pointer after it returns.
+ *
+ * Streams.  A map is bound to one HIP stream at creation (a hipStream_t passed as void*; NULL
+ * is the default stream).  All work is enqueued on that stream, asynchronously, unless a call
+ * writes a host output (counts, host gradients, statistics) -- those calls synchronise the
+ * stream before returning.  Errors a kernel detects (hash table full, heap full, block limit)
+ * are latched in device memory and returned by the next synchronising call (mrh_sync,
+ * mrh_extract_blocks with a count output, mrh_query_sdf_backward).
+ */
+#ifndef MRHASH_H
+#define MRHASH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRH_ABI_VERSION 1
+
+typedef int32_t mrh_status;
+enum {
+    MRH_OK = 0,
+    MRH_ERR_INVALID_ARG = -1,      /* null pointer, bad size, bad config, non-finite pose */
+    MRH_ERR_OOM = -2,              /* device allocation failed */
+    MRH_ERR_TABLE_FULL = -3,       /* a hash insert found no free slot within the probe limit */
+    MRH_ERR_HEAP_FULL = -4,        /* a level's block heap had no free block */
+    MRH_ERR_BUFFER_TOO_SMALL = -5, /* an output buffer is smaller than the result */
+    MRH_ERR_HIP = -6,              /* a HIP runtime call failed; mrh_last_error has its text */
+    MRH_ERR_BLOCK_LIMIT = -7       /* more distinct blocks than cfg.max_blocks */
+};
+
+/* Signed-distance form of the projective (RGB-D) update, Eq. 2 (Sec. 3.1). */
+enum {
+    MRH_FORM_RANGE = 0, /* range measured along the voxel's viewing ray minus ||x|| */
+    MRH_FORM_ZDIFF = 1  /* depth minus the voxel's z (fronto-parallel distance) */
+};
+
+/* Storage precision of the voxel state (arithmetic is always FP32 in registers). */
+enum {
+    MRH_STORE_F32 = 0,  /* D: float metres, S2: float m^2           | W: uint32 */
+    MRH_STORE_F16 = 1,  /* D: half of D / tau, S2: half of S2/tau^2 | W: uint16 */
+    MRH_STORE_BF16 = 2  /* D: bfloat16 of D / tau, S2: half         | W: half  */
+};
+
+typedef struct mrh_config {
+    double voxel;          /* finest voxel edge nu_0 (m); every block is 8 nu_0 wide (Sec. 3.2) */
+    int32_t levels;        /* resolution levels L in [1, 4]; level n holds (8 >> n)^3 voxels */
+    int32_t min_obs;       /* voxels with W >= min_obs enter the block mean variance (>= 1) */
+    double tau;            /* truncation distance (m), > 0 (Sec. 3.1) */
+    double var_thr;        /* merge a block whose mean voxel variance is below this (m^2) */
+    double max_depth;      /* RGB-D: a depth d is valid iff finite and 0 < d <= max_depth */
+    double min_range;      /* LiDAR: a point is valid iff min_range <= |p_s| <= max_range */
+    double max_range;
+    int32_t carve;         /* LiDAR: 1 = traverse [o, p + tau n], 0 = only [p - tau n, p + tau n] */
+    int32_t form;          /* MRH_FORM_* */
+    int64_t hash_slots;    /* open-addressing table size, a power of two >= 2 * max_blocks */
+    int64_t max_blocks;    /* capacity of the block table (distinct block keys ever inserted) */
+    int64_t heap_blocks[4];/* capacity of each level's block heap; 0 = max_blocks */
+    int32_t storage;       /* MRH_STORE_* */
+    int32_t max_probe;     /* linear-probe limit per lookup; 0 = 4096 */
+} mrh_config;
+
+typedef struct mrh_stats {
+    int64_t frames;         /* frames integrated (totals) or 1 (last frame) */
+    int64_t valid_points;   /* valid pixels or points */
+    int64_t dropped_points; /* valid points whose traversal left the 21-bit key range */
+    int64_t new_blocks;     /* blocks inserted */
+    int64_t observations;   /* voxel updates applied (one per voxel per observation) */
+    int64_t merges[4];      /* merges out of level n */
+    int64_t failed_inserts; /* inserts lost to a full table / heap / block limit */
+    int64_t fresh_observations; /* of `observations`, those applied to blocks created this frame */
+    int64_t blocks;         /* distinct blocks in the map after the frame */
+    uint32_t error_flags;   /* bit 0 table full, bit 1 heap full, bit 2 block limit */
+    uint32_t reserved;
+} mrh_stats;
+
+typedef struct mrh_map mrh_map;
+
+int32_t mrh_abi_version(void);
+
+/* Home slot of block key (x, y, z) in a table of n_hash slots: Eq. 4 (Sec. 3.2),
+ * ((x p1) xor (y p2) xor (z p3)) mod n_hash with p1 = 73856093, p2 = 19349669, p3 = 83492791,
+ * evaluated in 32-bit unsigned wrap-around arithmetic.  Host function, no GPU needed. */
+uint32_t mrh_block_hash(int32_t x, int32_t y, int32_t z, uint64_t n_hash);
+
+/* Create an empty map (Sec. 3.2): allocates the hash table, the block table and one block heap
+ * per level on the current HIP device, and clears them on `stream`.  *out receives the handle.
+ * Errors: MRH_ERR_INVALID_ARG (cfg or out NULL, levels outside [1,4], voxel/tau <= 0,
+ * hash_slots not a power of two or < 2 max_blocks, min_obs < 1), MRH_ERR_OOM, MRH_ERR_HIP. */
+mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out);
+
+/* Release the map's device memory (synchronises its stream).  NULL is ignored. */
+void mrh_map_destroy(mrh_map* map);
+
+/* Empty the map in place (asynchronous): no blocks, all heaps free, counters and latched errors
+ * cleared.  Device memory is kept. */
+mrh_status mrh_map_reset(mrh_map* map);
+
+/* Fuse one RGB-D frame (Sec. 3.1 "Cameras", Eq. 2, Eq. 3, Eq. 5; Sec. 3.2.1).
+ *   depth_dev: device float32[height][width], z-depth in metres, row-major; pixel (u, v) =
+ *              (column, row) has its centre at integer (u, v).  Non-finite, <= 0 or > max_depth
+ *              values are skipped.
+ *   K:         host double[4] = fx, fy, cx, cy.
+ *   T_ws:      host double[16], row-major world-from-sensor rigid transform.
+ * Steps: allocate at the finest level every block crossed by [p - tau n, p + tau n] for each valid
+ * pixel, update every voxel of every allocated block that projects onto a valid pixel and lies
+ * no more than tau behind it, then merge every updated block whose mean voxel variance is below
+ * var_thr one level coarser.  Asynchronous.  Errors: MRH_ERR_INVALID_ARG (NULL pointers, sizes
+ * <= 0, non-finite K or T_ws); kernel-side capacity errors are latched (see top). */
+mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                               const double K[4], const double T_ws[16]);
+
+/* Fuse one LiDAR scan (Sec. 3.1 "3D Point Cloud", Eq. 1, Eq. 3, Eq. 5; Sec. 3.2.1).
+ *   xyz_dev: device float32[n][3] points in the sensor frame; non-finite points and points with
+ *            range outside [min_range, max_range] are skipped.  n may be 0.
+ *   T_ws:    host double[16], row-major world-from-sensor transform (origin o = its translation).
+ * Every voxel each ray [o, p + tau n] (or [p - tau n, p + tau n] without carving) crosses, at its
+ * block's level, receives clip((p - x) . n, -tau, tau).  Asynchronous. */
+mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, int64_t n, const double T_ws[16]);
+
+/* Wait for the map's stream, then report.  last / totals may be NULL.  Returns the first latched
+ * capacity error (MRH_ERR_TABLE_FULL, MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT) or MRH_OK, and
+ * clears the latch. */
+mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals);
+
+/* Trilinear SDF query (Sec. 3.4).  For each point p_i (device float32[n][3]) the world point is
+ * x = T_wq p (T_wq host double[16] or NULL for identity).  The point's block fixes the lattice
+ * of its level; the 8 surrounding lattice points take the TSDF of whichever voxel, at any level,
+ * contains them; missing corners (no block or W = 0) are dropped and the weights renormalised.
+ * strict = 1 instead requires all 8 corners.  Outputs (device): sdf float32[n] (0 where invalid),
+ * valid uint8[n], grad float32[n][3] = d sdf / d x in the world frame (may be NULL).
+ * Asynchronous.  n may be 0. */
+mrh_status mrh_query_sdf(mrh_map* map, const float* pts_dev, int64_t n, const double* T_wq,
+                         int32_t strict, float* sdf_dev, uint8_t* valid_dev, float* grad_dev);
+
+/* Adjoint of mrh_query_sdf for L = sum_i g_i sdf_i, with g = grad_sdf_dev (device float32[n]):
+ * grad_pts_dev (device float32[n][3]) = dL/dp_i, and grad_pose_host (host double[6]) = dL/dxi for
+ * a left perturbation exp(xi) T_wq, xi = (rho, phi): the sum over points of (g_x, x cross g_x),
+ * reduced deterministically in FP64.  Synchronises the stream. */
+mrh_status mrh_query_sdf_backward(mrh_map* map, const float* pts_dev, int64_t n, const double* T_wq,
+                                  int32_t strict, const float* grad_sdf_dev, float* grad_pts_dev,
+                                  double grad_pose_host[6]);
+
+/* Copy the map out (Sec. 3.2 hash entries: key b_j, level n_j, and the block's voxels).
+ * Blocks are written in block-table order; *n_blocks and *n_voxels (host) receive the counts.
+ * Device outputs, each may be NULL: keys int32[n][3], levels uint8[n], offsets int64[n + 1]
+ * (block i owns voxels [offsets[i], offsets[i+1])), D float32 (m), W uint32, S2 float32 (m^2)
+ * with voxels x fastest.  With all outputs NULL only the counts are returned.  Returns
+ * MRH_ERR_BUFFER_TOO_SMALL (counts still set) if block_cap < n_blocks or, when a voxel output is
+ * given, voxel_cap < n_voxels.  Synchronises the stream. */
+mrh_status mrh_extract_blocks(mrh_map* map, int32_t* keys_dev, uint8_t* levels_dev,
+                              int64_t* offsets_dev, float* D_dev, uint32_t* W_dev, float* S2_dev,
+                              int64_t block_cap, int64_t voxel_cap, int64_t* n_blocks,
+                              int64_t* n_voxels);
+
+/* Kernel ids of the launch profiler. */
+enum {
+    MRH_KERNEL_RESET = 0,
+    MRH_KERNEL_ALLOC_DEPTH = 1,     /* RGB-D allocation (back-projection, band walk, insert) */
+    MRH_KERNEL_INTEGRATE_DEPTH = 2, /* RGB-D projective update, variance, merge */
+    MRH_KERNEL_FINALIZE = 3,        /* end of frame: freed slots, statistics */
+    MRH_KERNEL_ALLOC_POINTS = 4,    /* LiDAR allocation */
+    MRH_KERNEL_RAYS = 5,            /* LiDAR ray traversal and accumulation */
+    MRH_KERNEL_APPLY_POINTS = 6,    /* LiDAR state update, variance, merge */
+    MRH_KERNEL_QUERY = 7,
+    MRH_KERNEL_QUERY_BACKWARD = 8,
+    MRH_KERNEL_REDUCE = 9,
+    MRH_KERNEL_COUNT = 10
+};
+
+/* Launch profiler (measurement support, not part of the method).  With on != 0 every kernel the
+ * map launches is bracketed by a pair of HIP events on the map's stream.  mrh_profile_collect
+ * synchronises the stream and writes, for kernel ids 0 .. n_kernels-1, the summed event time in
+ * milliseconds (ms, host double[n_kernels]) and the number of launches (launches, host
+ * int64[n_kernels]) since the last collect, then recycles the events. */
+mrh_status mrh_profile_enable(mrh_map* map, int32_t on);
+mrh_status mrh_profile_collect(mrh_map* map, double* ms, int64_t* launches, int32_t n_kernels);
+
+/* Text of the last error on this map (never NULL; "" when none). */
+const char* mrh_last_error(const mrh_map* map);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRHASH_H */

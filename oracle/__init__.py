@@ -53,6 +53,8 @@ def lib():
         L.orc_near_threshold.argtypes = [P, P, P, P, ctypes.c_int64]
         L.orc_query.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P, P, P]
         L.orc_query_backward.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P, P, P]
+        L.orc_eq4_hash.restype = ctypes.c_uint32
+        L.orc_eq4_hash.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
         L.orc_block_dda.restype = ctypes.c_int64
         L.orc_block_dda.argtypes = [P, P, ctypes.c_double, P, ctypes.c_int64]
         L.orc_voxel_dda.restype = ctypes.c_int64
@@ -174,6 +176,10 @@ class OracleMap:
         lib().orc_query_backward(self._h, _p(pts), n, None if Tp is None else _p(Tp), int(strict),
                                  _p(g), _p(gp), _p(gpose))
         return gp, gpose
+
+
+def eq4_hash(x: int, y: int, z: int, n_hash: int) -> int:
+    return int(lib().orc_eq4_hash(x, y, z, n_hash))
 
 
 def block_dda(a, e, inv_cell, cap=100000) -> np.ndarray:

@@ -638,6 +638,12 @@ void orc_query_backward(const void* map, const float* pts, int64_t n, const doub
     for (int k = 0; k < 6; ++k) grad_pose[k] = acc[k];
 }
 
+uint32_t orc_eq4_hash(int32_t x, int32_t y, int32_t z, uint64_t n_hash) {
+    const uint32_t p1 = 73856093u, p2 = 19349669u, p3 = 83492791u;
+    const uint32_t h = ((uint32_t)x * p1) ^ ((uint32_t)y * p2) ^ ((uint32_t)z * p3);
+    return (uint32_t)((uint64_t)h % n_hash);
+}
+
 int64_t orc_block_dda(const double a[3], const double e[3], double inv_cell, int64_t* cells, int64_t cap) {
     std::vector<std::array<int64_t, 3>> out;
     block_walk(a, e, inv_cell, out);

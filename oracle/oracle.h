@@ -74,6 +74,11 @@ void orc_query_backward(const void* map, const float* pts, int64_t n, const doub
                         int32_t strict, const double* grad_sdf, double* grad_pts,
                         double grad_pose[6]);
 
+/* Eq. 4: (x p1 xor y p2 xor z p3) mod n_hash, products and xor in 32-bit unsigned arithmetic.
+ * The oracle's own map does not need it (a std::map keyed by block coordinates holds the blocks);
+ * it is here to write the stored hash vectors the library's hash is checked against. */
+uint32_t orc_eq4_hash(int32_t x, int32_t y, int32_t z, uint64_t n_hash);
+
 /* The traversals, exposed for brute-force pins.  Return the number of cells written (<= cap). */
 int64_t orc_block_dda(const double a[3], const double e[3], double inv_cell, int64_t* cells,
                       int64_t cap);

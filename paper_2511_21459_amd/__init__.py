@@ -1,0 +1,221 @@
+"""MI355X-native fusion of depth frames and LiDAR scans into a spatially hashed, variance-adaptive
+multi-resolution TSDF voxel-block map (MrHash, arXiv 2511.21459).
+
+Thin Python binding over the C ABI of ``libmrhash.so`` (``include/mrhash.h``): every step of
+allocation, integration, merging, querying and extraction runs in the library's HIP kernels; this
+module only marshals torch tensors (device memory) and host arrays into the calls.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FORM, STORAGE, MrhConfig, MrhError, MrhStats
+
+__all__ = ["Map", "SdfQuery", "block_hash", "MrhError"]
+
+
+def _host_doubles(a, n):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t: torch.Tensor, dtype, shape_tail=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape (N, {', '.join(map(str, shape_tail))})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def block_hash(x: int, y: int, z: int, n_hash: int) -> int:
+    """Home slot of block (x, y, z) in a table of n_hash slots (Eq. 4)."""
+    return int(_lib.load().mrh_block_hash(x, y, z, n_hash))
+
+
+class Map:
+    """One fused map living on the current GPU, bound to torch's current stream at creation."""
+
+    def __init__(self, voxel: float, levels: int = 1, tau: float | None = None, var_thr: float = 0.0,
+                 min_obs: int = 2, max_depth: float = 1e9, min_range: float = 0.0,
+                 max_range: float = 1e9, carve: bool = False, form: str = "range",
+                 max_blocks: int = 1 << 18, hash_slots: int | None = None, heap_blocks=None,
+                 storage: str = "f32", max_probe: int = 0):
+        L = _lib.load()
+        cfg = MrhConfig()
+        cfg.voxel = float(voxel)
+        cfg.levels = int(levels)
+        cfg.min_obs = int(min_obs)
+        cfg.tau = float(tau if tau is not None else 3.0 * voxel)
+        cfg.var_thr = float(var_thr)
+        cfg.max_depth = float(max_depth)
+        cfg.min_range = float(min_range)
+        cfg.max_range = float(max_range)
+        cfg.carve = int(bool(carve))
+        cfg.form = FORM[form]
+        cfg.max_blocks = int(max_blocks)
+        hs = hash_slots if hash_slots is not None else 1 << max(1, (2 * int(max_blocks) - 1).bit_length())
+        cfg.hash_slots = int(hs)
+        hb = list(heap_blocks) if heap_blocks is not None else [0, 0, 0, 0]
+        for n in range(4):
+            cfg.heap_blocks[n] = int(hb[n]) if n < len(hb) else 0
+        cfg.storage = STORAGE[storage]
+        cfg.max_probe = int(max_probe)
+        self.cfg = cfg
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = L.mrh_map_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise MrhError(st, "mrh_map_create")
+        self._h = h
+
+    # -- lifetime -------------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mrh_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            raise MrhError(st, what, _lib.load().mrh_last_error(self._h).decode())
+
+    def reset(self):
+        self._check(_lib.load().mrh_map_reset(self._h), "mrh_map_reset")
+
+    # -- fusion ---------------------------------------------------------------------------------
+    def integrate_depth(self, depth: torch.Tensor, K, T_ws):
+        """Fuse one z-depth frame (float32 [H, W] metres on the GPU) seen with intrinsics
+        K = (fx, fy, cx, cy) from world-from-sensor pose T_ws (4 x 4)."""
+        if depth.dim() != 2:
+            raise ValueError("depth must be [H, W]")
+        p = _dev(depth, torch.float32, name="depth")
+        Ka, Kp = _host_doubles(K, 4)
+        Ta, Tp = _host_doubles(T_ws, 16)
+        self._check(_lib.load().mrh_integrate_depth(self._h, p, depth.shape[1], depth.shape[0], Kp, Tp),
+                    "mrh_integrate_depth")
+
+    def integrate_points(self, xyz: torch.Tensor, T_ws):
+        """Fuse one LiDAR scan: float32 [N, 3] sensor-frame points on the GPU."""
+        p = _dev(xyz, torch.float32, (3,), name="xyz")
+        Ta, Tp = _host_doubles(T_ws, 16)
+        self._check(_lib.load().mrh_integrate_points(self._h, p, xyz.shape[0], Tp), "mrh_integrate_points")
+
+    def sync(self):
+        """Wait for the map's stream; return (last-frame stats, totals); raise a latched error."""
+        last, tot = MrhStats(), MrhStats()
+        self._check(_lib.load().mrh_sync(self._h, ctypes.byref(last), ctypes.byref(tot)), "mrh_sync")
+        return last.as_dict(), tot.as_dict()
+
+    # -- launch profiler ------------------------------------------------------------------------
+    def profile(self, on: bool = True):
+        self._check(_lib.load().mrh_profile_enable(self._h, int(on)), "mrh_profile_enable")
+
+    def profile_collect(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last collect (synchronises)."""
+        n = len(_lib.KERNELS)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        self._check(_lib.load().mrh_profile_collect(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                                    cnt.ctypes.data_as(ctypes.c_void_p), n),
+                    "mrh_profile_collect")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(_lib.KERNELS) if cnt[i]}
+
+    # -- queries --------------------------------------------------------------------------------
+    def query(self, pts: torch.Tensor, T=None, strict: bool = False, with_grad: bool = False):
+        """Trilinear SDF at float32 [N, 3] points (optionally through pose T); returns
+        (sdf float32 [N], valid bool [N], grad float32 [N, 3] or None)."""
+        p = _dev(pts, torch.float32, (3,), name="pts")
+        n = pts.shape[0]
+        sdf = torch.empty(n, dtype=torch.float32, device=pts.device)
+        valid = torch.empty(n, dtype=torch.uint8, device=pts.device)
+        grad = torch.empty((n, 3), dtype=torch.float32, device=pts.device) if with_grad else None
+        Tp = None
+        if T is not None:
+            Ta, Tp = _host_doubles(T, 16)
+        self._check(_lib.load().mrh_query_sdf(self._h, p, n, Tp, int(strict), ctypes.c_void_p(sdf.data_ptr()),
+                                              ctypes.c_void_p(valid.data_ptr()),
+                                              ctypes.c_void_p(grad.data_ptr()) if grad is not None else None),
+                    "mrh_query_sdf")
+        return sdf, valid.bool(), grad
+
+    def query_backward(self, pts: torch.Tensor, grad_sdf: torch.Tensor, T=None, strict: bool = False):
+        """Adjoint of query: returns (dL/dp float32 [N, 3], dL/dxi float64 numpy [6])."""
+        p = _dev(pts, torch.float32, (3,), name="pts")
+        g = _dev(grad_sdf.contiguous(), torch.float32, name="grad_sdf")
+        n = pts.shape[0]
+        gp = torch.empty((n, 3), dtype=torch.float32, device=pts.device)
+        pose = np.zeros(6, dtype=np.float64)
+        Tp = None
+        if T is not None:
+            Ta, Tp = _host_doubles(T, 16)
+        self._check(_lib.load().mrh_query_sdf_backward(self._h, p, n, Tp, int(strict), g,
+                                                       ctypes.c_void_p(gp.data_ptr()),
+                                                       pose.ctypes.data_as(ctypes.c_void_p)),
+                    "mrh_query_sdf_backward")
+        return gp, pose
+
+    # -- extraction -----------------------------------------------------------------------------
+    def counts(self):
+        nb, nv = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.load().mrh_extract_blocks(self._h, None, None, None, None, None, None, 0, 0,
+                                                   ctypes.byref(nb), ctypes.byref(nv)), "mrh_extract_blocks")
+        return nb.value, nv.value
+
+    def extract(self, voxels: bool = True) -> dict:
+        """Blocks in table order: keys int32 [n, 3], levels uint8 [n] and, with voxels, offsets
+        int64 [n + 1] and D float32, W int32 (bit pattern of the uint32 weights), S2 float32."""
+        nb, nv = self.counts()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        keys = torch.empty((nb, 3), dtype=torch.int32, device=dev)
+        levels = torch.empty(nb, dtype=torch.uint8, device=dev)
+        out = {"keys": keys, "levels": levels}
+        args = [ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(levels.data_ptr())]
+        if voxels:
+            offs = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+            D = torch.empty(nv, dtype=torch.float32, device=dev)
+            W = torch.empty(nv, dtype=torch.int32, device=dev)
+            S2 = torch.empty(nv, dtype=torch.float32, device=dev)
+            args += [ctypes.c_void_p(t.data_ptr()) for t in (offs, D, W, S2)]
+            out.update(offsets=offs, D=D, W=W, S2=S2)
+        else:
+            args += [None, None, None, None]
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.load().mrh_extract_blocks(self._h, *args, nb, nv, ctypes.byref(a), ctypes.byref(b)),
+                    "mrh_extract_blocks")
+        return out
+
+
+class SdfQuery(torch.autograd.Function):
+    """sdf = SdfQuery.apply(map, pts, T, strict): differentiable in pts; the pose gradient of the
+    last backward is kept in ``map.last_pose_grad`` (dL/dxi for a left perturbation of T)."""
+
+    @staticmethod
+    def forward(ctx, fmap: Map, pts: torch.Tensor, T=None, strict: bool = False):
+        pts_c = pts.detach().contiguous()
+        sdf, valid, _ = fmap.query(pts_c, T=T, strict=strict)
+        ctx.fmap, ctx.T, ctx.strict = fmap, T, strict
+        ctx.save_for_backward(pts_c)
+        ctx.mark_non_differentiable(valid)
+        return sdf, valid
+
+    @staticmethod
+    def backward(ctx, grad_sdf, grad_valid):
+        (pts_c,) = ctx.saved_tensors
+        if grad_sdf is None:
+            return None, None, None, None
+        gp, pose = ctx.fmap.query_backward(pts_c, grad_sdf.float().contiguous(), T=ctx.T, strict=ctx.strict)
+        ctx.fmap.last_pose_grad = pose
+        return None, gp, None, None

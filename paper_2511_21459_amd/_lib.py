@@ -1,0 +1,114 @@
+"""ctypes declarations of the C ABI in ``include/mrhash.h`` (argument marshalling only).
+
+The shared library is loaded from this package directory.  There is no fallback: when
+``libmrhash.so`` is missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrhash.so")
+
+MRH_OK = 0
+ERRORS = {
+    -1: "MRH_ERR_INVALID_ARG",
+    -2: "MRH_ERR_OOM",
+    -3: "MRH_ERR_TABLE_FULL",
+    -4: "MRH_ERR_HEAP_FULL",
+    -5: "MRH_ERR_BUFFER_TOO_SMALL",
+    -6: "MRH_ERR_HIP",
+    -7: "MRH_ERR_BLOCK_LIMIT",
+}
+FORM = {"range": 0, "zdiff": 1}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+EXPORTS = [
+    "mrh_abi_version", "mrh_block_hash", "mrh_map_create", "mrh_map_destroy", "mrh_map_reset",
+    "mrh_integrate_depth", "mrh_integrate_points", "mrh_sync", "mrh_query_sdf",
+    "mrh_query_sdf_backward", "mrh_extract_blocks", "mrh_last_error", "mrh_profile_enable",
+    "mrh_profile_collect",
+]
+KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
+           "query", "query_backward", "reduce"]
+
+
+class MrhConfig(ctypes.Structure):
+    _fields_ = [
+        ("voxel", ctypes.c_double), ("levels", ctypes.c_int32), ("min_obs", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("var_thr", ctypes.c_double), ("max_depth", ctypes.c_double),
+        ("min_range", ctypes.c_double), ("max_range", ctypes.c_double), ("carve", ctypes.c_int32),
+        ("form", ctypes.c_int32), ("hash_slots", ctypes.c_int64), ("max_blocks", ctypes.c_int64),
+        ("heap_blocks", ctypes.c_int64 * 4), ("storage", ctypes.c_int32), ("max_probe", ctypes.c_int32),
+    ]
+
+
+class MrhStats(ctypes.Structure):
+    _fields_ = [
+        ("frames", ctypes.c_int64), ("valid_points", ctypes.c_int64), ("dropped_points", ctypes.c_int64),
+        ("new_blocks", ctypes.c_int64), ("observations", ctypes.c_int64), ("merges", ctypes.c_int64 * 4),
+        ("failed_inserts", ctypes.c_int64), ("fresh_observations", ctypes.c_int64),
+        ("blocks", ctypes.c_int64), ("error_flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"frames": self.frames, "valid_points": self.valid_points,
+                "dropped_points": self.dropped_points, "new_blocks": self.new_blocks,
+                "observations": self.observations, "merges": list(self.merges),
+                "failed_inserts": self.failed_inserts, "fresh_observations": self.fresh_observations,
+                "blocks": self.blocks,
+                "error_flags": self.error_flags}
+
+
+class MrhError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {ERRORS.get(code, code)}" + (f" ({detail})" if detail else ""))
+
+
+_lib = None
+
+
+def load():
+    """Load libmrhash.so (built by ``paper_2511_21459_amd.build``); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first "
+                          "(the HIP library is required, there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.mrh_abi_version.restype = i32
+    L.mrh_abi_version.argtypes = []
+    L.mrh_block_hash.restype = ctypes.c_uint32
+    L.mrh_block_hash.argtypes = [i32, i32, i32, ctypes.c_uint64]
+    L.mrh_map_create.restype = i32
+    L.mrh_map_create.argtypes = [ctypes.POINTER(MrhConfig), P, ctypes.POINTER(P)]
+    L.mrh_map_destroy.restype = None
+    L.mrh_map_destroy.argtypes = [P]
+    L.mrh_map_reset.restype = i32
+    L.mrh_map_reset.argtypes = [P]
+    L.mrh_integrate_depth.restype = i32
+    L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_integrate_points.restype = i32
+    L.mrh_integrate_points.argtypes = [P, P, i64, P]
+    L.mrh_sync.restype = i32
+    L.mrh_sync.argtypes = [P, ctypes.POINTER(MrhStats), ctypes.POINTER(MrhStats)]
+    L.mrh_query_sdf.restype = i32
+    L.mrh_query_sdf.argtypes = [P, P, i64, P, i32, P, P, P]
+    L.mrh_query_sdf_backward.restype = i32
+    L.mrh_query_sdf_backward.argtypes = [P, P, i64, P, i32, P, P, P]
+    L.mrh_extract_blocks.restype = i32
+    L.mrh_extract_blocks.argtypes = [P, P, P, P, P, P, P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.mrh_profile_enable.restype = i32
+    L.mrh_profile_enable.argtypes = [P, i32]
+    L.mrh_profile_collect.restype = i32
+    L.mrh_profile_collect.argtypes = [P, P, P, i32]
+    L.mrh_last_error.restype = ctypes.c_char_p
+    L.mrh_last_error.argtypes = [P]
+    _ = dbl
+    _lib = L
+    return L

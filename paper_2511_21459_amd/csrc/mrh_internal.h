@@ -1,0 +1,331 @@
+// Internal layout and device helpers of the mrhash library (gfx950).
+//
+// Map layout in HBM (all arrays allocated once at map creation):
+//   hash table   hkeys[u64 n_hash] packed block keys (EMPTY = all ones), hvals[u32 n_hash] block id
+//   block table  bkey[u64 max_blocks], binfo[u32] = heap slot | level << 27 | NEW | NOBLOCK,
+//                bvsum[f64] = sum over voxels with W >= min_obs of S2 / W, bvcnt[u32] = their count
+//   heaps        per level n: D, W, S2 planes of heap_blocks[n] blocks x (8 >> n)^3 voxels, voxels
+//                of a block in Morton (Z) order so the 2x2x2 children of a coarse voxel are
+//                contiguous; a free stack of slot indices and a pending-free list per level
+//   counters     DevCounters (block count, stack tops, stats, latched error flags)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "mrhash.h"
+
+namespace mrh {
+
+constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr uint32_t kInvalidId = 0xFFFFFFFFu;
+constexpr int64_t kKeyLimit = (int64_t(1) << 20) - 2;  // |block coordinate| bound for segment ends
+
+constexpr uint32_t kSlotMask = (1u << 27) - 1;
+constexpr int kLevelShift = 27;
+constexpr uint32_t kNewBit = 1u << 29;
+constexpr uint32_t kNoBlockBit = 1u << 31;
+
+constexpr uint32_t kErrTableFull = 1u, kErrHeapFull = 2u, kErrBlockLimit = 4u;
+
+// per-frame statistics slots (u64)
+enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, S_MERGE3, S_FAILED, S_OBS_FRESH, S_COUNT };
+
+struct DevCounters {
+    uint32_t n_blocks;
+    uint32_t error_flags;
+    int32_t top[4];
+    uint32_t pending[4];
+    uint32_t pad[6];
+    unsigned long long frame[S_COUNT];
+    unsigned long long last[S_COUNT];
+    unsigned long long total[S_COUNT];
+    unsigned long long frames;
+};
+
+// Everything a kernel needs to find the map; passed by value as a kernel argument.
+struct DevMap {
+    unsigned long long* hkeys;
+    uint32_t* hvals;
+    uint32_t hmask;
+    int32_t max_probe;
+    unsigned long long* bkey;
+    uint32_t* binfo;
+    double* bvsum;
+    uint32_t* bvcnt;
+    uint32_t max_blocks;
+    int32_t levels;
+    DevCounters* ctr;
+    uint32_t* stack[4];
+    uint32_t* pend[4];
+    int32_t heap_cap[4];
+    float* D[4];
+    uint32_t* W[4];
+    float* S2[4];
+    // LiDAR per-frame accumulators, parallel to the heaps (zero between frames):
+    // saturated (+tau) observation counts, band observation counts, and fixed-point sums of
+    // (d - D) and (d - D)^2 relative to the voxel's mean at the start of the frame
+    uint32_t* acc_sat[4];
+    uint32_t* acc_band[4];
+    unsigned long long* acc_s1[4];
+    unsigned long long* acc_s2[4];
+    uint32_t* btouch;  // per block: touched by a ray this frame
+    double B, invB;
+    double nu[4], inv_nu[4];
+    double tau, var_thr;
+    double max_depth, r2lo, r2hi;
+    int32_t min_obs, form, carve, storage;
+};
+
+// world <- sensor rigid transform, FP64
+struct Pose {
+    double R[3][3];
+    double t[3];
+};
+
+// ---------------------------------------------------------------------------------------------
+// keys and the spatial hash (Eq. 4)
+// ---------------------------------------------------------------------------------------------
+
+__host__ __device__ inline unsigned long long pack_key(int64_t x, int64_t y, int64_t z) {
+    const unsigned long long b = 1ull << 20;
+    return ((unsigned long long)(x + (int64_t)b) & 0x1FFFFFull) |
+           (((unsigned long long)(y + (int64_t)b) & 0x1FFFFFull) << 21) |
+           (((unsigned long long)(z + (int64_t)b) & 0x1FFFFFull) << 42);
+}
+
+__host__ __device__ inline void unpack_key(unsigned long long k, int32_t& x, int32_t& y, int32_t& z) {
+    x = (int32_t)(k & 0x1FFFFFull) - (1 << 20);
+    y = (int32_t)((k >> 21) & 0x1FFFFFull) - (1 << 20);
+    z = (int32_t)((k >> 42) & 0x1FFFFFull) - (1 << 20);
+}
+
+// Eq. 4: (x p1 xor y p2 xor z p3) in 32-bit unsigned arithmetic; the table size is a power of two
+// so "mod n_hash" is a mask of the low bits.
+__host__ __device__ inline uint32_t spatial_hash(int32_t x, int32_t y, int32_t z) {
+    return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u);
+}
+
+__device__ inline uint32_t home_slot(unsigned long long key, uint32_t mask) {
+    int32_t x, y, z;
+    unpack_key(key, x, y, z);
+    return spatial_hash(x, y, z) & mask;
+}
+
+// Read-only probe.  Returns the slot holding `key`, or kInvalidId; *stop gets the first EMPTY
+// slot met (where an insert would start) or kInvalidId when the probe limit was reached.
+__device__ inline uint32_t probe_find(const DevMap& m, unsigned long long key, uint32_t* stop) {
+    uint32_t h = home_slot(key, m.hmask);
+    for (int p = 0; p < m.max_probe; ++p) {
+        const unsigned long long k = __hip_atomic_load(&m.hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) return h;
+        if (k == kEmptyKey) {
+            if (stop) *stop = h;
+            return kInvalidId;
+        }
+        h = (h + 1) & m.hmask;
+    }
+    if (stop) *stop = kInvalidId;
+    return kInvalidId;
+}
+
+// Block id of `key`, or kInvalidId when absent (or inserted without a block id).
+__device__ inline uint32_t find_block(const DevMap& m, unsigned long long key) {
+    const uint32_t h = probe_find(m, key, nullptr);
+    return h == kInvalidId ? kInvalidId : m.hvals[h];
+}
+
+enum InsertResult { INS_FOUND = 0, INS_NEW = 1, INS_FULL = 2 };
+
+// Lock-free linear-probing insert from slot `start` (the first EMPTY slot a read-only probe met).
+// Keys are only ever written by this CAS, so the returned old value decides every race.
+__device__ inline int probe_insert(const DevMap& m, unsigned long long key, uint32_t start, uint32_t* slot) {
+    uint32_t h = start;
+    for (int p = 0; p < m.max_probe; ++p) {
+        const unsigned long long k = __hip_atomic_load(&m.hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) return INS_FOUND;
+        if (k == kEmptyKey) {
+            const unsigned long long old = atomicCAS(&m.hkeys[h], kEmptyKey, key);
+            if (old == kEmptyKey) {
+                *slot = h;
+                return INS_NEW;
+            }
+            if (old == key) return INS_FOUND;
+        }
+        h = (h + 1) & m.hmask;
+    }
+    return INS_FULL;
+}
+
+// ---------------------------------------------------------------------------------------------
+// wave helpers (wave64)
+// ---------------------------------------------------------------------------------------------
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline int rank_in_mask(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+__device__ inline unsigned long long shfl_u64(unsigned long long v, int src) {
+    const uint32_t lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline int wave_sum(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Morton (Z-order) position of voxel (i, j, k) inside a block of side 8 >> level, x lowest bit.
+__host__ __device__ inline int morton3(int i, int j, int k) {
+    int p = 0;
+    for (int b = 0; b < 3; ++b) p |= (((i >> b) & 1) << (3 * b)) | (((j >> b) & 1) << (3 * b + 1)) | (((k >> b) & 1) << (3 * b + 2));
+    return p;
+}
+
+__host__ __device__ inline void demorton3(int p, int& i, int& j, int& k) {
+    i = j = k = 0;
+    for (int b = 0; b < 3; ++b) {
+        i |= ((p >> (3 * b)) & 1) << b;
+        j |= ((p >> (3 * b + 1)) & 1) << b;
+        k |= ((p >> (3 * b + 2)) & 1) << b;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// canonical FP64 geometry shared by the kernels of this library (the library is built with
+// -ffp-contract=off: every expression is evaluated exactly as written)
+// ---------------------------------------------------------------------------------------------
+
+__device__ inline void pose_apply(const Pose& P, const double p[3], double out[3]) {
+    for (int r = 0; r < 3; ++r) out[r] = ((P.R[r][0] * p[0] + P.R[r][1] * p[1]) + P.R[r][2] * p[2]) + P.t[r];
+}
+
+__device__ inline void unit_direction(const double p[3], const double o[3], double n[3]) {
+    const double v0 = p[0] - o[0], v1 = p[1] - o[1], v2 = p[2] - o[2];
+    const double inv = 1.0 / __builtin_sqrt((v0 * v0 + v1 * v1) + v2 * v2);
+    n[0] = v0 * inv;
+    n[1] = v1 * inv;
+    n[2] = v2 * inv;
+}
+
+__device__ inline bool segment_in_range(const double a[3], const double e[3], double invB) {
+    for (int k = 0; k < 3; ++k) {
+        const double fa = __builtin_floor(a[k] * invB), fe = __builtin_floor(e[k] * invB);
+        if (!(__builtin_fabs(fa) <= (double)kKeyLimit && __builtin_fabs(fe) <= (double)kKeyLimit)) return false;
+    }
+    return true;
+}
+
+// Amanatides-Woo walk over unit cells of a lattice scaled by inv_cell: half-open cells, start in
+// the cell of a, step across the nearest boundary (lowest axis on ties), stop past e.  Boundary
+// parameters are recomputed from the cell index at every step.
+struct Walk {
+    double A[3], invD[3], tmax[3];
+    int64_t c[3];
+    int st[3];
+    int64_t guard;
+
+    __device__ inline void init(const double a[3], const double e[3], double inv_cell) {
+        guard = 3;
+        for (int k = 0; k < 3; ++k) {
+            A[k] = a[k] * inv_cell;
+            const double E = e[k] * inv_cell;
+            c[k] = (int64_t)__builtin_floor(A[k]);
+            const double dv = E - A[k];
+            const int64_t fe = (int64_t)__builtin_floor(E);
+            guard += fe > c[k] ? fe - c[k] : c[k] - fe;
+            if (dv > 0.0) {
+                st[k] = 1;
+                invD[k] = 1.0 / dv;
+                tmax[k] = ((double)(c[k] + 1) - A[k]) * invD[k];
+            } else if (dv < 0.0) {
+                st[k] = -1;
+                invD[k] = 1.0 / dv;
+                tmax[k] = ((double)c[k] - A[k]) * invD[k];
+            } else {
+                st[k] = 0;
+                invD[k] = 0.0;
+                tmax[k] = __builtin_inf();
+            }
+        }
+    }
+    // advance to the next cell; false once the walk is over
+    __device__ inline bool next() {
+        if (guard <= 0) return false;
+        --guard;
+        int k = 0;
+        if (tmax[1] < tmax[k]) k = 1;
+        if (tmax[2] < tmax[k]) k = 2;
+        if (!(tmax[k] <= 1.0)) return false;
+        c[k] += st[k];
+        tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - A[k]) * invD[k];
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// host-side helpers shared by the entry points
+// ---------------------------------------------------------------------------------------------
+
+inline int side_of(int level) { return 8 >> level; }
+
+// kernel ids reported by mrh_profile_collect (same order as MRH_KERNEL_* in the public header)
+enum KernelId { K_RESET = MRH_KERNEL_RESET, K_ALLOC_DEPTH = MRH_KERNEL_ALLOC_DEPTH, K_INTEGRATE_DEPTH = MRH_KERNEL_INTEGRATE_DEPTH,
+                K_FINALIZE = MRH_KERNEL_FINALIZE, K_ALLOC_POINTS = MRH_KERNEL_ALLOC_POINTS, K_RAYS = MRH_KERNEL_RAYS,
+                K_APPLY_POINTS = MRH_KERNEL_APPLY_POINTS, K_QUERY = MRH_KERNEL_QUERY, K_QUERY_BACKWARD = MRH_KERNEL_QUERY_BACKWARD,
+                K_REDUCE = MRH_KERNEL_REDUCE };
+
+// one profiled launch: kernel id and its bracketing events on the map's stream
+struct ProfRec {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace mrh
+
+struct mrh_map {
+    mrh_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    mrh::DevMap dm{};
+    mrh::DevCounters* ctr = nullptr;
+    double* partials = nullptr;  // query-backward per-workgroup FP64 partial sums
+    double* pose_out = nullptr;  // 6 doubles, final reduction
+    int32_t partials_cap = 0;
+    bool lidar_ready = false;    // accumulators allocated
+    bool profiling = false;      // bracket every launch with events (mrh_profile_enable)
+    std::vector<mrh::ProfRec> prof;
+    std::vector<hipEvent_t> event_pool;
+    char err[512] = {0};
+};
+
+namespace mrh {
+mrh_status set_error(mrh_map* m, mrh_status code, const char* fmt, ...);
+mrh_status check_hip(mrh_map* m, hipError_t e, const char* what);
+bool pose_from(const double* T, Pose& P);
+
+// Launch through `fn` (a callable that enqueues one kernel on m->stream), bracketed by events
+// when profiling is on.
+hipEvent_t take_event(mrh_map* m);
+template <typename F>
+inline void launch(mrh_map* m, int kernel, F&& fn) {
+    if (!m->profiling) {
+        fn();
+        return;
+    }
+    hipEvent_t a = take_event(m), b = take_event(m);
+    (void)hipEventRecord(a, m->stream);
+    fn();
+    (void)hipEventRecord(b, m->stream);
+    m->prof.push_back({kernel, a, b});
+}
+}  // namespace mrh

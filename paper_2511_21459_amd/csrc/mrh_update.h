@@ -1,0 +1,251 @@
+// Per-block voxel-state helpers shared by the RGB-D and LiDAR update kernels: FP32 state I/O,
+// the running mean / Welford update (Eq. 3, Eq. 5), the block mean-variance bookkeeping (Eq. 6
+// averaged over a block) and the merging criterion of Sec. 3.2.1 with 2x2x2 pooling.
+//
+// Work split: one wave per block.  A level-0 block (8^3 voxels, Morton order) gives lane l the
+// 8 contiguous voxels 8l .. 8l+7, which are the children of coarse voxel l; a level n >= 1 block
+// (at most 64 voxels) gives lane l the voxel at Morton position l.
+#pragma once
+
+#include "mrh_internal.h"
+
+namespace mrh {
+
+// Eq. 3 with w_k = 1 and Eq. 5 (Welford) in FP32.
+__device__ inline void welford(float obs, float& D, uint32_t& W, float& S2) {
+    const uint32_t Wn = W + 1;
+    const float Dold = D;
+    const float Dnew = Dold + (obs - Dold) / (float)Wn;
+    S2 = S2 + (obs - Dold) * (obs - Dnew);
+    D = Dnew;
+    W = Wn;
+}
+
+// A voxel's term of the block mean variance: sigma^2 = S2 / W (Eq. 6) for voxels with W >= min_obs.
+__device__ inline double var_term(const DevMap& m, uint32_t W, float S2) {
+    return W >= (uint32_t)m.min_obs ? (double)S2 / (double)W : 0.0;
+}
+
+__device__ inline int var_count(const DevMap& m, uint32_t W) { return W >= (uint32_t)m.min_obs ? 1 : 0; }
+
+// Pop one slot from a level's free stack (single lane).  Returns -1 when the heap is exhausted.
+__device__ inline int64_t pop_slot(const DevMap& m, int level) {
+    const int32_t top = atomicSub(&m.ctr->top[level], 1);
+    if (top <= 0) {
+        atomicAdd(&m.ctr->top[level], 1);
+        atomicOr(&m.ctr->error_flags, kErrHeapFull);
+        return -1;
+    }
+    return (int64_t)m.stack[level][top - 1];
+}
+
+// Slots freed by a merge wait in a pending list until the frame's end (a stack that is popped
+// in the same launch is never pushed).
+__device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
+    const uint32_t p = atomicAdd(&m.ctr->pending[level], 1u);
+    m.pend[level][p] = slot;
+}
+
+__device__ inline void load_group(const DevMap& m, size_t base, float D[8], uint32_t W[8], float S2[8]) {
+    const float4* dp = reinterpret_cast<const float4*>(m.D[0] + base);
+    const uint4* wp = reinterpret_cast<const uint4*>(m.W[0] + base);
+    const float4* sp = reinterpret_cast<const float4*>(m.S2[0] + base);
+    const float4 d0 = dp[0], d1 = dp[1], s0 = sp[0], s1 = sp[1];
+    const uint4 w0 = wp[0], w1 = wp[1];
+    D[0] = d0.x, D[1] = d0.y, D[2] = d0.z, D[3] = d0.w, D[4] = d1.x, D[5] = d1.y, D[6] = d1.z, D[7] = d1.w;
+    S2[0] = s0.x, S2[1] = s0.y, S2[2] = s0.z, S2[3] = s0.w, S2[4] = s1.x, S2[5] = s1.y, S2[6] = s1.z, S2[7] = s1.w;
+    W[0] = w0.x, W[1] = w0.y, W[2] = w0.z, W[3] = w0.w, W[4] = w1.x, W[5] = w1.y, W[6] = w1.z, W[7] = w1.w;
+}
+
+__device__ inline void store_group(const DevMap& m, size_t base, const float D[8], const uint32_t W[8],
+                                   const float S2[8]) {
+    float4* dp = reinterpret_cast<float4*>(m.D[0] + base);
+    uint4* wp = reinterpret_cast<uint4*>(m.W[0] + base);
+    float4* sp = reinterpret_cast<float4*>(m.S2[0] + base);
+    dp[0] = make_float4(D[0], D[1], D[2], D[3]);
+    dp[1] = make_float4(D[4], D[5], D[6], D[7]);
+    wp[0] = make_uint4(W[0], W[1], W[2], W[3]);
+    wp[1] = make_uint4(W[4], W[5], W[6], W[7]);
+    sp[0] = make_float4(S2[0], S2[1], S2[2], S2[3]);
+    sp[1] = make_float4(S2[4], S2[5], S2[6], S2[7]);
+}
+
+// End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
+// sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
+// written back, have whether D/W/S2 hold the lane's current group.
+__device__ inline void finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
+                                   bool have, bool dirty, int nupd, double dsum, int dcnt) {
+    const int lane = lane_id();
+    const uint32_t slot = info & kSlotMask;
+    const size_t base = (size_t)slot * 512 + (size_t)lane * 8;
+    dsum = wave_sum(dsum);
+    dcnt = wave_sum(dcnt);
+    const double vsum = m.bvsum[id] + dsum;
+    const uint32_t vcnt = m.bvcnt[id] + (uint32_t)dcnt;
+    bool merge = nupd > 0 && m.levels > 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
+    int64_t cslot = -1;
+    if (merge) {
+        if (lane == 0) cslot = pop_slot(m, 1);
+        cslot = (int64_t)__shfl((long long)cslot, 0);
+        merge = cslot >= 0;
+    }
+    if (!merge) {
+        if (dirty) store_group(m, base, D, W, S2);
+        if (lane == 0) {
+            m.bvsum[id] = vsum;
+            m.bvcnt[id] = vcnt;
+            if (info & kNewBit) m.binfo[id] = info & ~kNewBit;
+        }
+        return;
+    }
+    if (!have) load_group(m, base, D, W, S2);
+    // pool the 8 children: total weight, weighted mean TSDF, summed S2
+    uint32_t Wc = 0;
+    float sd = 0.f, s2 = 0.f;
+    for (int q = 0; q < 8; ++q) {
+        if (W[q] == 0) continue;
+        Wc += W[q];
+        sd += (float)W[q] * D[q];
+        s2 += S2[q];
+    }
+    const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+    const float Sc = Wc > 0 ? s2 : 0.f;
+    const size_t cb = (size_t)cslot * 64 + lane;
+    m.D[1][cb] = Dc;
+    m.W[1][cb] = Wc;
+    m.S2[1][cb] = Sc;
+    const double csum = wave_sum(var_term(m, Wc, Sc));
+    const int ccnt = wave_sum(var_count(m, Wc));
+    if (lane == 0) {
+        m.bvsum[id] = csum;
+        m.bvcnt[id] = (uint32_t)ccnt;
+        m.binfo[id] = (uint32_t)cslot | (1u << kLevelShift);
+        push_pending(m, 0, slot);
+        atomicAdd(&m.ctr->frame[S_MERGE0], 1ull);
+    }
+}
+
+// End of a level n >= 1 block's update (lane = Morton position; lanes >= the block's voxel count
+// hold W = 0).  The 8 children of a coarse voxel are 8 consecutive lanes.
+__device__ inline void finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
+                                     float S2, bool dirty, int nupd, double dsum, int dcnt) {
+    const int lane = lane_id();
+    const int side = 8 >> level, nv = side * side * side;
+    const uint32_t slot = info & kSlotMask;
+    const size_t at = (size_t)slot * nv + lane;
+    dsum = wave_sum(dsum);
+    dcnt = wave_sum(dcnt);
+    const double vsum = m.bvsum[id] + dsum;
+    const uint32_t vcnt = m.bvcnt[id] + (uint32_t)dcnt;
+    bool merge = nupd > 0 && level < m.levels - 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
+    int64_t cslot = -1;
+    if (merge) {
+        if (lane == 0) cslot = pop_slot(m, level + 1);
+        cslot = (int64_t)__shfl((long long)cslot, 0);
+        merge = cslot >= 0;
+    }
+    if (!merge) {
+        if (dirty && lane < nv) {
+            m.D[level][at] = D;
+            m.W[level][at] = W;
+            m.S2[level][at] = S2;
+        }
+        if (lane == 0) {
+            m.bvsum[id] = vsum;
+            m.bvcnt[id] = vcnt;
+        }
+        return;
+    }
+    uint32_t Wc = W;
+    float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
+    for (int o = 1; o < 8; o <<= 1) {
+        Wc += (uint32_t)__shfl_xor((int)Wc, o);
+        sd += __shfl_xor(sd, o);
+        s2 += __shfl_xor(s2, o);
+    }
+    const bool writer = lane < nv && (lane & 7) == 0;
+    const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+    const float Sc = Wc > 0 ? s2 : 0.f;
+    if (writer) {
+        const size_t cbase = (size_t)cslot * (size_t)(nv / 8) + (size_t)(lane >> 3);
+        m.D[level + 1][cbase] = Dc;
+        m.W[level + 1][cbase] = Wc;
+        m.S2[level + 1][cbase] = Sc;
+    }
+    const double csum = wave_sum(writer ? var_term(m, Wc, Sc) : 0.0);
+    const int ccnt = wave_sum(writer ? var_count(m, Wc) : 0);
+    if (lane == 0) {
+        m.bvsum[id] = csum;
+        m.bvcnt[id] = (uint32_t)ccnt;
+        m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
+        push_pending(m, level, slot);
+        atomicAdd(&m.ctr->frame[S_MERGE0 + level], 1ull);
+    }
+}
+
+// Wave-cooperative insert of one key per lane (has_key).  Keys found by a read-only probe need
+// nothing; the missing ones are deduplicated across the wave (one leader per distinct key does
+// the CAS insert), and the new entries get block ids and level-0 heap slots from one atomic each
+// per wave, ranked by a ballot prefix count.
+__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key) {
+    const int lane = lane_id();
+    uint32_t stop = kInvalidId;
+    bool need = false;
+    if (has_key) need = probe_find(m, key, &stop) == kInvalidId;
+    bool is_new = false;
+    uint32_t slot = 0;
+    unsigned long long pending = __ballot(need);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const unsigned long long lkey = shfl_u64(key, leader);
+        const bool same = need && key == lkey;
+        pending &= ~__ballot(same);
+        if (lane == leader) {
+            const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, &slot);
+            if (r == INS_NEW) {
+                is_new = true;
+            } else if (r == INS_FULL) {
+                atomicOr(&m.ctr->error_flags, kErrTableFull);
+                atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
+            }
+        }
+    }
+    const unsigned long long newmask = __ballot(is_new);
+    if (!newmask) return;
+    const int cnt = __popcll(newmask);
+    const int first = __ffsll((long long)newmask) - 1;
+    uint32_t base = 0;
+    int32_t top = 0;
+    if (lane == first) {
+        base = atomicAdd(&m.ctr->n_blocks, (uint32_t)cnt);
+        top = atomicSub(&m.ctr->top[0], cnt);
+        if (top < cnt) atomicAdd(&m.ctr->top[0], cnt - (top > 0 ? top : 0));  // undo the over-draw
+        atomicAdd(&m.ctr->frame[S_NEW], (unsigned long long)cnt);
+    }
+    base = (uint32_t)__shfl((int)base, first);
+    top = __shfl(top, first);
+    if (!is_new) return;
+    const int rank = rank_in_mask(newmask);
+    const uint32_t id = base + (uint32_t)rank;
+    if (id >= m.max_blocks) {
+        m.hvals[slot] = kInvalidId;
+        atomicOr(&m.ctr->error_flags, kErrBlockLimit);
+        atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
+        return;
+    }
+    uint32_t info;
+    if (rank < top) {
+        info = m.stack[0][top - 1 - rank] | kNewBit;
+    } else {
+        info = kNoBlockBit;
+        atomicOr(&m.ctr->error_flags, kErrHeapFull);
+        atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
+    }
+    m.bkey[id] = key;
+    m.binfo[id] = info;
+    m.bvsum[id] = 0.0;
+    m.bvcnt[id] = 0;
+    m.hvals[slot] = id;
+}
+
+}  // namespace mrh

@@ -1,0 +1,335 @@
+// LiDAR fusion (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3 and Eq. 5; Sec. 3.2.1 merging criterion).
+//
+// One scan is four launches on the map's stream:
+//   k_alloc_points  one thread per point: validity, segment [o, p + tau n] (carving) or the band
+//                   [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated insert
+//   k_rays          one thread per point: the same block walk; inside each block a walk over the
+//                   block's own voxel lattice; each crossed voxel gets clip((p - x) . n, -tau, tau).
+//                   Saturated observations (+tau) only bump an integer count; the others add to
+//                   fixed-point sums of (d - D) and (d - D)^2, D being the voxel's mean at the start
+//                   of the scan, so the accumulation is exact and order-independent
+//   k_apply_points  one wave per touched block: merges each voxel's scan statistics into its state
+//                   (W' = W + n, D' = D + s1 / W', S2' = S2 + s2 - s1^2 / W', the batch form of
+//                   Eq. 3 and Eq. 5), then the block variance bookkeeping and the merging criterion
+//   k_finalize      freed slots back to their stacks, statistics
+#include <cmath>
+
+#include "mrh_update.h"
+
+namespace mrh {
+
+void launch_finalize(mrh_map* m);
+
+constexpr double kS1Scale = 16777216.0;                 // 2^24 per metre
+constexpr double kS2Scale = 281474976710656.0;          // 2^48 per square metre
+
+struct ScanParams {
+    Pose P;
+};
+
+__device__ inline bool point_segment(const DevMap& m, const ScanParams& sp, const float* __restrict__ xyz, int64_t i,
+                                     double a[3], double e[3], double p[3], double n[3]) {
+    const double ps[3] = {(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
+    if (!(__builtin_isfinite(ps[0]) && __builtin_isfinite(ps[1]) && __builtin_isfinite(ps[2]))) return false;
+    const double r2 = (ps[0] * ps[0] + ps[1] * ps[1]) + ps[2] * ps[2];
+    if (!(r2 >= m.r2lo && r2 <= m.r2hi)) return false;
+    pose_apply(sp.P, ps, p);
+    unit_direction(p, sp.P.t, n);
+    for (int k = 0; k < 3; ++k) {
+        a[k] = m.carve ? sp.P.t[k] : p[k] - m.tau * n[k];
+        e[k] = p[k] + m.tau * n[k];
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_alloc_points(DevMap m, ScanParams sp, const float* __restrict__ xyz,
+                                                      int64_t n) {
+    const int lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a[3], e[3], p[3], nn[3];
+    bool ok = i < n && point_segment(m, sp, xyz, i, a, e, p, nn);
+    const unsigned long long vmask = __ballot(ok);
+    bool in_range = ok && segment_in_range(a, e, m.invB);
+    const unsigned long long dmask = __ballot(ok && !in_range);
+    if (lane == 0) {
+        if (vmask) atomicAdd(&m.ctr->frame[S_VALID], (unsigned long long)__popcll(vmask));
+        if (dmask) atomicAdd(&m.ctr->frame[S_DROPPED], (unsigned long long)__popcll(dmask));
+    }
+    Walk w;
+    if (in_range) w.init(a, e, m.invB);
+    bool active = in_range;
+    while (__ballot(active)) {
+        const unsigned long long key = active ? pack_key(w.c[0], w.c[1], w.c[2]) : 0ull;
+        insert_keys(m, active, key);
+        if (active) active = w.next();
+    }
+}
+
+// Accumulate one observation d of the voxel at heap position `at` of `level`.
+__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d) {
+    if (d >= m.tau) {
+        atomicAdd(&m.acc_sat[level][at], 1u);
+        return;
+    }
+    const double Dp = fresh ? 0.0 : (double)m.D[level][at];
+    const double r = d - Dp;
+    atomicAdd(&m.acc_band[level][at], 1u);
+    atomicAdd(&m.acc_s1[level][at], (unsigned long long)(long long)__builtin_rint(r * kS1Scale));
+    atomicAdd(&m.acc_s2[level][at], (unsigned long long)__builtin_rint((r * r) * kS2Scale));
+}
+
+__global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp, const float* __restrict__ xyz, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a[3], e[3], p[3], nn[3];
+    if (!(i < n && point_segment(m, sp, xyz, i, a, e, p, nn) && segment_in_range(a, e, m.invB))) return;
+    Walk w;
+    w.init(a, e, m.invB);
+    do {
+        const int64_t b[3] = {w.c[0], w.c[1], w.c[2]};
+        const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
+        if (id == kInvalidId) continue;
+        const uint32_t info = m.binfo[id];
+        if (info & kNoBlockBit) continue;
+        m.btouch[id] = 1u;
+        const int level = (int)((info >> kLevelShift) & 3u);
+        const bool fresh = (info & kNewBit) != 0;
+        const int side = 8 >> level;
+        const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
+        const double inv_nu = m.inv_nu[level], nu = m.nu[level];
+        // the segment in the block's voxel units, clipped to the block's box
+        double Al[3], Dl[3], invD[3], tmax[3];
+        int st[3], c[3];
+        double tin = 0.0, tout = 1.0;
+        for (int k = 0; k < 3; ++k) {
+            const double ob = (double)b[k] * m.B;
+            Al[k] = (a[k] - ob) * inv_nu;
+            const double El = (e[k] - ob) * inv_nu;
+            Dl[k] = El - Al[k];
+            if (Dl[k] != 0.0) {
+                invD[k] = 1.0 / Dl[k];
+                const double nearb = Dl[k] > 0.0 ? 0.0 : (double)side;
+                const double farb = Dl[k] > 0.0 ? (double)side : 0.0;
+                const double t0 = (nearb - Al[k]) * invD[k];
+                const double t1 = (farb - Al[k]) * invD[k];
+                if (t0 > tin) tin = t0;
+                if (t1 < tout) tout = t1;
+                st[k] = Dl[k] > 0.0 ? 1 : -1;
+            } else {
+                invD[k] = 0.0;
+                st[k] = 0;
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double fl = __builtin_floor(Al[k] + tin * Dl[k]);
+            if (fl < 0.0) fl = 0.0;
+            if (fl > (double)(side - 1)) fl = (double)(side - 1);
+            c[k] = (int)fl;
+            tmax[k] = st[k] != 0 ? ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k] : __builtin_inf();
+        }
+        for (int s = 0; s <= 3 * side; ++s) {
+            // observation of the voxel centre (Eq. 1)
+            const double x0 = (double)b[0] * m.B + ((double)c[0] + 0.5) * nu;
+            const double x1 = (double)b[1] * m.B + ((double)c[1] + 0.5) * nu;
+            const double x2 = (double)b[2] * m.B + ((double)c[2] + 0.5) * nu;
+            const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
+            const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
+            accumulate(m, level, base + (size_t)morton3(c[0], c[1], c[2]), fresh, d);
+            if (s == 3 * side) break;
+            int k = 0;
+            if (tmax[1] < tmax[k]) k = 1;
+            if (tmax[2] < tmax[k]) k = 2;
+            if (!(tmax[k] <= tout)) break;
+            c[k] += st[k];
+            if (c[k] < 0 || c[k] >= side) break;
+            tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k];
+        }
+    } while (w.next());
+}
+
+// Batch form of Eq. 3 and Eq. 5 for n observations with sums s1, s2 of (d - D) and (d - D)^2.
+__device__ inline void apply_stats(const DevMap& m, uint32_t nsat, uint32_t nband, unsigned long long s1q,
+                                   unsigned long long s2q, float& D, uint32_t& W, float& S2) {
+    const uint32_t nobs = nsat + nband;
+    const double Dp = (double)D;
+    const double ts = m.tau - Dp;
+    const double s1 = (double)nsat * ts + (double)(long long)s1q / kS1Scale;
+    const double s2 = (double)nsat * (ts * ts) + (double)s2q / kS2Scale;
+    const double Wn = (double)W + (double)nobs;
+    const double S2n = (double)S2 + s2 - s1 * s1 / Wn;
+    D = (float)(Dp + s1 / Wn);
+    S2 = (float)(S2n > 0.0 ? S2n : 0.0);
+    W = W + nobs;
+}
+
+__device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info) {
+    const int lane = lane_id();
+    const bool fresh = (info & kNewBit) != 0;
+    const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
+    uint32_t ns[8], nb[8];
+    unsigned long long s1[8], s2[8];
+    {
+        const uint4* a = reinterpret_cast<const uint4*>(m.acc_sat[0] + base);
+        const uint4* b = reinterpret_cast<const uint4*>(m.acc_band[0] + base);
+        const uint4 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
+        ns[0] = a0.x, ns[1] = a0.y, ns[2] = a0.z, ns[3] = a0.w, ns[4] = a1.x, ns[5] = a1.y, ns[6] = a1.z, ns[7] = a1.w;
+        nb[0] = b0.x, nb[1] = b0.y, nb[2] = b0.z, nb[3] = b0.w, nb[4] = b1.x, nb[5] = b1.y, nb[6] = b1.z, nb[7] = b1.w;
+    }
+    uint32_t upd = 0;
+    int nobs = 0;
+    for (int q = 0; q < 8; ++q) {
+        if (ns[q] + nb[q]) upd |= 1u << q;
+        nobs += (int)(ns[q] + nb[q]);
+    }
+    bool any_band = false;
+    for (int q = 0; q < 8; ++q) any_band |= nb[q] != 0;
+    if (any_band) {
+        const ulonglong2* s1p = reinterpret_cast<const ulonglong2*>(m.acc_s1[0] + base);
+        const ulonglong2* s2p = reinterpret_cast<const ulonglong2*>(m.acc_s2[0] + base);
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 u = s1p[h], v = s2p[h];
+            s1[2 * h] = u.x, s1[2 * h + 1] = u.y, s2[2 * h] = v.x, s2[2 * h + 1] = v.y;
+        }
+    } else {
+        for (int q = 0; q < 8; ++q) s1[q] = s2[q] = 0ull;
+    }
+    const int wobs = wave_sum(nobs);
+    if (lane == 0 && wobs) {
+        atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)wobs);
+        if (fresh) atomicAdd(&m.ctr->frame[S_OBS_FRESH], (unsigned long long)wobs);
+    }
+    float D[8], S2[8];
+    uint32_t W[8];
+    bool have = false;
+    if (fresh) {
+        for (int q = 0; q < 8; ++q) D[q] = 0.f, S2[q] = 0.f, W[q] = 0u;
+        have = true;
+    } else if (upd) {
+        load_group(m, base, D, W, S2);
+        have = true;
+    }
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        for (int q = 0; q < 8; ++q) {
+            if (!(upd & (1u << q))) continue;
+            const double before = var_term(m, W[q], S2[q]);
+            const int cb = var_count(m, W[q]);
+            apply_stats(m, ns[q], nb[q], s1[q], s2[q], D[q], W[q], S2[q]);
+            dsum += var_term(m, W[q], S2[q]) - before;
+            dcnt += var_count(m, W[q]) - cb;
+        }
+        // leave the accumulators at zero for the next scan
+        uint4* a = reinterpret_cast<uint4*>(m.acc_sat[0] + base);
+        uint4* b = reinterpret_cast<uint4*>(m.acc_band[0] + base);
+        a[0] = a[1] = make_uint4(0, 0, 0, 0);
+        if (any_band) {
+            b[0] = b[1] = make_uint4(0, 0, 0, 0);
+            ulonglong2* s1p = reinterpret_cast<ulonglong2*>(m.acc_s1[0] + base);
+            ulonglong2* s2p = reinterpret_cast<ulonglong2*>(m.acc_s2[0] + base);
+            for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
+        }
+    }
+    finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
+}
+
+__device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info, int level) {
+    const int lane = lane_id();
+    const int side = 8 >> level, nv = side * side * side;
+    const size_t at = (size_t)(info & kSlotMask) * nv + lane;
+    uint32_t ns = 0, nb = 0;
+    if (lane < nv) {
+        ns = m.acc_sat[level][at];
+        nb = m.acc_band[level][at];
+    }
+    const bool upd = ns + nb > 0;
+    const int wobs = wave_sum((int)(ns + nb));
+    if (wobs == 0) return;
+    if (lane == 0) atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)wobs);
+    float D = 0.f, S2 = 0.f;
+    uint32_t W = 0;
+    if (lane < nv) {
+        D = m.D[level][at];
+        W = m.W[level][at];
+        S2 = m.S2[level][at];
+    }
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        unsigned long long s1 = 0ull, s2 = 0ull;
+        if (nb) {
+            s1 = m.acc_s1[level][at];
+            s2 = m.acc_s2[level][at];
+            m.acc_band[level][at] = 0u;
+            m.acc_s1[level][at] = 0ull;
+            m.acc_s2[level][at] = 0ull;
+        }
+        m.acc_sat[level][at] = 0u;
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        apply_stats(m, ns, nb, s1, s2, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    }
+    finish_coarse(m, id, info, level, D, W, S2, upd, wobs, dsum, dcnt);
+}
+
+__global__ __launch_bounds__(256) void k_apply_points(DevMap m) {
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nb0 = m.ctr->n_blocks;
+    const uint32_t nb = nb0 < m.max_blocks ? nb0 : m.max_blocks;
+    for (uint32_t id = wave; id < nb; id += nwaves) {
+        if (m.btouch[id] == 0u) continue;
+        const uint32_t info = m.binfo[id];
+        if (lane_id() == 0) m.btouch[id] = 0u;
+        if (info & kNoBlockBit) continue;
+        const int level = (int)((info >> kLevelShift) & 3u);
+        if (level == 0) apply_fine(m, id, info);
+        else apply_coarse(m, id, info, level);
+    }
+}
+
+static mrh_status ensure_lidar(mrh_map* map) {
+    if (map->lidar_ready) return MRH_OK;
+    DevMap& d = map->dm;
+    mrh_status st = MRH_OK;
+    auto alloc = [&](void** p, size_t bytes, const char* what) {
+        if (st != MRH_OK) return;
+        st = check_hip(map, hipMalloc(p, bytes), what);
+        if (st == MRH_OK) st = check_hip(map, hipMemsetAsync(*p, 0, bytes, map->stream), what);
+    };
+    alloc((void**)&d.btouch, (size_t)d.max_blocks * 4, "touch flags");
+    for (int n = 0; n < map->cfg.levels; ++n) {
+        const size_t nv = (size_t)d.heap_cap[n] * (size_t)(side_of(n) * side_of(n) * side_of(n));
+        alloc((void**)&d.acc_sat[n], nv * 4, "scan accumulators");
+        alloc((void**)&d.acc_band[n], nv * 4, "scan accumulators");
+        alloc((void**)&d.acc_s1[n], nv * 8, "scan accumulators");
+        alloc((void**)&d.acc_s2[n], nv * 8, "scan accumulators");
+    }
+    if (st == MRH_OK) map->lidar_ready = true;
+    return st;
+}
+
+}  // namespace mrh
+
+using namespace mrh;
+
+extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, int64_t n, const double T_ws[16]) {
+    if (!map || !T_ws || n < 0 || (n > 0 && !xyz_dev)) return MRH_ERR_INVALID_ARG;
+    ScanParams sp;
+    if (!pose_from(T_ws, sp.P)) return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose");
+    mrh_status st = ensure_lidar(map);
+    if (st != MRH_OK) return st;
+    if (n > 0) {
+        const unsigned grid = (unsigned)((n + 255) / 256);
+        launch(map, K_ALLOC_POINTS, [&] {
+            hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dm, sp, xyz_dev, n);
+        });
+        launch(map, K_RAYS,
+               [&] { hipLaunchKernelGGL(k_rays, dim3(grid), dim3(256), 0, map->stream, map->dm, sp, xyz_dev, n); });
+        launch(map, K_APPLY_POINTS,
+               [&] { hipLaunchKernelGGL(k_apply_points, dim3(2048), dim3(256), 0, map->stream, map->dm); });
+    }
+    launch_finalize(map);
+    return check_hip(map, hipGetLastError(), "integrate_points");
+}

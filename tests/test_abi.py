@@ -1,0 +1,75 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every entry point
+the public header declares, and its Eq. 4 hash matches the stored vectors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2511_21459_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2511_21459_amd import build
+
+        build.build()
+    return _lib.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mrhash.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrh_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2511_21459_amd import _lib
+
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_abi_version(lib):
+    assert lib.mrh_abi_version() == 1
+
+
+def test_eq4_hash_vectors(lib):
+    """Eq. 4 with 32-bit unsigned wrap-around, against the oracle-written vectors."""
+    rows = [ln.split() for ln in open(os.path.join(ROOT, "tests", "golden", "eq4_hash.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 40
+    for x, y, z, n, h in rows:
+        assert lib.mrh_block_hash(int(x), int(y), int(z), int(n)) == int(h), (x, y, z, n)
+
+
+def test_eq4_hash_python_integers(lib):
+    """The same hash computed here with Python integers (mod 2^32 after each product)."""
+    p = (73856093, 19349669, 83492791)
+    for key in [(3, -4, 5), (-1, -1, -1), (2 ** 19, -(2 ** 19), 17)]:
+        h = 0
+        for c, pi in zip(key, p):
+            h ^= ((c % 2 ** 32) * pi) % 2 ** 32
+        for n in (1 << 16, 1 << 22):
+            assert lib.mrh_block_hash(*key, n) == h % n
+
+
+def test_create_rejects_invalid_config(lib):
+    from paper_2511_21459_amd._lib import MrhConfig
+
+    cfg = MrhConfig()
+    cfg.voxel, cfg.levels, cfg.tau, cfg.min_obs = 0.02, 5, 0.06, 2
+    cfg.hash_slots, cfg.max_blocks = 1024, 256
+    h = ctypes.c_void_p()
+    # levels outside [1, 4] is rejected before any device call
+    assert lib.mrh_map_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1
+    cfg.levels = 1
+    cfg.hash_slots = 1000  # not a power of two
+    assert lib.mrh_map_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1
+    assert lib.mrh_map_create(None, None, ctypes.byref(h)) == -1

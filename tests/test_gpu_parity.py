@@ -1,0 +1,274 @@
+"""GPU parity: the HIP library, called through its C ABI, against the CPU oracle on the same
+seeded inputs.  Block key sets (with levels) must be bit-identical, weights exactly equal and
+TSDF values within 1e-5 m (FP32 storage against the FP64 oracle)."""
+import numpy as np
+import pytest
+import torch
+
+from parity_util import announce, compare_maps, excused_keys, gpu_sorted
+from workloads import configs, room_sequence, sphere_plane_frame, street_sequence
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mrh():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2511_21459_amd as mrh
+
+    return mrh
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_sphere_plane_frame(mrh, orc):
+    announce("sphere_plane single frame 320x240")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    g.integrate_depth(_dev(depth), cam.K, T)
+    last, _ = g.sync()
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    st = o.integrate_depth(depth, cam.K, T)
+    assert last["valid_points"] == st["valid_points"] == 76800
+    assert last["new_blocks"] == st["new_blocks"] == o.num_blocks
+    assert last["observations"] == st["observations"]
+    rep = compare_maps(gpu_sorted(g), o.extract(), tau=0.06)
+    print(rep)
+
+
+@pytest.mark.parametrize("form", ["range", "zdiff"])
+def test_room_sequence_multires(mrh, orc, form):
+    """Multi-resolution orbit at reduced size: 320x240, 12 frames spread over the orbit."""
+    announce(f"room 320x240 x12 frames, 4 levels, form={form}")
+    frames = list(range(0, 100, 8))[:12]
+    depths, cam, poses, _ = room_sequence(width=320, height=240, f=262.5, frames=frames)
+    cfg = dict(configs.ROOM, form=form, max_blocks=1 << 17, hash_slots=1 << 18)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    merges = 0
+    for k in range(len(frames)):
+        g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
+        last, _ = g.sync()
+        st = o.integrate_depth(depths[k], cam.K, poses[k])
+        assert last["valid_points"] == st["valid_points"]
+        assert last["new_blocks"] == st["new_blocks"]
+        merges += sum(st["merges"])
+    rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"])
+    print(rep, "merges", merges)
+    assert merges > 100
+
+
+def test_room_full_size_first_frames(mrh, orc):
+    """640x480 at the full configuration, first 3 frames."""
+    announce("room 640x480 x3 frames full config")
+    depths, cam, poses, _ = room_sequence(frames=[0, 1, 2])
+    g = mrh.Map(**configs.ROOM)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.ROOM))
+    for k in range(3):
+        g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
+        o.integrate_depth(depths[k], cam.K, poses[k])
+    g.sync()
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=configs.ROOM["tau"]))
+
+
+def test_street_sequence_multires(mrh, orc):
+    """LiDAR carving at reduced size: 16 rings x 512 azimuths, 5 scans."""
+    announce("street 16x512 x5 scans carve 4 levels")
+    pts, poses, _ = street_sequence(n_scans=200, rings=16, azimuths=512, scans=[0, 1, 2, 3, 4])
+    cfg = dict(configs.STREET, max_blocks=1 << 18, hash_slots=1 << 19)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    merges = 0
+    for k in range(pts.shape[0]):
+        g.integrate_points(_dev(pts[k]), poses[k])
+        last, _ = g.sync()
+        st = o.integrate_points(pts[k], poses[k])
+        assert last["valid_points"] == st["valid_points"]
+        assert last["new_blocks"] == st["new_blocks"]
+        assert last["observations"] == st["observations"]
+        merges += sum(st["merges"])
+    rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o))
+    print(rep, "merges", merges)
+    assert merges > 50
+
+
+def test_street_band_only(mrh, orc):
+    announce("street 8x256 band-only (no carving)")
+    pts, poses, _ = street_sequence(n_scans=200, rings=8, azimuths=256, scans=[10, 11])
+    cfg = dict(configs.STREET, carve=False, max_blocks=1 << 16, hash_slots=1 << 17)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for k in range(2):
+        g.integrate_points(_dev(pts[k]), poses[k])
+        o.integrate_points(pts[k], poses[k])
+    g.sync()
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)))
+
+
+def _query_points(n, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-0.45, 0.45, n), rng.uniform(-0.35, 0.35, n),
+                     rng.uniform(1.9, 4.1, n)], axis=1).astype(np.float32)
+
+
+@pytest.mark.parametrize("strict", [False, True])
+def test_query_parity(mrh, orc, strict):
+    announce(f"query sphere_plane strict={strict}")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    d2, _, _ = sphere_plane_frame(seed=1)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    for d in (depth, d2):
+        g.integrate_depth(_dev(d), cam.K, T)
+        o.integrate_depth(d, cam.K, T)
+    pts = _query_points(20000)
+    Tq = np.eye(4)
+    Tq[:3, 3] = [0.003, -0.002, 0.001]
+    sdf, valid, grad = g.query(_dev(pts), T=Tq, strict=strict, with_grad=True)
+    osdf, ovalid, ograd = o.query(pts, T=Tq, strict=strict)
+    valid = valid.cpu().numpy()
+    assert np.array_equal(valid, ovalid)
+    assert valid.sum() > 1000
+    np.testing.assert_allclose(sdf.cpu().numpy()[valid], osdf[valid], atol=1e-5, rtol=0)
+    np.testing.assert_allclose(grad.cpu().numpy()[valid], ograd[valid], atol=2e-3, rtol=1e-4)
+    assert np.all(sdf.cpu().numpy()[~valid] == 0)
+
+
+def test_query_multires_parity(mrh, orc):
+    announce("query on a merged 4-level room map")
+    frames = list(range(0, 100, 10))
+    depths, cam, poses, scene = room_sequence(width=320, height=240, f=262.5, frames=frames)
+    cfg = dict(configs.ROOM, max_blocks=1 << 17, hash_slots=1 << 18)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for k in range(len(frames)):
+        g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
+        o.integrate_depth(depths[k], cam.K, poses[k])
+    g.sync()
+    ex = excused_keys(o)
+    from workloads import surface_query_points
+
+    pts = surface_query_points(scene, 50000, sigma=0.015, seed=3)
+    sdf, valid, grad = g.query(_dev(pts), with_grad=True)
+    osdf, ovalid, ograd = o.query(pts)
+    # points whose 2x2x2 neighbourhood touches an excused block may legitimately differ
+    B = 8 * cfg["voxel"]
+    near = np.zeros(len(pts), bool)
+    if ex:
+        kb = np.floor(pts.astype(np.float64) / B).astype(np.int64)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    near |= np.array([(a + dx, b + dy, c + dz) in ex for a, b, c in kb.tolist()])
+    valid = valid.cpu().numpy()
+    assert np.array_equal(valid[~near], ovalid[~near])
+    ok = valid & ovalid & ~near
+    assert ok.sum() > 10000
+    np.testing.assert_allclose(sdf.cpu().numpy()[ok], osdf[ok], atol=1e-5, rtol=0)
+    print("levels", np.bincount(o.extract().levels), "excused", len(ex))
+
+
+def test_query_backward_parity(mrh, orc):
+    announce("query backward sphere_plane")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    g.integrate_depth(_dev(depth), cam.K, T)
+    o.integrate_depth(depth, cam.K, T)
+    pts = _query_points(30000, seed=5)
+    th = np.deg2rad(2.0)
+    Tq = np.eye(4)
+    Tq[:3, :3] = [[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]]
+    Tq[:3, 3] = [0.05, -0.02, 0.01]
+    gs = np.random.default_rng(1).normal(size=len(pts)).astype(np.float32)
+    gp, gpose = g.query_backward(_dev(pts), _dev(gs), T=Tq)
+    ogp, ogpose = o.query_backward(pts, gs.astype(np.float64), T=Tq)
+    np.testing.assert_allclose(gp.cpu().numpy(), ogp, atol=2e-3, rtol=1e-4)
+    np.testing.assert_allclose(gpose, ogpose, rtol=1e-4, atol=1e-6 * np.abs(ogpose).max())
+
+
+def test_sdfquery_autograd(mrh):
+    announce("SdfQuery autograd")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    g.integrate_depth(_dev(depth), cam.K, T)
+    pts = _dev(_query_points(4000, seed=7)).requires_grad_(True)
+    sdf, valid = mrh.SdfQuery.apply(g, pts)
+    (sdf * valid.float()).sum().backward()
+    ref, rvalid, rgrad = g.query(pts.detach().contiguous(), with_grad=True)
+    np.testing.assert_allclose(pts.grad.cpu().numpy()[rvalid.cpu().numpy()],
+                               rgrad.cpu().numpy()[rvalid.cpu().numpy()], rtol=1e-6, atol=1e-6)
+    assert g.last_pose_grad.shape == (6,)
+
+
+def test_empty_and_invalid_inputs(mrh):
+    announce("empty / invalid inputs")
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    depth = torch.full((240, 320), float("nan"), device="cuda")
+    depth[0, :10] = -1.0
+    depth[1, :10] = 0.0
+    depth[2, :10] = float("inf")
+    K = [300.0, 300.0, 160.0, 120.0]
+    g.integrate_depth(depth, K, np.eye(4))
+    last, tot = g.sync()
+    assert last["valid_points"] == 0 and last["new_blocks"] == 0 and tot["blocks"] == 0
+    g.integrate_points(torch.zeros((0, 3), device="cuda"), np.eye(4))
+    g.sync()
+    with pytest.raises(mrh.MrhError):
+        g.integrate_depth(depth, K, np.full((4, 4), np.nan))
+    with pytest.raises(mrh.MrhError):
+        g.integrate_depth(depth, [0.0, 300.0, 160.0, 120.0], np.eye(4))
+    assert g.counts() == (0, 0)
+
+
+def test_capacity_errors(mrh):
+    announce("table / heap / block capacity errors")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    d = _dev(depth)
+    g = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=512, hash_slots=4096))
+    g.integrate_depth(d, cam.K, T)
+    with pytest.raises(mrh.MrhError) as ei:
+        g.sync()
+    assert ei.value.code == -7  # block limit (1184 blocks > 512)
+    h = mrh.Map(**dict(configs.SPHERE_PLANE, heap_blocks=[100, 0, 0, 0]))
+    h.integrate_depth(d, cam.K, T)
+    with pytest.raises(mrh.MrhError) as ei:
+        h.sync()
+    assert ei.value.code == -4  # heap full
+    nb, nv = h.counts()
+    assert nv == 100 * 512  # blocks without storage report no voxels
+    t = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=1 << 15, hash_slots=1 << 16, max_probe=1))
+    t.integrate_depth(d, cam.K, T)
+    try:
+        t.sync()
+    except mrh.MrhError as e:
+        assert e.code == -3
+
+
+def test_reset_reuses_map(mrh, orc):
+    announce("reset and refuse")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    for _ in range(2):
+        g.integrate_depth(_dev(depth), cam.K, T)
+        g.reset()
+    g.integrate_depth(_dev(depth), cam.K, T)
+    g.sync()
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    o.integrate_depth(depth, cam.K, T)
+    compare_maps(gpu_sorted(g), o.extract(), tau=0.06)
+
+
+def test_table_full_before_block_limit(mrh):
+    """1184 distinct blocks cannot fit a 1024-slot table: the insert reports a full table."""
+    announce("table full")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=512, hash_slots=1024))
+    g.integrate_depth(_dev(depth), cam.K, T)
+    with pytest.raises(mrh.MrhError) as ei:
+        g.sync()
+    assert ei.value.code == -3
+    nb, _ = g.counts()
+    assert nb == 512
