@@ -1,12 +1,15 @@
 // RGB-D fusion (Sec. 3.1 "Cameras", Eq. 2; Eq. 3 and Eq. 5; Sec. 3.2.1 merging criterion).
 //
 // One frame is three launches on the map's stream:
-//   k_alloc_depth      one thread per pixel: back-projection, band walk over the block lattice,
-//                      lookup, wave-deduplicated lock-free insert, ballot/prefix-sum id and heap
-//                      slot assignment for the new blocks
-//   k_integrate_depth  one wave per allocated block (grid-stride): conservative frustum cull,
-//                      per-voxel projection and update, block variance bookkeeping, and the merge
-//                      of a block whose mean variance fell below the threshold
+//   k_alloc_depth      pixel workgroups: back-projection, band walk over the block lattice, lookup,
+//                      wave-deduplicated lock-free insert, ballot/prefix-sum ids and heap slots for
+//                      new blocks (queued for the update); cull workgroups: one thread per block
+//                      that existed at the frame's start, conservative frustum test, visible blocks
+//                      queued per level
+//   k_integrate_depth  one task per queued level-0 or level-1 block (a wave), 8 level-2 or 64
+//                      level-3 blocks per wave: per-voxel projection and update, block variance
+//                      bookkeeping and the merge of a block whose mean variance fell below the
+//                      threshold
 //   k_finalize         freed slots back to their stacks, statistics
 #include <cmath>
 
@@ -29,18 +32,48 @@ struct DepthFrame {
 // allocation
 // ---------------------------------------------------------------------------------------------
 
-// 256 threads = 4 waves cover a 16 x 16 pixel tile; each wave a 16 x 4 strip (good key reuse).
-__global__ __launch_bounds__(256) void k_alloc_depth(DevMap m, DepthFrame f, const float* __restrict__ depth) {
+__device__ inline bool block_visible(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz);
+
+// Workgroups [0, tiles): 16 x 16 pixel tiles, each wave a 16 x 4 strip (good key reuse).
+// Workgroups [tiles, gridDim): one thread per block that existed at the frame's start.
+__global__ __launch_bounds__(256) void k_alloc_depth(DevMap m, DepthFrame f, const float* __restrict__ depth,
+                                                     uint32_t tiles_x, uint32_t tiles) {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const int u = blockIdx.x * 16 + (lane & 15);
-    const int v = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+    if (blockIdx.x >= tiles) {
+        // conservative frustum cull of the existing blocks
+        const uint32_t n = m.ctr->n_prev;
+        const uint32_t stride = (gridDim.x - tiles) * blockDim.x;
+        for (uint32_t base = (blockIdx.x - tiles) * blockDim.x; base < n; base += stride) {
+            const uint32_t id = base + threadIdx.x;
+            int level = -1;
+            if (id < n) {
+                const uint32_t info = m.binfo[id];
+                if (!(info & kNoBlockBit)) {
+                    int32_t bx, by, bz;
+                    unpack_key(m.bkey[id], bx, by, bz);
+                    if ((info & kNewBit) || block_visible(m, f, bx, by, bz)) level = (int)((info >> kLevelShift) & 3u);
+                }
+            }
+            for (int lv = 0; lv < 4; ++lv) {
+                const unsigned long long msk = __ballot(level == lv);
+                if (!msk) continue;
+                const int f0 = __ffsll((long long)msk) - 1;
+                uint32_t vb = 0;
+                if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[lv], (uint32_t)__popcll(msk));
+                vb = (uint32_t)__shfl((int)vb, f0);
+                if (level == lv) m.vis[lv][vb + rank_in_mask(msk)] = id;
+            }
+        }
+        return;
+    }
+    const int u = (blockIdx.x % tiles_x) * 16 + (lane & 15);
+    const int v = (blockIdx.x / tiles_x) * 16 + wave * 4 + (lane >> 4);
     bool ok = u < f.width && v < f.height;
     double d = 0.0;
     if (ok) {
         d = (double)depth[(int64_t)v * f.width + u];
         ok = __builtin_isfinite(d) && d > 0.0 && d <= m.max_depth;
     }
-    const unsigned long long vmask = __ballot(ok);
     Walk w;
     bool in_range = false;
     if (ok) {
@@ -54,16 +87,24 @@ __global__ __launch_bounds__(256) void k_alloc_depth(DevMap m, DepthFrame f, con
         in_range = segment_in_range(a, e, m.invB);
         if (in_range) w.init(a, e, m.invB);
     }
-    const unsigned long long dmask = __ballot(ok && !in_range);
+    __shared__ uint32_t cnt[2];
+    if (threadIdx.x == 0) cnt[0] = cnt[1] = 0;
+    __syncthreads();
+    const unsigned long long vmask = __ballot(ok), dmask = __ballot(ok && !in_range);
     if (lane == 0) {
-        if (vmask) atomicAdd(&m.ctr->frame[S_VALID], (unsigned long long)__popcll(vmask));
-        if (dmask) atomicAdd(&m.ctr->frame[S_DROPPED], (unsigned long long)__popcll(dmask));
+        atomicAdd(&cnt[0], (uint32_t)__popcll(vmask));
+        atomicAdd(&cnt[1], (uint32_t)__popcll(dmask));
     }
     bool active = in_range;
     while (__ballot(active)) {
-        const unsigned long long key = active ? pack_key(w.c[0], w.c[1], w.c[2]) : 0ull;
-        insert_keys(m, active, key);
+        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
+        insert_keys(m, active, key, true);
         if (active) active = w.next();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        stat_add(m, S_VALID, cnt[0]);
+        stat_add(m, S_DROPPED, cnt[1]);
     }
 }
 
@@ -109,10 +150,19 @@ __device__ inline bool block_visible(const DevMap& m, const DepthFrame& f, int64
     return true;
 }
 
+// Statistics gathered by one wave over its tasks: obs / fresh / merges[0..1] are wave-uniform,
+// lane_obs / lane_merges (packed blocks) are per lane.
+struct TaskStats {
+    unsigned long long obs = 0, fresh = 0, merges[2] = {0, 0}, lane_obs = 0, lane_merges = 0;
+};
+
 // Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
 __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            uint32_t id, int64_t bx, int64_t by, int64_t bz, uint32_t info) {
+                                            uint32_t id, TaskStats& ts) {
     const int lane = lane_id();
+    const uint32_t info = m.binfo[id];
+    int32_t bx, by, bz;
+    unpack_key(m.bkey[id], bx, by, bz);
     const bool fresh = (info & kNewBit) != 0;
     int I, J, K;
     demorton3(lane, I, J, K);
@@ -142,10 +192,8 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
     }
     const int nupd = wave_sum((int)__popc(upd));
     if (nupd == 0 && !fresh) return;
-    if (lane == 0 && nupd) {
-        atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)nupd);
-        if (fresh) atomicAdd(&m.ctr->frame[S_OBS_FRESH], (unsigned long long)nupd);
-    }
+    ts.obs += (unsigned long long)nupd;
+    if (fresh) ts.fresh += (unsigned long long)nupd;
 
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
     float D[8], S2[8];
@@ -168,41 +216,41 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         dsum += var_term(m, W[q], S2[q]) - before;
         dcnt += var_count(m, W[q]) - cb;
     }
-    finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt);
+    ts.merges[0] += (unsigned long long)finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt);
 }
 
-// Level n >= 1 block: lane l owns the voxel at Morton position l.
-__device__ inline void integrate_coarse_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                              uint32_t id, int64_t bx, int64_t by, int64_t bz, uint32_t info,
-                                              int level) {
+// Camera-frame centre of voxel (i, j, k) of block b at `level`, canonical FP64.
+__device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz, int level,
+                                    int i, int j, int k, double& x0, double& x1, double& x2) {
+    const double nu = m.nu[level];
+    const double c0 = (double)bx * m.B + ((double)i + 0.5) * nu;
+    const double c1 = (double)by * m.B + ((double)j + 0.5) * nu;
+    const double c2 = (double)bz * m.B + ((double)k + 0.5) * nu;
+    const double d0 = c0 - f.P.t[0], d1 = c1 - f.P.t[1], d2 = c2 - f.P.t[2];
+    x0 = (f.P.R[0][0] * d0 + f.P.R[1][0] * d1) + f.P.R[2][0] * d2;
+    x1 = (f.P.R[0][1] * d0 + f.P.R[1][1] * d1) + f.P.R[2][1] * d2;
+    x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
+}
+
+// Level-1 block: lane l owns the voxel at Morton position l.
+__device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                              uint32_t id, TaskStats& ts) {
     const int lane = lane_id();
-    const int side = 8 >> level, nv = side * side * side;
+    const uint32_t info = m.binfo[id];
+    int32_t bx, by, bz;
+    unpack_key(m.bkey[id], bx, by, bz);
+    int i, j, k;
+    demorton3(lane, i, j, k);
+    double x0, x1, x2;
+    voxel_camera(m, f, bx, by, bz, 1, i, j, k, x0, x1, x2);
     float obs = 0.f;
-    bool upd = false;
-    if (lane < nv) {
-        int i, j, k;
-        demorton3(lane, i, j, k);
-        const double nu = m.nu[level];
-        const double c0 = (double)bx * m.B + ((double)i + 0.5) * nu;
-        const double c1 = (double)by * m.B + ((double)j + 0.5) * nu;
-        const double c2 = (double)bz * m.B + ((double)k + 0.5) * nu;
-        const double d0 = c0 - f.P.t[0], d1 = c1 - f.P.t[1], d2 = c2 - f.P.t[2];
-        const double x0 = (f.P.R[0][0] * d0 + f.P.R[1][0] * d1) + f.P.R[2][0] * d2;
-        const double x1 = (f.P.R[0][1] * d0 + f.P.R[1][1] * d1) + f.P.R[2][1] * d2;
-        const double x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
-        upd = project_observe(m, f, depth, x0, x1, x2, obs);
-    }
+    const bool upd = project_observe(m, f, depth, x0, x1, x2, obs);
     const int nupd = __popcll(__ballot(upd));
     if (nupd == 0) return;
-    if (lane == 0) atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)nupd);
-    const size_t at = (size_t)(info & kSlotMask) * nv + lane;
-    float D = 0.f, S2 = 0.f;
-    uint32_t W = 0;
-    if (lane < nv) {
-        D = m.D[level][at];
-        W = m.W[level][at];
-        S2 = m.S2[level][at];
-    }
+    ts.obs += (unsigned long long)nupd;
+    const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
+    float D = m.D[1][at], S2 = m.S2[1][at];
+    uint32_t W = m.W[1][at];
     double dsum = 0.0;
     int dcnt = 0;
     if (upd) {
@@ -212,23 +260,78 @@ __device__ inline void integrate_coarse_block(const DevMap& m, const DepthFrame&
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    finish_coarse(m, id, info, level, D, W, S2, upd, nupd, dsum, dcnt);
+    ts.merges[1] += (unsigned long long)finish_coarse(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt);
+}
+
+// 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
+__device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                               const uint32_t* list, uint32_t count, uint32_t group, int level,
+                                               TaskStats& ts) {
+    const int lane = lane_id();
+    const int seg = level == 2 ? 8 : 1;
+    const uint32_t bi = group * (uint32_t)(64 / seg) + (uint32_t)(lane / seg);
+    const bool live = bi < count;
+    uint32_t id = 0, info = 0;
+    bool upd = false;
+    float obs = 0.f;
+    if (live) {
+        id = list[bi];
+        info = m.binfo[id];
+        int32_t bx, by, bz;
+        unpack_key(m.bkey[id], bx, by, bz);
+        int i, j, k;
+        demorton3(lane % seg, i, j, k);
+        double x0, x1, x2;
+        voxel_camera(m, f, bx, by, bz, level, i, j, k, x0, x1, x2);
+        upd = project_observe(m, f, depth, x0, x1, x2, obs);
+    }
+    if (!__ballot(upd)) return;
+    float D = 0.f, S2 = 0.f;
+    uint32_t W = 0;
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        const size_t at = (size_t)(info & kSlotMask) * seg + (lane % seg);
+        D = m.D[level][at];
+        W = m.W[level][at];
+        S2 = m.S2[level][at];
+        ts.lane_obs += 1;
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        welford(obs, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    } else if (live && seg > 1) {
+        // a segment whose block merges needs all of its voxels
+        const size_t at = (size_t)(info & kSlotMask) * seg + (lane % seg);
+        D = m.D[level][at];
+        W = m.W[level][at];
+        S2 = m.S2[level][at];
+    }
+    ts.lane_merges += (unsigned long long)finish_packed(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum,
+                                                      dcnt);
 }
 
 __global__ __launch_bounds__(256) void k_integrate_depth(DevMap m, DepthFrame f, const float* __restrict__ depth) {
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t nb0 = m.ctr->n_blocks;
-    const uint32_t nb = nb0 < m.max_blocks ? nb0 : m.max_blocks;
-    for (uint32_t id = wave; id < nb; id += nwaves) {
-        const uint32_t info = m.binfo[id];
-        if (info & kNoBlockBit) continue;
-        int32_t bx, by, bz;
-        unpack_key(m.bkey[id], bx, by, bz);
-        if (!(info & kNewBit) && !block_visible(m, f, bx, by, bz)) continue;
-        const int level = (int)((info >> kLevelShift) & 3u);
-        if (level == 0) integrate_fine_block(m, f, depth, id, bx, by, bz, info);
-        else integrate_coarse_block(m, f, depth, id, bx, by, bz, info, level);
+    const uint32_t n0 = m.ctr->vis_n[0], n1 = m.ctr->vis_n[1], n2 = m.ctr->vis_n[2], n3 = m.ctr->vis_n[3];
+    const uint32_t g2 = (n2 + 7) / 8, g3 = (n3 + 63) / 64;
+    const uint32_t ntask = n0 + n1 + g2 + g3;
+    TaskStats ts;
+    for (uint32_t t = wave; t < ntask; t += nwaves) {
+        if (t < n0) integrate_fine_block(m, f, depth, m.vis[0][t], ts);
+        else if (t < n0 + n1) integrate_level1_block(m, f, depth, m.vis[1][t - n0], ts);
+        else if (t < n0 + n1 + g2) integrate_packed_blocks(m, f, depth, m.vis[2], n2, t - n0 - n1, 2, ts);
+        else integrate_packed_blocks(m, f, depth, m.vis[3], n3, t - n0 - n1 - g2, 3, ts);
+    }
+    const unsigned long long lane_obs = wave_sum(ts.lane_obs), lane_merges = wave_sum(ts.lane_merges);
+    if (lane_id() == 0) {
+        stat_add(m, S_OBS, ts.obs + lane_obs);
+        stat_add(m, S_OBS_FRESH, ts.fresh);
+        stat_add(m, S_MERGE0, ts.merges[0]);
+        stat_add(m, S_MERGE1, ts.merges[1]);
+        stat_add(m, S_MERGE2, lane_merges);
     }
 }
 
@@ -272,11 +375,14 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
         for (double yy : {lo_y, hi_y}) lam = std::max(lam, std::sqrt(1.0 + xx * xx + yy * yy));
     f.cull_range = lam * (map->cfg.max_depth + map->cfg.tau) * (1.0 + 1e-9) + 1e-6;
 
-    dim3 ga((width + 15) / 16, (height + 15) / 16);
-    launch(map, K_ALLOC_DEPTH,
-           [&] { hipLaunchKernelGGL(k_alloc_depth, ga, dim3(256), 0, map->stream, map->dm, f, depth_dev); });
+    const uint32_t tiles_x = (uint32_t)(width + 15) / 16, tiles = tiles_x * (uint32_t)((height + 15) / 16);
+    const uint32_t cull_groups = 128;
+    launch(map, K_ALLOC_DEPTH, [&] {
+        hipLaunchKernelGGL(k_alloc_depth, dim3(tiles + cull_groups), dim3(256), 0, map->stream, map->dm, f, depth_dev,
+                           tiles_x, tiles);
+    });
     launch(map, K_INTEGRATE_DEPTH, [&] {
-        hipLaunchKernelGGL(k_integrate_depth, dim3(2048), dim3(256), 0, map->stream, map->dm, f, depth_dev);
+        hipLaunchKernelGGL(k_integrate_depth, dim3(1024), dim3(256), 0, map->stream, map->dm, f, depth_dev);
     });
     launch_finalize(map);
     return check_hip(map, hipGetLastError(), "integrate_depth");

@@ -50,8 +50,13 @@ __global__ void k_reset(DevMap m, uint32_t n_hash) {
         for (int n = 0; n < 4; ++n) {
             c->top[n] = n < m.levels ? m.heap_cap[n] : 0;
             c->pending[n] = 0;
+            c->vis_n[n] = 0;
         }
-        for (int s = 0; s < S_COUNT; ++s) c->frame[s] = c->last[s] = c->total[s] = 0;
+        c->n_prev = 0;
+        for (int s = 0; s < 16; ++s) {
+            c->last[s] = c->total[s] = 0;
+            for (int k = 0; k < kStripes; ++k) c->frame[k][s] = 0;
+        }
         c->frames = 0;
     }
 }
@@ -72,12 +77,19 @@ __global__ void k_finalize(DevMap m) {
         __syncthreads();
     }
     if (threadIdx.x < S_COUNT) {
-        const unsigned long long v = c->frame[threadIdx.x];
+        unsigned long long v = 0;
+        for (int k = 0; k < kStripes; ++k) {
+            v += c->frame[k][threadIdx.x];
+            c->frame[k][threadIdx.x] = 0;
+        }
         c->last[threadIdx.x] = v;
         c->total[threadIdx.x] += v;
-        c->frame[threadIdx.x] = 0;
     }
-    if (threadIdx.x == 0) c->frames += 1;
+    if (threadIdx.x == 0) {
+        c->frames += 1;
+        for (int n = 0; n < 4; ++n) c->vis_n[n] = 0;
+        c->n_prev = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
+    }
 }
 
 // Copy blocks out: keys, levels and (optionally) voxels converted from Morton to x-fastest order.
@@ -135,6 +147,8 @@ static void free_all(mrh_map* m) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);
+    for (int n = 0; n < 4; ++n)
+        if (d.vis[n]) (void)hipFree(d.vis[n]);
     for (int n = 0; n < 4; ++n) {
         void* lp[] = {d.stack[n], d.pend[n], d.D[n], d.W[n], d.S2[n], d.acc_sat[n], d.acc_band[n], d.acc_s1[n], d.acc_s2[n]};
         for (void* p : lp)
@@ -196,6 +210,7 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     alloc((void**)&d.bvsum, nb * 8, "block variance sums");
     alloc((void**)&d.bvcnt, nb * 4, "block variance counts");
     alloc((void**)&m->ctr, sizeof(DevCounters), "counters");
+    for (int n = 0; n < c.levels; ++n) alloc((void**)&d.vis[n], nb * 4, "visible-block lists");
     for (int n = 0; n < c.levels; ++n) {
         const int64_t cap = c.heap_blocks[n] > 0 ? c.heap_blocks[n] : c.max_blocks;
         d.heap_cap[n] = (int32_t)cap;

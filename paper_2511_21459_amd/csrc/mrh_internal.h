@@ -33,15 +33,22 @@ constexpr uint32_t kErrTableFull = 1u, kErrHeapFull = 2u, kErrBlockLimit = 4u;
 // per-frame statistics slots (u64)
 enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, S_MERGE3, S_FAILED, S_OBS_FRESH, S_COUNT };
 
+// Per-frame statistics are accumulated in kStripes cache-line-sized stripes (a workgroup adds to
+// the stripe of its index) so that atomics from different workgroups rarely meet on one line; the
+// end-of-frame kernel sums the stripes.
+constexpr int kStripes = 32;
+
 struct DevCounters {
     uint32_t n_blocks;
     uint32_t error_flags;
     int32_t top[4];
     uint32_t pending[4];
-    uint32_t pad[6];
-    unsigned long long frame[S_COUNT];
-    unsigned long long last[S_COUNT];
-    unsigned long long total[S_COUNT];
+    uint32_t vis_n[4];   // blocks queued for the projective update this frame, per level
+    uint32_t n_prev;     // blocks that existed when the frame started
+    uint32_t pad[13];
+    unsigned long long frame[kStripes][16];
+    unsigned long long last[16];
+    unsigned long long total[16];
     unsigned long long frames;
 };
 
@@ -72,6 +79,7 @@ struct DevMap {
     unsigned long long* acc_s1[4];
     unsigned long long* acc_s2[4];
     uint32_t* btouch;  // per block: touched by a ray this frame
+    uint32_t* vis[4];  // per level: ids of the blocks the projective update visits this frame
     double B, invB;
     double nu[4], inv_nu[4];
     double tau, var_thr;
@@ -184,6 +192,16 @@ __device__ inline int wave_sum(int v) {
     return v;
 }
 
+__device__ inline unsigned long long wave_sum(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
+    return v;
+}
+
+// add to a per-frame statistic (striped by workgroup)
+__device__ inline void stat_add(const DevMap& m, int s, unsigned long long v) {
+    if (v) atomicAdd(&m.ctr->frame[(blockIdx.x + 7u * blockIdx.y) % kStripes][s], v);
+}
+
 // Morton (Z-order) position of voxel (i, j, k) inside a block of side 8 >> level, x lowest bit.
 __host__ __device__ inline int morton3(int i, int j, int k) {
     int p = 0;
@@ -228,46 +246,66 @@ __device__ inline bool segment_in_range(const double a[3], const double e[3], do
 // Amanatides-Woo walk over unit cells of a lattice scaled by inv_cell: half-open cells, start in
 // the cell of a, step across the nearest boundary (lowest axis on ties), stop past e.  Boundary
 // parameters are recomputed from the cell index at every step.
+// One axis of a walk: position A (in cell units), cell c, step direction, inverse extent and the
+// parameter of the next boundary.
+__device__ inline void walk_axis(double a, double e, double inv_cell, double& A, int64_t& c, int& st, double& iD,
+                                 double& t, int64_t& guard) {
+    A = a * inv_cell;
+    const double E = e * inv_cell;
+    c = (int64_t)__builtin_floor(A);
+    const double dv = E - A;
+    const int64_t fe = (int64_t)__builtin_floor(E);
+    guard += fe > c ? fe - c : c - fe;
+    if (dv > 0.0) {
+        st = 1;
+        iD = 1.0 / dv;
+        t = ((double)(c + 1) - A) * iD;
+    } else if (dv < 0.0) {
+        st = -1;
+        iD = 1.0 / dv;
+        t = ((double)c - A) * iD;
+    } else {
+        st = 0;
+        iD = 0.0;
+        t = __builtin_inf();
+    }
+}
+
+// Amanatides-Woo walk over unit cells of a lattice scaled by inv_cell: half-open cells, start in
+// the cell of a, step across the nearest boundary (lowest axis on ties), stop past e.  Boundary
+// parameters are recomputed from the cell index at every step.  Kept in scalars (no indexed
+// arrays) so the walk state lives in registers.
 struct Walk {
-    double A[3], invD[3], tmax[3];
-    int64_t c[3];
-    int st[3];
+    double A0, A1, A2, iD0, iD1, iD2, t0, t1, t2;
+    int64_t c0, c1, c2;
+    int s0, s1, s2;
     int64_t guard;
 
     __device__ inline void init(const double a[3], const double e[3], double inv_cell) {
         guard = 3;
-        for (int k = 0; k < 3; ++k) {
-            A[k] = a[k] * inv_cell;
-            const double E = e[k] * inv_cell;
-            c[k] = (int64_t)__builtin_floor(A[k]);
-            const double dv = E - A[k];
-            const int64_t fe = (int64_t)__builtin_floor(E);
-            guard += fe > c[k] ? fe - c[k] : c[k] - fe;
-            if (dv > 0.0) {
-                st[k] = 1;
-                invD[k] = 1.0 / dv;
-                tmax[k] = ((double)(c[k] + 1) - A[k]) * invD[k];
-            } else if (dv < 0.0) {
-                st[k] = -1;
-                invD[k] = 1.0 / dv;
-                tmax[k] = ((double)c[k] - A[k]) * invD[k];
-            } else {
-                st[k] = 0;
-                invD[k] = 0.0;
-                tmax[k] = __builtin_inf();
-            }
-        }
+        walk_axis(a[0], e[0], inv_cell, A0, c0, s0, iD0, t0, guard);
+        walk_axis(a[1], e[1], inv_cell, A1, c1, s1, iD1, t1, guard);
+        walk_axis(a[2], e[2], inv_cell, A2, c2, s2, iD2, t2, guard);
     }
     // advance to the next cell; false once the walk is over
     __device__ inline bool next() {
         if (guard <= 0) return false;
         --guard;
+        double tm = t0;
         int k = 0;
-        if (tmax[1] < tmax[k]) k = 1;
-        if (tmax[2] < tmax[k]) k = 2;
-        if (!(tmax[k] <= 1.0)) return false;
-        c[k] += st[k];
-        tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - A[k]) * invD[k];
+        if (t1 < tm) tm = t1, k = 1;
+        if (t2 < tm) tm = t2, k = 2;
+        if (!(tm <= 1.0)) return false;
+        if (k == 0) {
+            c0 += s0;
+            t0 = ((double)(c0 + (s0 > 0 ? 1 : 0)) - A0) * iD0;
+        } else if (k == 1) {
+            c1 += s1;
+            t1 = ((double)(c1 + (s1 > 0 ? 1 : 0)) - A1) * iD1;
+        } else {
+            c2 += s2;
+            t2 = ((double)(c2 + (s2 > 0 ? 1 : 0)) - A2) * iD2;
+        }
         return true;
     }
 };

@@ -72,8 +72,8 @@ __device__ inline void store_group(const DevMap& m, size_t base, const float D[8
 
 // End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
 // sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
-// written back, have whether D/W/S2 hold the lane's current group.
-__device__ inline void finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
+// written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
+__device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
                                    bool have, bool dirty, int nupd, double dsum, int dcnt) {
     const int lane = lane_id();
     const uint32_t slot = info & kSlotMask;
@@ -96,7 +96,7 @@ __device__ inline void finish_fine(const DevMap& m, uint32_t id, uint32_t info, 
             m.bvcnt[id] = vcnt;
             if (info & kNewBit) m.binfo[id] = info & ~kNewBit;
         }
-        return;
+        return 0;
     }
     if (!have) load_group(m, base, D, W, S2);
     // pool the 8 children: total weight, weighted mean TSDF, summed S2
@@ -121,13 +121,13 @@ __device__ inline void finish_fine(const DevMap& m, uint32_t id, uint32_t info, 
         m.bvcnt[id] = (uint32_t)ccnt;
         m.binfo[id] = (uint32_t)cslot | (1u << kLevelShift);
         push_pending(m, 0, slot);
-        atomicAdd(&m.ctr->frame[S_MERGE0], 1ull);
     }
+    return 1;
 }
 
-// End of a level n >= 1 block's update (lane = Morton position; lanes >= the block's voxel count
-// hold W = 0).  The 8 children of a coarse voxel are 8 consecutive lanes.
-__device__ inline void finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
+// End of a level-1 block's update (lane = Morton position).  The 8 children of a coarse voxel are
+// 8 consecutive lanes.  Returns 1 when the block merged.
+__device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
                                      float S2, bool dirty, int nupd, double dsum, int dcnt) {
     const int lane = lane_id();
     const int side = 8 >> level, nv = side * side * side;
@@ -154,7 +154,7 @@ __device__ inline void finish_coarse(const DevMap& m, uint32_t id, uint32_t info
             m.bvsum[id] = vsum;
             m.bvcnt[id] = vcnt;
         }
-        return;
+        return 0;
     }
     uint32_t Wc = W;
     float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
@@ -179,15 +179,75 @@ __device__ inline void finish_coarse(const DevMap& m, uint32_t id, uint32_t info
         m.bvcnt[id] = (uint32_t)ccnt;
         m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
         push_pending(m, level, slot);
-        atomicAdd(&m.ctr->frame[S_MERGE0 + level], 1ull);
     }
+    return 1;
+}
+
+// Packed coarse blocks: `seg` consecutive lanes (8 for level 2, 1 for level 3) hold one block's
+// voxels, lane % seg = Morton position.  All reductions stay inside the segment.  Returns, on the
+// segment's first lane, 1 when its block merged.
+__device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uint32_t info, int level, int seg, float D,
+                                    uint32_t W, float S2, bool dirty, int nupd, double dsum, int dcnt) {
+    const int lane = lane_id();
+    for (int o = 1; o < seg; o <<= 1) {
+        dsum += __shfl_xor(dsum, o);
+        dcnt += __shfl_xor(dcnt, o);
+        nupd += __shfl_xor(nupd, o);
+    }
+    const bool leader = (lane % seg) == 0;
+    double vsum = 0.0;
+    uint32_t vcnt = 0;
+    if (live) {
+        vsum = m.bvsum[id] + dsum;
+        vcnt = m.bvcnt[id] + (uint32_t)dcnt;
+    }
+    bool merge = live && nupd > 0 && level < m.levels - 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
+    int64_t cslot = -1;
+    if (merge && leader) cslot = pop_slot(m, level + 1);
+    if (seg > 1) cslot = (int64_t)__shfl((long long)cslot, lane - (lane % seg));
+    merge = merge && cslot >= 0;
+    const uint32_t slot = info & kSlotMask;
+    if (!merge) {
+        if (live && dirty) {
+            const size_t at = (size_t)slot * seg + (lane % seg);
+            m.D[level][at] = D;
+            m.W[level][at] = W;
+            m.S2[level][at] = S2;
+        }
+        if (live && leader) {
+            m.bvsum[id] = vsum;
+            m.bvcnt[id] = vcnt;
+        }
+        return 0;
+    }
+    // only level 2 (seg = 8) can merge: pool the segment's 8 voxels into the single level-3 voxel
+    uint32_t Wc = W;
+    float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
+    for (int o = 1; o < seg; o <<= 1) {
+        Wc += (uint32_t)__shfl_xor((int)Wc, o);
+        sd += __shfl_xor(sd, o);
+        s2 += __shfl_xor(s2, o);
+    }
+    if (leader) {
+        const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+        const float Sc = Wc > 0 ? s2 : 0.f;
+        m.D[level + 1][cslot] = Dc;
+        m.W[level + 1][cslot] = Wc;
+        m.S2[level + 1][cslot] = Sc;
+        m.bvsum[id] = var_term(m, Wc, Sc);
+        m.bvcnt[id] = (uint32_t)var_count(m, Wc);
+        m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
+        push_pending(m, level, slot);
+        return 1;
+    }
+    return 0;
 }
 
 // Wave-cooperative insert of one key per lane (has_key).  Keys found by a read-only probe need
 // nothing; the missing ones are deduplicated across the wave (one leader per distinct key does
 // the CAS insert), and the new entries get block ids and level-0 heap slots from one atomic each
 // per wave, ranked by a ballot prefix count.
-__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key) {
+__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key, bool list_new) {
     const int lane = lane_id();
     uint32_t stop = kInvalidId;
     bool need = false;
@@ -206,7 +266,7 @@ __device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long 
                 is_new = true;
             } else if (r == INS_FULL) {
                 atomicOr(&m.ctr->error_flags, kErrTableFull);
-                atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
+                stat_add(m, S_FAILED, 1ull);
             }
         }
     }
@@ -220,32 +280,46 @@ __device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long 
         base = atomicAdd(&m.ctr->n_blocks, (uint32_t)cnt);
         top = atomicSub(&m.ctr->top[0], cnt);
         if (top < cnt) atomicAdd(&m.ctr->top[0], cnt - (top > 0 ? top : 0));  // undo the over-draw
-        atomicAdd(&m.ctr->frame[S_NEW], (unsigned long long)cnt);
+        stat_add(m, S_NEW, (unsigned long long)cnt);
     }
     base = (uint32_t)__shfl((int)base, first);
     top = __shfl(top, first);
-    if (!is_new) return;
     const int rank = rank_in_mask(newmask);
     const uint32_t id = base + (uint32_t)rank;
-    if (id >= m.max_blocks) {
-        m.hvals[slot] = kInvalidId;
-        atomicOr(&m.ctr->error_flags, kErrBlockLimit);
-        atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
-        return;
+    bool stored = false;
+    if (is_new) {
+        if (id >= m.max_blocks) {
+            m.hvals[slot] = kInvalidId;
+            atomicOr(&m.ctr->error_flags, kErrBlockLimit);
+            stat_add(m, S_FAILED, 1ull);
+        } else {
+            uint32_t info;
+            if (rank < top) {
+                info = m.stack[0][top - 1 - rank] | kNewBit;
+                stored = true;
+            } else {
+                info = kNoBlockBit;
+                atomicOr(&m.ctr->error_flags, kErrHeapFull);
+                stat_add(m, S_FAILED, 1ull);
+            }
+            m.bkey[id] = key;
+            m.binfo[id] = info;
+            m.bvsum[id] = 0.0;
+            m.bvcnt[id] = 0;
+            m.hvals[slot] = id;
+        }
     }
-    uint32_t info;
-    if (rank < top) {
-        info = m.stack[0][top - 1 - rank] | kNewBit;
-    } else {
-        info = kNoBlockBit;
-        atomicOr(&m.ctr->error_flags, kErrHeapFull);
-        atomicAdd(&m.ctr->frame[S_FAILED], 1ull);
+    if (list_new) {
+        // new blocks are always visited by this frame's projective update
+        const unsigned long long smask = __ballot(stored);
+        if (smask) {
+            const int f2 = __ffsll((long long)smask) - 1;
+            uint32_t vb = 0;
+            if (lane == f2) vb = atomicAdd(&m.ctr->vis_n[0], (uint32_t)__popcll(smask));
+            vb = (uint32_t)__shfl((int)vb, f2);
+            if (stored) m.vis[0][vb + rank_in_mask(smask)] = id;
+        }
     }
-    m.bkey[id] = key;
-    m.binfo[id] = info;
-    m.bvsum[id] = 0.0;
-    m.bvcnt[id] = 0;
-    m.hvals[slot] = id;
 }
 
 }  // namespace mrh

@@ -52,15 +52,15 @@ __global__ __launch_bounds__(256) void k_alloc_points(DevMap m, ScanParams sp, c
     bool in_range = ok && segment_in_range(a, e, m.invB);
     const unsigned long long dmask = __ballot(ok && !in_range);
     if (lane == 0) {
-        if (vmask) atomicAdd(&m.ctr->frame[S_VALID], (unsigned long long)__popcll(vmask));
-        if (dmask) atomicAdd(&m.ctr->frame[S_DROPPED], (unsigned long long)__popcll(dmask));
+        stat_add(m, S_VALID, (unsigned long long)__popcll(vmask));
+        stat_add(m, S_DROPPED, (unsigned long long)__popcll(dmask));
     }
     Walk w;
     if (in_range) w.init(a, e, m.invB);
     bool active = in_range;
     while (__ballot(active)) {
-        const unsigned long long key = active ? pack_key(w.c[0], w.c[1], w.c[2]) : 0ull;
-        insert_keys(m, active, key);
+        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
+        insert_keys(m, active, key, false);
         if (active) active = w.next();
     }
 }
@@ -78,6 +78,74 @@ __device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fr
     atomicAdd(&m.acc_s2[level][at], (unsigned long long)__builtin_rint((r * r) * kS2Scale));
 }
 
+// The block walk restricted to one block: the segment is clipped to the block's box, the walk
+// starts in the (clamped) cell of the clipped entry point and steps on the block's own lattice of
+// side^3 voxels until it leaves the block or passes the clipped exit parameter.
+struct BoxWalk {
+    double A0, A1, A2, iD0, iD1, iD2, t0, t1, t2, tout;
+    int c0, c1, c2, s0, s1, s2, side;
+
+    __device__ static inline void axis(double a, double e, double ob, double inv_nu, int side, double& A, double& D,
+                                       double& iD, int& st, double& tin, double& tout) {
+        A = (a - ob) * inv_nu;
+        const double El = (e - ob) * inv_nu;
+        D = El - A;
+        if (D != 0.0) {
+            iD = 1.0 / D;
+            const double nearb = D > 0.0 ? 0.0 : (double)side;
+            const double farb = D > 0.0 ? (double)side : 0.0;
+            const double ta = (nearb - A) * iD;
+            const double tb = (farb - A) * iD;
+            if (ta > tin) tin = ta;
+            if (tb < tout) tout = tb;
+            st = D > 0.0 ? 1 : -1;
+        } else {
+            iD = 0.0;
+            st = 0;
+        }
+    }
+    __device__ static inline void start(double A, double D, double iD, int st, double tin, int side, int& c, double& t) {
+        double fl = __builtin_floor(A + tin * D);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(side - 1)) fl = (double)(side - 1);
+        c = (int)fl;
+        t = st != 0 ? ((double)(c + (st > 0 ? 1 : 0)) - A) * iD : __builtin_inf();
+    }
+    __device__ inline void init(const double a[3], const double e[3], const int64_t b[3], double B, double inv_nu,
+                                int side_) {
+        side = side_;
+        double D0, D1, D2, tin = 0.0;
+        tout = 1.0;
+        axis(a[0], e[0], (double)b[0] * B, inv_nu, side, A0, D0, iD0, s0, tin, tout);
+        axis(a[1], e[1], (double)b[1] * B, inv_nu, side, A1, D1, iD1, s1, tin, tout);
+        axis(a[2], e[2], (double)b[2] * B, inv_nu, side, A2, D2, iD2, s2, tin, tout);
+        start(A0, D0, iD0, s0, tin, side, c0, t0);
+        start(A1, D1, iD1, s1, tin, side, c1, t1);
+        start(A2, D2, iD2, s2, tin, side, c2, t2);
+    }
+    __device__ inline bool next() {
+        double tm = t0;
+        int k = 0;
+        if (t1 < tm) tm = t1, k = 1;
+        if (t2 < tm) tm = t2, k = 2;
+        if (!(tm <= tout)) return false;
+        if (k == 0) {
+            c0 += s0;
+            if (c0 < 0 || c0 >= side) return false;
+            t0 = ((double)(c0 + (s0 > 0 ? 1 : 0)) - A0) * iD0;
+        } else if (k == 1) {
+            c1 += s1;
+            if (c1 < 0 || c1 >= side) return false;
+            t1 = ((double)(c1 + (s1 > 0 ? 1 : 0)) - A1) * iD1;
+        } else {
+            c2 += s2;
+            if (c2 < 0 || c2 >= side) return false;
+            t2 = ((double)(c2 + (s2 > 0 ? 1 : 0)) - A2) * iD2;
+        }
+        return true;
+    }
+};
+
 __global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp, const float* __restrict__ xyz, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double a[3], e[3], p[3], nn[3];
@@ -85,7 +153,7 @@ __global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp, const flo
     Walk w;
     w.init(a, e, m.invB);
     do {
-        const int64_t b[3] = {w.c[0], w.c[1], w.c[2]};
+        const int64_t b[3] = {w.c0, w.c1, w.c2};
         const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
         if (id == kInvalidId) continue;
         const uint32_t info = m.binfo[id];
@@ -95,53 +163,18 @@ __global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp, const flo
         const bool fresh = (info & kNewBit) != 0;
         const int side = 8 >> level;
         const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
-        const double inv_nu = m.inv_nu[level], nu = m.nu[level];
-        // the segment in the block's voxel units, clipped to the block's box
-        double Al[3], Dl[3], invD[3], tmax[3];
-        int st[3], c[3];
-        double tin = 0.0, tout = 1.0;
-        for (int k = 0; k < 3; ++k) {
-            const double ob = (double)b[k] * m.B;
-            Al[k] = (a[k] - ob) * inv_nu;
-            const double El = (e[k] - ob) * inv_nu;
-            Dl[k] = El - Al[k];
-            if (Dl[k] != 0.0) {
-                invD[k] = 1.0 / Dl[k];
-                const double nearb = Dl[k] > 0.0 ? 0.0 : (double)side;
-                const double farb = Dl[k] > 0.0 ? (double)side : 0.0;
-                const double t0 = (nearb - Al[k]) * invD[k];
-                const double t1 = (farb - Al[k]) * invD[k];
-                if (t0 > tin) tin = t0;
-                if (t1 < tout) tout = t1;
-                st[k] = Dl[k] > 0.0 ? 1 : -1;
-            } else {
-                invD[k] = 0.0;
-                st[k] = 0;
-            }
-        }
-        for (int k = 0; k < 3; ++k) {
-            double fl = __builtin_floor(Al[k] + tin * Dl[k]);
-            if (fl < 0.0) fl = 0.0;
-            if (fl > (double)(side - 1)) fl = (double)(side - 1);
-            c[k] = (int)fl;
-            tmax[k] = st[k] != 0 ? ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k] : __builtin_inf();
-        }
-        for (int s = 0; s <= 3 * side; ++s) {
+        const double nu = m.nu[level];
+        BoxWalk bw;
+        bw.init(a, e, b, m.B, m.inv_nu[level], side);
+        for (int s = 0;; ++s) {
             // observation of the voxel centre (Eq. 1)
-            const double x0 = (double)b[0] * m.B + ((double)c[0] + 0.5) * nu;
-            const double x1 = (double)b[1] * m.B + ((double)c[1] + 0.5) * nu;
-            const double x2 = (double)b[2] * m.B + ((double)c[2] + 0.5) * nu;
+            const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
+            const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
+            const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
             const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
             const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
-            accumulate(m, level, base + (size_t)morton3(c[0], c[1], c[2]), fresh, d);
-            if (s == 3 * side) break;
-            int k = 0;
-            if (tmax[1] < tmax[k]) k = 1;
-            if (tmax[2] < tmax[k]) k = 2;
-            if (!(tmax[k] <= tout)) break;
-            c[k] += st[k];
-            if (c[k] < 0 || c[k] >= side) break;
-            tmax[k] = ((double)(c[k] + (st[k] > 0 ? 1 : 0)) - Al[k]) * invD[k];
+            accumulate(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d);
+            if (s == 3 * side || !bw.next()) break;
         }
     } while (w.next());
 }
@@ -161,7 +194,12 @@ __device__ inline void apply_stats(const DevMap& m, uint32_t nsat, uint32_t nban
     W = W + nobs;
 }
 
-__device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info) {
+// Statistics gathered by one wave over its blocks (wave-uniform).
+struct ApplyStats {
+    unsigned long long obs = 0, fresh = 0, merges[3] = {0, 0, 0};
+};
+
+__device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info, ApplyStats& as) {
     const int lane = lane_id();
     const bool fresh = (info & kNewBit) != 0;
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
@@ -193,10 +231,8 @@ __device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info) {
         for (int q = 0; q < 8; ++q) s1[q] = s2[q] = 0ull;
     }
     const int wobs = wave_sum(nobs);
-    if (lane == 0 && wobs) {
-        atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)wobs);
-        if (fresh) atomicAdd(&m.ctr->frame[S_OBS_FRESH], (unsigned long long)wobs);
-    }
+    as.obs += (unsigned long long)wobs;
+    if (fresh) as.fresh += (unsigned long long)wobs;
     float D[8], S2[8];
     uint32_t W[8];
     bool have = false;
@@ -229,10 +265,11 @@ __device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info) {
             for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
         }
     }
-    finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
+    as.merges[0] += (unsigned long long)finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
 }
 
-__device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info, int level) {
+// A level >= 1 block, one voxel per lane (lanes beyond the block's voxel count idle).
+__device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, ApplyStats& as) {
     const int lane = lane_id();
     const int side = 8 >> level, nv = side * side * side;
     const size_t at = (size_t)(info & kSlotMask) * nv + lane;
@@ -244,7 +281,7 @@ __device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info,
     const bool upd = ns + nb > 0;
     const int wobs = wave_sum((int)(ns + nb));
     if (wobs == 0) return;
-    if (lane == 0) atomicAdd(&m.ctr->frame[S_OBS], (unsigned long long)wobs);
+    as.obs += (unsigned long long)wobs;
     float D = 0.f, S2 = 0.f;
     uint32_t W = 0;
     if (lane < nv) {
@@ -270,7 +307,14 @@ __device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info,
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    finish_coarse(m, id, info, level, D, W, S2, upd, wobs, dsum, dcnt);
+    if (level == 1) {
+        as.merges[1] += (unsigned long long)finish_coarse(m, id, info, level, D, W, S2, upd, wobs, dsum, dcnt);
+    } else {
+        const int seg = level == 2 ? 8 : 1;
+        // lanes beyond the block's voxels carry no state; only the first segment is live
+        const int merged = finish_packed(m, lane < seg, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum, dcnt);
+        as.merges[2] += (unsigned long long)__shfl(merged, 0);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_apply_points(DevMap m) {
@@ -278,14 +322,20 @@ __global__ __launch_bounds__(256) void k_apply_points(DevMap m) {
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t nb0 = m.ctr->n_blocks;
     const uint32_t nb = nb0 < m.max_blocks ? nb0 : m.max_blocks;
+    ApplyStats as;
     for (uint32_t id = wave; id < nb; id += nwaves) {
         if (m.btouch[id] == 0u) continue;
         const uint32_t info = m.binfo[id];
         if (lane_id() == 0) m.btouch[id] = 0u;
         if (info & kNoBlockBit) continue;
         const int level = (int)((info >> kLevelShift) & 3u);
-        if (level == 0) apply_fine(m, id, info);
-        else apply_coarse(m, id, info, level);
+        if (level == 0) apply_fine(m, id, info, as);
+        else apply_coarse(m, id, info, level, as);
+    }
+    if (lane_id() == 0) {
+        stat_add(m, S_OBS, as.obs);
+        stat_add(m, S_OBS_FRESH, as.fresh);
+        for (int n = 0; n < 3; ++n) stat_add(m, S_MERGE0 + n, as.merges[n]);
     }
 }
 

@@ -227,7 +227,7 @@ def test_capacity_errors(mrh):
     announce("table / heap / block capacity errors")
     depth, cam, T = sphere_plane_frame(seed=0)
     d = _dev(depth)
-    g = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=512, hash_slots=4096))
+    g = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=512, hash_slots=4096, heap_blocks=[4096, 0, 0, 0]))
     g.integrate_depth(d, cam.K, T)
     with pytest.raises(mrh.MrhError) as ei:
         g.sync()
