@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
-"""Fusion throughput on one MI355X: the 100-frame 640x480 RGB-D room sequence, 4 levels.
+"""Fusion throughput on one MI355X.
 
-A step is one pass of the whole fusion hot path over the sequence: reset the map, then for each of
-the 100 frames allocate, integrate (projective update, variance, merging criterion) and finish the
-frame.  The depth frames are resident in HBM before the timed region starts.
+Headline (`value`): the 100-frame 640x480 RGB-D room sequence, 4 levels, FP32 state.  A step is one
+pass of the whole fusion hot path over the sequence: reset the map, then for each of the 100 frames
+allocate, integrate (projective update, variance, merging criterion) and finish the frame.  The
+depth frames are resident in HBM before the timed region starts.
 
-Prints ONE JSON line: metric / value (M valid points fused per second) plus G voxel updates/s, the
-roofline of the dominant kernel (projective update) measured with HIP events on the library's
-stream, and the CPU oracle's throughput on a bounded sample of the same workload.
+Also reported on the same JSON line:
+  * G voxel updates/s, and the roofline of the dominant kernel (projective update) measured with HIP
+    events on the library's stream;
+  * `precision`: the same sequence with FP16 / BF16 state, speed-up and |dD| against the FP32 map;
+  * `batched`: 16 independent streams (8 RGB-D 320x240..640x480, 8 LiDAR 32x1024..64x2048), 20
+    launches, fused by the batched FP16 graph path against plain FP32 per-map calls;
+  * `query`: 1M trilinear queries near the room's surfaces, forward and adjoint;
+  * `cpu_baseline`: the FP64 oracle on a bounded sample of the headline workload.
 """
 import argparse
 import json
@@ -19,15 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STATE_BYTES = 12  # FP32 D + uint32 W + FP32 S2 per voxel
+STATE_BYTES = {"f32": 12, "f16": 6, "bf16": 6}
 
 
-def algorithmic_bytes_integrate(frames, width, height):
+def algorithmic_bytes_integrate(frames, width, height, s=12):
     """Bytes the projective-update kernel must move for the census of one sequence (lower bound):
     read + write of each updated voxel of an existing block, the full zero-initialised write of
     each new block, one read of each depth pixel, the block-table scan (key + info, 12 B per
     allocated block per frame) and the pooled read/write of merged blocks."""
-    s = STATE_BYTES
     total = 0
     for f in frames:
         upd_old = f["observations"] - f["fresh_observations"]
@@ -40,41 +45,55 @@ def algorithmic_bytes_integrate(frames, width, height):
     return total
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--cpu-frames", type=int, default=40, help="oracle sample: first N frames")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the fusion of one map runs "
-              "on one device; see the sharding notes in the design document)", file=sys.stderr)
-        sys.exit(2)
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
 
+
+def compare_maps(a, b):
+    """max / RMS |dD| over observed voxels of blocks present in both maps at the same level."""
     import numpy as np
-    import torch
 
-    import paper_2511_21459_amd as mrh
-    from workloads import configs, room_sequence
+    ea, eb = a.extract(), b.extract()
+    out = []
+    for e in (ea, eb):
+        k = e["keys"].cpu().numpy().astype(np.int64)
+        code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
+        out.append((code, e["levels"].cpu().numpy(), e["offsets"].cpu().numpy(), e["D"].cpu().numpy(),
+                    e["W"].cpu().numpy()))
+    (ca, la, oa, Da, Wa), (cb, lb, ob, Db, Wb) = out
+    common, ia, ib = np.intersect1d(ca, cb, return_indices=True)
+    same = la[ia] == lb[ib]
+    ia, ib = ia[same], ib[same]
+    sa = np.concatenate([np.arange(oa[i], oa[i + 1]) for i in ia]) if len(ia) else np.zeros(0, int)
+    sb = np.concatenate([np.arange(ob[i], ob[i + 1]) for i in ib]) if len(ib) else np.zeros(0, int)
+    obs = (Wa[sa] > 0) & (Wb[sb] > 0)
+    d = np.abs(Da[sa] - Db[sb])[obs].astype(np.float64)
+    return {"blocks_compared": int(len(ia)), "blocks_level_differs": int((~same).sum()),
+            "max_abs_dD_m": float(d.max()) if d.size else 0.0,
+            "rms_dD_m": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    depths, cam, poses, _ = room_sequence(n_frames=100, frames=range(args.frames))
+
+def run_room(args, torch, np, mrh, configs, room_sequence):
+    depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
+    poses = np.ascontiguousarray(poses)
     H, W = depths.shape[1:]
     dev = torch.from_numpy(depths).cuda()
     frames = [dev[k] for k in range(args.frames)]
     torch.cuda.synchronize()
 
+    def make_step(fmap):
+        def step():
+            fmap.reset()
+            fmap.integrate_depth_sequence(dev, cam.K, poses)
+        return step
+
     fmap = mrh.Map(**configs.ROOM)
-
-    def step():
-        fmap.reset()
-        for k in range(args.frames):
-            fmap.integrate_depth(frames[k], cam.K, poses[k])
-
+    step = make_step(fmap)
     # census: per-frame statistics of one pass (the workload is deterministic)
     fmap.reset()
     census = []
@@ -82,13 +101,9 @@ def main():
         fmap.integrate_depth(frames[k], cam.K, poses[k])
         last, _ = fmap.sync()
         census.append(last)
-    valid_points = sum(f["valid_points"] for f in census)
-    updates = sum(f["observations"] for f in census)
-
     for _ in range(args.warmup):
         step()
     fmap.sync()
-
     # timed region A: throughput (no profiling events)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -99,11 +114,9 @@ def main():
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    wall = (time.perf_counter() - t0) / args.steps
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
     _, tot = fmap.sync()
-    ms_per_step = wall * 1e3 / args.steps
-
     # timed region B: the same steps with every launch bracketed by events on the map's stream
     fmap.profile(True)
     torch.cuda.synchronize()
@@ -114,16 +127,171 @@ def main():
     k_ms, k_launches = prof["integrate_depth"]
     avg_launch_s = k_ms / k_launches / 1e3
     bytes_per_launch = algorithmic_bytes_integrate(census, W, H) / args.frames
-    achieved = bytes_per_launch / avg_launch_s / 1e9
 
+    # precision variants of the same sequence
+    precision = {}
+    for st in ("f16", "bf16"):
+        pm = mrh.Map(**dict(configs.ROOM, storage=st))
+        pstep = make_step(pm)
+        pstep()
+        t = timed(pstep, args.steps, torch)
+        acc = compare_maps(pm, fmap)  # both hold the whole sequence
+        precision[st] = dict(m_points_per_s=round(sum(f["valid_points"] for f in census) / t / 1e6, 3),
+                             ms_per_step=round(t * 1e3, 3), speedup_vs_f32=round(wall / t, 3),
+                             state_bytes_per_voxel=STATE_BYTES[st], **acc)
+        pm.close()
+    return dict(depths=depths, cam=cam, poses=poses, scene=scene, W=W, H=H, census=census, wall=wall,
+                gpu_ms=gpu_ms, prof=prof, avg_launch_s=avg_launch_s, bytes_per_launch=bytes_per_launch,
+                tot=tot, precision=precision, fmap=fmap)
+
+
+RGBD_STREAMS = [(320, 240), (384, 288), (416, 312), (480, 360), (512, 384), (560, 420), (608, 456), (640, 480)]
+LIDAR_STREAMS = [(32, 1024), (32, 2048), (40, 1024), (48, 1536), (48, 2048), (56, 1792), (64, 1024), (64, 2048)]
+
+
+def run_batched(args, torch, np, mrh, configs):
+    from workloads import room_sequence, street_sequence
+
+    L = args.launches
+    streams = []
+    for i, (w, h) in enumerate(RGBD_STREAMS):
+        d, cam, P, _ = room_sequence(width=w, height=h, f=525.0 * w / 640.0, frames=range(L), scene_seed=100 + i,
+                                     noise_seed=200 + i)
+        streams.append(("depth", torch.from_numpy(d).cuda(), cam.K, P, dict(configs.ROOM, max_blocks=1 << 17,
+                                                                               hash_slots=1 << 18)))
+    for i, (r, a) in enumerate(LIDAR_STREAMS):
+        p, P, _ = street_sequence(rings=r, azimuths=a, scans=range(L), scene_seed=108 + i, noise_seed=208 + i)
+        nb = 1 << 20
+        streams.append(("points", torch.from_numpy(p).cuda(), None, P,
+                        dict(configs.STREET, max_blocks=nb, hash_slots=2 * nb, heap_blocks=[nb // 2, nb // 2, nb // 2, nb])))
+    torch.cuda.synchronize()
+
+    def frame(s, k):
+        kind, data, K, P, _ = s
+        return ("depth", data[k], K, P[k]) if kind == "depth" else ("points", data[k], P[k])
+
+    # plain FP32, one map at a time
+    seq_maps = [mrh.Map(**s[4]) for s in streams]
+
+    def seq_step():
+        for m in seq_maps:
+            m.reset()
+        for k in range(L):
+            for s, m in zip(streams, seq_maps):
+                fr = frame(s, k)
+                if fr[0] == "depth":
+                    m.integrate_depth(fr[1], fr[2], fr[3])
+                else:
+                    m.integrate_points(fr[1], fr[2])
+
+    seq_step()
+    t_seq = timed(seq_step, 1, torch)
+    pts = 0
+    for m in seq_maps:
+        _, tot = m.sync()
+        pts += tot["valid_points"]
+    # batched FP16 graph path, launch shape from the autotuner
+    b_maps = [mrh.Map(**dict(s[4], storage="f16")) for s in streams]
+    batch = mrh.Batch(b_maps)
+    best = batch.autotune([frame(s, 0) for s in streams], reps=2)
+
+    def batch_step():
+        for m in b_maps:
+            m.reset()
+        for k in range(L):
+            batch.integrate([frame(s, k) for s in streams])
+
+    batch_step()
+    t_b = timed(batch_step, 1, torch)
+    accs = [compare_maps(bm, sm) for bm, sm in zip(b_maps, seq_maps)]
+    batch.close()
+    for m in b_maps + seq_maps:
+        m.close()
+    # batched FP32 (same graph path) to separate the two effects
+    b32_maps = [mrh.Map(**s[4]) for s in streams]
+    batch32 = mrh.Batch(b32_maps)
+    batch32.set_launch(*best)
+
+    def batch32_step():
+        for m in b32_maps:
+            m.reset()
+        for k in range(L):
+            batch32.integrate([frame(s, k) for s in streams])
+
+    batch32_step()
+    t_b32 = timed(batch32_step, 1, torch)
+    batch32.close()
+    for m in b32_maps:
+        m.close()
+    return {"streams": len(streams), "launches": L, "valid_points_per_pass": pts,
+            "sequential_f32_ms": round(t_seq * 1e3, 3), "batched_f32_ms": round(t_b32 * 1e3, 3),
+            "batched_f16_ms": round(t_b * 1e3, 3),
+            "sequential_f32_m_points_per_s": round(pts / t_seq / 1e6, 3),
+            "batched_f16_m_points_per_s": round(pts / t_b / 1e6, 3),
+            "speedup_batched_f16_vs_sequential_f32": round(t_seq / t_b, 3),
+            "speedup_batched_f32_vs_sequential_f32": round(t_seq / t_b32, 3),
+            "autotuned_launch": list(best),
+            "f16_vs_f32_max_abs_dD_m": max(a["max_abs_dD_m"] for a in accs),
+            "f16_vs_f32_rms_dD_m": float(np.sqrt(np.mean([a["rms_dD_m"] ** 2 for a in accs]))),
+            "blocks_level_differs": sum(a["blocks_level_differs"] for a in accs)}
+
+
+def run_query(room, torch, np, mrh):
+    from workloads import surface_query_points
+
+    fmap = room["fmap"]
+    pts = torch.from_numpy(surface_query_points(room["scene"], 1_000_000, sigma=0.015, seed=100)).cuda()
+    gs = torch.ones(pts.shape[0], device="cuda")
+    T = np.eye(4)
+    T[:3, 3] = [0.01, -0.01, 0.005]
+    fmap.query(pts, T=T)
+    t_f = timed(lambda: fmap.query(pts, T=T), 5, torch)
+    fmap.query_backward(pts, gs, T=T)
+    t_b = timed(lambda: fmap.query_backward(pts, gs, T=T), 5, torch)
+    _, valid, _ = fmap.query(pts, T=T)
+    return {"points": int(pts.shape[0]), "valid_frac": round(float(valid.float().mean()), 4),
+            "forward_m_queries_per_s": round(pts.shape[0] / t_f / 1e6, 1),
+            "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--launches", type=int, default=20, help="batched workload: frames per stream")
+    ap.add_argument("--cpu-frames", type=int, default=40, help="oracle sample: first N frames")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the fusion of one map runs "
+              "on one device; the sharding plan is documented, not measured)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2511_21459_amd as mrh
+    from workloads import configs, room_sequence
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    room = run_room(args, torch, np, mrh, configs, room_sequence)
+    census, wall, prof = room["census"], room["wall"], room["prof"]
+    valid_points = sum(f["valid_points"] for f in census)
+    updates = sum(f["observations"] for f in census)
+    achieved = room["bytes_per_launch"] / room["avg_launch_s"] / 1e9
+    W, H = room["W"], room["H"]
     result = {
         "metric": "M points/s fused + G voxel-updates/s; batched/FP16 vs plain FP32 fusion",
-        "value": round(valid_points * args.steps / wall / 1e6, 3),
+        "value": round(valid_points / wall / 1e6, 3),
         "unit": "M points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(wall * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -133,17 +301,21 @@ def main():
                    "frames_per_step": args.frames, "valid_points_per_step": valid_points,
                    "voxel_updates_per_step": updates, "blocks_at_end": census[-1]["blocks"],
                    "merges_per_step": [sum(f["merges"][n] for f in census) for n in range(4)]},
-        "g_voxel_updates_per_s": round(updates * args.steps / wall / 1e9, 4),
-        "gpu_event_ms_per_step": round(gpu_ms / args.steps, 3),
+        "g_voxel_updates_per_s": round(updates / wall / 1e9, 4),
+        "gpu_event_ms_per_step": round(room["gpu_ms"], 3),
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "roofline": {"kernel": "k_integrate_depth", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(bytes_per_launch),
-                     "avg_launch_us": round(avg_launch_s * 1e6, 3)},
+                     "traffic": None, "bytes_per_launch": int(room["bytes_per_launch"]),
+                     "avg_launch_us": round(room["avg_launch_s"] * 1e6, 3)},
+        "precision": room["precision"],
         "cpu_baseline": None,
     }
-    if tot["error_flags"]:
-        result["errors"] = tot["error_flags"]
+    if room["tot"]["error_flags"]:
+        result["errors"] = room["tot"]["error_flags"]
+    if not args.no_extras:
+        result["batched"] = run_batched(args, torch, np, mrh, configs)
+        result["query"] = run_query(room, torch, np, mrh)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -153,7 +325,7 @@ def main():
         t0 = time.perf_counter()
         pts = 0
         for k in range(n):
-            pts += o.integrate_depth(depths[k], cam.K, poses[k])["valid_points"]
+            pts += o.integrate_depth(room["depths"][k], room["cam"].K, room["poses"][k])["valid_points"]
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(pts / dt / 1e6, 4), "unit": "M points/s", "cores": 1,
                                   "kind": "oracle",

@@ -128,6 +128,18 @@ mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t wid
  * block's level, receives clip((p - x) . n, -tau, tau).  Asynchronous. */
 mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, int64_t n, const double T_ws[16]);
 
+/* Fuse a recorded sequence: frames f = 0 .. n_frames-1 in order, exactly as n_frames calls of
+ * mrh_integrate_depth (the frame loop runs in the library, not in the caller).
+ *   depth_dev: device float32[n_frames][height][width];  T_ws: host double[n_frames][16].
+ * Asynchronous.  Errors as mrh_integrate_depth; on a bad pose nothing is enqueued. */
+mrh_status mrh_integrate_depth_sequence(mrh_map* map, const float* depth_dev, int32_t n_frames, int32_t width,
+                                        int32_t height, const double K[4], const double* T_ws);
+
+/* The same for LiDAR: xyz_dev device float32[n_frames][n][3] (n points per scan, NaN padding
+ * allowed), T_ws host double[n_frames][16]. */
+mrh_status mrh_integrate_points_sequence(mrh_map* map, const float* xyz_dev, int32_t n_frames, int64_t n,
+                                         const double* T_ws);
+
 /* Wait for the map's stream, then report.  last / totals may be NULL.  Returns the first latched
  * capacity error (MRH_ERR_TABLE_FULL, MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT) or MRH_OK, and
  * clears the latch. */
@@ -175,7 +187,12 @@ enum {
     MRH_KERNEL_QUERY = 7,
     MRH_KERNEL_QUERY_BACKWARD = 8,
     MRH_KERNEL_REDUCE = 9,
-    MRH_KERNEL_COUNT = 10
+    MRH_KERNEL_BATCH_ALLOC = 10,    /* batched: allocation + cull of every map */
+    MRH_KERNEL_BATCH_RAYS = 11,     /* batched: LiDAR traversal of every map */
+    MRH_KERNEL_BATCH_UPDATE = 12,   /* batched: update tasks of every map */
+    MRH_KERNEL_BATCH_FINALIZE = 13, /* batched: end of frame of every map */
+    MRH_KERNEL_BATCH_GRAPH = 14,    /* batched: one replay of the captured step */
+    MRH_KERNEL_COUNT = 15
 };
 
 /* Launch profiler (measurement support, not part of the method).  With on != 0 every kernel the
@@ -185,6 +202,45 @@ enum {
  * int64[n_kernels]) since the last collect, then recycles the events. */
 mrh_status mrh_profile_enable(mrh_map* map, int32_t on);
 mrh_status mrh_profile_collect(mrh_map* map, double* ms, int64_t* launches, int32_t n_kernels);
+
+/* ---- Batched fusion of many independent maps ------------------------------------------------
+ * One call fuses one frame into each map of the batch with four launches in total (allocation and
+ * culling, LiDAR traversal, update, end of frame), each covering every map; the four launches are
+ * captured once into a HIP graph and replayed on later calls with the same frame sizes.  Per-map
+ * results are identical to calling mrh_integrate_depth / mrh_integrate_points map by map. */
+
+enum { MRH_FRAME_NONE = 0, MRH_FRAME_DEPTH = 1, MRH_FRAME_POINTS = 2 };
+
+typedef struct mrh_frame {
+    int32_t kind;          /* MRH_FRAME_* (NONE leaves the map untouched this call) */
+    int32_t width, height; /* DEPTH: image size */
+    const float* data_dev; /* DEPTH: float32[height][width] z-depth (m); POINTS: float32[n][3] */
+    int64_t n;             /* POINTS: number of points */
+    double K[4];           /* DEPTH: fx, fy, cx, cy */
+    double T_ws[16];       /* row-major world-from-sensor transform */
+} mrh_frame;
+
+typedef struct mrh_batch mrh_batch;
+
+/* Group n_maps maps (same device, same storage format) into a batch.  The batch enqueues on
+ * maps[0]'s stream; the maps must not be used on other streams while a batched call runs.  The
+ * batch keeps the map pointers (the maps must outlive it).  Errors: MRH_ERR_INVALID_ARG. */
+mrh_status mrh_batch_create(mrh_map* const* maps, int32_t n_maps, mrh_batch** out);
+void mrh_batch_destroy(mrh_batch* batch);
+
+/* Fuse frames[i] into map i for every i (host array of n_maps descriptors; device data).
+ * Asynchronous.  Errors: MRH_ERR_INVALID_ARG (bad descriptor), MRH_ERR_HIP. */
+mrh_status mrh_batch_integrate(mrh_batch* batch, const mrh_frame* frames);
+
+/* Launch shape of the batched kernels: params[0] = workgroups of the update launch, params[1] =
+ * cull workgroups per depth map, params[2] = 1 to replay a captured graph, 0 to launch directly. */
+mrh_status mrh_batch_set_launch(mrh_batch* batch, const int32_t params[3]);
+mrh_status mrh_batch_get_launch(const mrh_batch* batch, int32_t params[3]);
+
+/* Autotuner: for every candidate launch shape, reset all maps and time `reps` calls of
+ * mrh_batch_integrate(frames) with HIP events; keep the fastest shape (written to best[3]) and
+ * leave every map reset.  Meant for start-up, before the real stream of frames. */
+mrh_status mrh_batch_autotune(mrh_batch* batch, const mrh_frame* frames, int32_t reps, int32_t best[3]);
 
 /* Text of the last error on this map (never NULL; "" when none). */
 const char* mrh_last_error(const mrh_map* map);

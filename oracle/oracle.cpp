@@ -284,10 +284,8 @@ void variance_and_merge(Map& m) {
         if (cnt == 0) continue;
         const double mv = sum / (double)cnt;
         const double margin = std::fabs(mv - thr) / thr;
-        if (margin < 1e-3) {
-            m.near.push_back({kv.first, m.frame, margin});
-            m.last.near_threshold++;
-        }
+        if (margin < 5e-2) m.near.push_back({kv.first, m.frame, margin});
+        if (margin < 1e-3) m.last.near_threshold++;
         if (mv < thr) {
             m.last.merges[blk.level]++;
             merge_block(m, blk);

@@ -59,8 +59,9 @@ int64_t orc_num_voxels(const void* map);
 void orc_extract(const void* map, int32_t* keys, uint8_t* levels, int64_t* offsets,
                  double* D, uint32_t* W, double* S2);
 
-/* Merge decisions taken within 1e-3 relative of the threshold so far: per event the block key,
- * the frame index and the relative margin.  Returns the total count; fills at most cap. */
+/* Merge decisions taken within 5e-2 relative of the threshold so far: per event the block key,
+ * the frame index and the relative margin |mv - thr| / thr.  Returns the total count; fills at
+ * most cap. */
 int64_t orc_near_threshold(const void* map, int32_t* keys, int64_t* frames, double* margins,
                            int64_t cap);
 

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import FORM, STORAGE, MrhConfig, MrhError, MrhStats
 
-__all__ = ["Map", "SdfQuery", "block_hash", "MrhError"]
+__all__ = ["Map", "Batch", "SdfQuery", "block_hash", "MrhError"]
 
 
 def _host_doubles(a, n):
@@ -113,6 +113,26 @@ class Map:
         Ta, Tp = _host_doubles(T_ws, 16)
         self._check(_lib.load().mrh_integrate_points(self._h, p, xyz.shape[0], Tp), "mrh_integrate_points")
 
+    def integrate_depth_sequence(self, depths: torch.Tensor, K, poses):
+        """Fuse frames depths[0..F-1] (float32 [F, H, W] on the GPU) with poses [F, 4, 4] in order;
+        the frame loop runs inside the library."""
+        if depths.dim() != 3:
+            raise ValueError("depths must be [F, H, W]")
+        p = _dev(depths, torch.float32, name="depths")
+        Ka, Kp = _host_doubles(K, 4)
+        Pa, Pp = _host_doubles(poses, 16 * depths.shape[0])
+        self._check(_lib.load().mrh_integrate_depth_sequence(self._h, p, depths.shape[0], depths.shape[2],
+                                                             depths.shape[1], Kp, Pp), "mrh_integrate_depth_sequence")
+
+    def integrate_points_sequence(self, xyz: torch.Tensor, poses):
+        """Fuse scans xyz[0..F-1] (float32 [F, N, 3] on the GPU) with poses [F, 4, 4] in order."""
+        if xyz.dim() != 3 or xyz.shape[2] != 3:
+            raise ValueError("xyz must be [F, N, 3]")
+        p = _dev(xyz, torch.float32, name="xyz")
+        Pa, Pp = _host_doubles(poses, 16 * xyz.shape[0])
+        self._check(_lib.load().mrh_integrate_points_sequence(self._h, p, xyz.shape[0], xyz.shape[1], Pp),
+                    "mrh_integrate_points_sequence")
+
     def sync(self):
         """Wait for the map's stream; return (last-frame stats, totals); raise a latched error."""
         last, tot = MrhStats(), MrhStats()
@@ -196,6 +216,85 @@ class Map:
         self._check(_lib.load().mrh_extract_blocks(self._h, *args, nb, nv, ctypes.byref(a), ctypes.byref(b)),
                     "mrh_extract_blocks")
         return out
+
+
+class Batch:
+    """Many maps fused together: one frame per map per ``integrate`` call, four launches in total,
+    replayed from a captured HIP graph while the frame sizes stay the same."""
+
+    def __init__(self, maps):
+        self.maps = list(maps)
+        arr = (ctypes.c_void_p * len(self.maps))(*[m._h.value for m in self.maps])
+        h = ctypes.c_void_p()
+        st = _lib.load().mrh_batch_create(arr, len(self.maps), ctypes.byref(h))
+        if st != 0:
+            raise MrhError(st, "mrh_batch_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mrh_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _frames(self, frames):
+        """frames: one entry per map, ("depth", tensor [H, W], K, T), ("points", tensor [N, 3], T) or None."""
+        if len(frames) != len(self.maps):
+            raise ValueError("one frame per map")
+        arr = (_lib.MrhFrame * len(frames))()
+        for i, fr in enumerate(frames):
+            if fr is None:
+                arr[i].kind = _lib.FRAME_NONE
+                continue
+            T = np.asarray(fr[-1], dtype=np.float64).reshape(16)
+            for k in range(16):
+                arr[i].T_ws[k] = T[k]
+            if fr[0] == "depth":
+                d = fr[1]
+                _dev(d, torch.float32, name="depth")
+                arr[i].kind, arr[i].width, arr[i].height = _lib.FRAME_DEPTH, d.shape[1], d.shape[0]
+                arr[i].data_dev = d.data_ptr()
+                for k in range(4):
+                    arr[i].K[k] = float(fr[2][k])
+            elif fr[0] == "points":
+                x = fr[1]
+                _dev(x, torch.float32, (3,), name="xyz")
+                arr[i].kind, arr[i].n, arr[i].data_dev = _lib.FRAME_POINTS, x.shape[0], x.data_ptr()
+            else:
+                raise ValueError(f"unknown frame kind {fr[0]}")
+        return arr
+
+    def integrate(self, frames):
+        arr = self._frames(frames)
+        st = _lib.load().mrh_batch_integrate(self._h, arr)
+        if st != 0:
+            raise MrhError(st, "mrh_batch_integrate", _lib.load().mrh_last_error(self.maps[0]._h).decode())
+
+    def set_launch(self, update_wgs: int, cull_wgs: int, graph: bool = True):
+        p = (ctypes.c_int32 * 3)(update_wgs, cull_wgs, int(graph))
+        st = _lib.load().mrh_batch_set_launch(self._h, p)
+        if st != 0:
+            raise MrhError(st, "mrh_batch_set_launch")
+
+    def get_launch(self):
+        p = (ctypes.c_int32 * 3)()
+        _lib.load().mrh_batch_get_launch(self._h, p)
+        return tuple(p)
+
+    def autotune(self, frames, reps: int = 3):
+        """Time every candidate launch shape on `frames` (maps are reset before and after)."""
+        arr = self._frames(frames)
+        best = (ctypes.c_int32 * 3)()
+        st = _lib.load().mrh_batch_autotune(self._h, arr, int(reps), best)
+        if st != 0:
+            raise MrhError(st, "mrh_batch_autotune", _lib.load().mrh_last_error(self.maps[0]._h).decode())
+        return tuple(best)
 
 
 class SdfQuery(torch.autograd.Function):

@@ -28,10 +28,13 @@ EXPORTS = [
     "mrh_abi_version", "mrh_block_hash", "mrh_map_create", "mrh_map_destroy", "mrh_map_reset",
     "mrh_integrate_depth", "mrh_integrate_points", "mrh_sync", "mrh_query_sdf",
     "mrh_query_sdf_backward", "mrh_extract_blocks", "mrh_last_error", "mrh_profile_enable",
-    "mrh_profile_collect",
+    "mrh_profile_collect", "mrh_batch_create", "mrh_batch_destroy", "mrh_batch_integrate", "mrh_batch_set_launch",
+    "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
-           "query", "query_backward", "reduce"]
+           "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
+           "batch_step"]
+FRAME_NONE, FRAME_DEPTH, FRAME_POINTS = 0, 1, 2
 
 
 class MrhConfig(ctypes.Structure):
@@ -60,6 +63,12 @@ class MrhStats(ctypes.Structure):
                 "failed_inserts": self.failed_inserts, "fresh_observations": self.fresh_observations,
                 "blocks": self.blocks,
                 "error_flags": self.error_flags}
+
+
+class MrhFrame(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("data_dev", ctypes.c_void_p), ("n", ctypes.c_int64), ("K", ctypes.c_double * 4),
+                ("T_ws", ctypes.c_double * 16)]
 
 
 class MrhError(RuntimeError):
@@ -95,6 +104,10 @@ def load():
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
     L.mrh_integrate_points.restype = i32
     L.mrh_integrate_points.argtypes = [P, P, i64, P]
+    L.mrh_integrate_depth_sequence.restype = i32
+    L.mrh_integrate_depth_sequence.argtypes = [P, P, i32, i32, i32, P, P]
+    L.mrh_integrate_points_sequence.restype = i32
+    L.mrh_integrate_points_sequence.argtypes = [P, P, i32, i64, P]
     L.mrh_sync.restype = i32
     L.mrh_sync.argtypes = [P, ctypes.POINTER(MrhStats), ctypes.POINTER(MrhStats)]
     L.mrh_query_sdf.restype = i32
@@ -107,6 +120,18 @@ def load():
     L.mrh_profile_enable.argtypes = [P, i32]
     L.mrh_profile_collect.restype = i32
     L.mrh_profile_collect.argtypes = [P, P, P, i32]
+    L.mrh_batch_create.restype = i32
+    L.mrh_batch_create.argtypes = [P, i32, ctypes.POINTER(P)]
+    L.mrh_batch_destroy.restype = None
+    L.mrh_batch_destroy.argtypes = [P]
+    L.mrh_batch_integrate.restype = i32
+    L.mrh_batch_integrate.argtypes = [P, P]
+    L.mrh_batch_set_launch.restype = i32
+    L.mrh_batch_set_launch.argtypes = [P, P]
+    L.mrh_batch_get_launch.restype = i32
+    L.mrh_batch_get_launch.argtypes = [P, P]
+    L.mrh_batch_autotune.restype = i32
+    L.mrh_batch_autotune.argtypes = [P, P, i32, P]
     L.mrh_last_error.restype = ctypes.c_char_p
     L.mrh_last_error.argtypes = [P]
     _ = dbl

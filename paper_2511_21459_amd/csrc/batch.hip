@@ -1,0 +1,359 @@
+// Batched fusion of many independent maps: one frame per map per call, four launches in total,
+// each covering every map through device-side tables (the per-map work is exactly that of the
+// single-map path), captured once into a HIP graph and replayed while the frame sizes stay fixed.
+//
+//   k_batch_alloc     workgroup ranges per map: depth maps get their pixel tiles then their cull
+//                     workgroups, LiDAR maps one workgroup per 256 points
+//   k_batch_rays      LiDAR maps: one workgroup per 256 points (traversal and accumulation)
+//   k_batch_update    the update tasks of every map (per-level queues), each wave taking a
+//                     contiguous range of the concatenated task space (mostly one map per wave)
+//   k_batch_finalize  one workgroup per map
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mrh_depth.h"
+#include "mrh_points.h"
+
+namespace mrh {
+
+mrh_status ensure_lidar(mrh_map* map);
+
+constexpr int kMaxBatch = 64;
+
+struct BatchEntry {
+    int32_t kind;
+    uint32_t alloc_begin, alloc_end;  // workgroups of this map in the allocation launch
+    uint32_t tiles, tiles_x;          // depth: pixel tiles (cull workgroups follow them)
+    uint32_t ray_begin, ray_end;      // points: workgroups of this map in the ray launch
+    DepthFrame df;
+    ScanParams sp;
+};
+
+__device__ inline int entry_of(const BatchEntry* __restrict__ e, int n, uint32_t b, bool rays) {
+    for (int i = 0; i < n; ++i) {
+        const uint32_t lo = rays ? e[i].ray_begin : e[i].alloc_begin, hi = rays ? e[i].ray_end : e[i].alloc_end;
+        if (b >= lo && b < hi) return i;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(256) void k_batch_alloc(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
+                                                     int n) {
+    const int i = entry_of(ents, n, blockIdx.x, false);
+    if (i < 0) return;
+    const BatchEntry& e = ents[i];
+    const DevMap& m = maps[i];
+    const uint32_t local = blockIdx.x - e.alloc_begin;
+    if (e.kind == MRH_FRAME_DEPTH) {
+        if (local < e.tiles) depth_alloc_tile(m, e.df, local, e.tiles_x);
+        else depth_cull(m, e.df, local - e.tiles, e.alloc_end - e.alloc_begin - e.tiles);
+    } else {
+        points_alloc_chunk(m, e.sp, local);
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
+                                                    int n) {
+    const int i = entry_of(ents, n, blockIdx.x, true);
+    if (i < 0) return;
+    points_ray_chunk<ST>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
+                                                      int n) {
+    __shared__ uint32_t cnt[kMaxBatch][4];
+    __shared__ uint32_t pre[kMaxBatch + 1];
+    for (int k = threadIdx.x; k < 4 * n; k += blockDim.x) {
+        const int i = k >> 2;
+        cnt[i][k & 3] = ents[i].kind == MRH_FRAME_NONE ? 0u : maps[i].ctr->vis_n[k & 3];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + update_task_count(cnt[i]);
+    }
+    __syncthreads();
+    const uint32_t total = pre[n];
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t t0 = (uint32_t)(((unsigned long long)total * wave) / nwaves);
+    const uint32_t t1 = (uint32_t)(((unsigned long long)total * (wave + 1)) / nwaves);
+    int cur = -1;
+    TaskStats ts;
+    for (uint32_t t = t0; t < t1; ++t) {
+        int i = cur < 0 ? 0 : cur;
+        while (t >= pre[i + 1]) ++i;
+        if (i != cur) {
+            if (cur >= 0) flush_task_stats(maps[cur], ts);
+            ts = TaskStats();
+            cur = i;
+        }
+        const uint32_t local = t - pre[i];
+        if (ents[i].kind == MRH_FRAME_DEPTH) depth_update_task<ST>(maps[i], ents[i].df, local, cnt[i], ts);
+        else points_update_task<ST>(maps[i], local, cnt[i], ts);
+    }
+    if (cur >= 0) flush_task_stats(maps[cur], ts);
+}
+
+__global__ void k_batch_finalize(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents, int n) {
+    if ((int)blockIdx.x < n && ents[blockIdx.x].kind != MRH_FRAME_NONE) finalize_map(maps[blockIdx.x]);
+}
+
+}  // namespace mrh
+
+using namespace mrh;
+
+struct mrh_batch {
+    std::vector<mrh_map*> maps;
+    int n = 0;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    DevMap* d_maps = nullptr;
+    BatchEntry* d_ents = nullptr;
+    BatchEntry* h_ents[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    int buf = 0;
+    std::vector<char> lidar_seen;  // map accumulators present when d_maps was last uploaded
+    int32_t update_wgs = 1024, cull_wgs = 32, use_graph = 1;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> graph_sig;  // launch geometry the graph was captured with
+};
+
+namespace mrh {
+
+static mrh_status batch_err(mrh_batch* b, mrh_status code, const char* what) {
+    return set_error(b->maps.empty() ? nullptr : b->maps[0], code, "%s", what);
+}
+
+static void drop_graph(mrh_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->graph_sig.clear();
+}
+
+// Enqueue the four batched launches on stream s for the geometry in h (host copy of the table).
+static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32_t ray_wgs) {
+    const int n = b->n;
+    if (alloc_wgs) hipLaunchKernelGGL(k_batch_alloc, dim3(alloc_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
+    if (ray_wgs) {
+        switch (b->storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_F16>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_BF16>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+            default: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_F32>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
+        }
+    }
+    const dim3 ug((unsigned)b->update_wgs);
+    switch (b->storage) {
+        case MRH_STORE_F16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+        case MRH_STORE_BF16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_BF16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+        default: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F32>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n);
+    }
+    hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)n), dim3(1024), 0, s, b->d_maps, b->d_ents, n);
+}
+
+}  // namespace mrh
+
+extern "C" {
+
+mrh_status mrh_batch_create(mrh_map* const* maps, int32_t n_maps, mrh_batch** out) {
+    if (!maps || !out || n_maps < 1 || n_maps > kMaxBatch) return MRH_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n_maps; ++i) {
+        if (!maps[i] || maps[i]->device != maps[0]->device || maps[i]->cfg.storage != maps[0]->cfg.storage)
+            return MRH_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j)
+            if (maps[j] == maps[i]) return MRH_ERR_INVALID_ARG;
+    }
+    mrh_batch* b = new mrh_batch();
+    b->maps.assign(maps, maps + n_maps);
+    b->n = n_maps;
+    b->storage = maps[0]->cfg.storage;
+    b->stream = maps[0]->stream;
+    b->lidar_seen.assign(n_maps, 0);
+    bool ok = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc((void**)&b->d_maps, sizeof(DevMap) * n_maps) == hipSuccess &&
+              hipMalloc((void**)&b->d_ents, sizeof(BatchEntry) * n_maps) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+        ok = hipHostMalloc((void**)&b->h_ents[k], sizeof(BatchEntry) * n_maps, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        std::vector<DevMap> dm(n_maps);
+        for (int i = 0; i < n_maps; ++i) dm[i] = maps[i]->dm;
+        ok = hipMemcpy(b->d_maps, dm.data(), sizeof(DevMap) * n_maps, hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+        mrh_batch_destroy(b);
+        return MRH_ERR_HIP;
+    }
+    *out = b;
+    return MRH_OK;
+}
+
+void mrh_batch_destroy(mrh_batch* b) {
+    if (!b) return;
+    if (b->stream || b->maps.size()) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (int k = 0; k < 2; ++k) {
+        if (b->h_ents[k]) (void)hipHostFree(b->h_ents[k]);
+        if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+    }
+    if (b->d_maps) (void)hipFree(b->d_maps);
+    if (b->d_ents) (void)hipFree(b->d_ents);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+}
+
+mrh_status mrh_batch_set_launch(mrh_batch* b, const int32_t params[3]) {
+    if (!b || !params || params[0] < 1 || params[0] > 65536 || params[1] < 1 || params[1] > 4096) return MRH_ERR_INVALID_ARG;
+    if (params[0] != b->update_wgs || params[1] != b->cull_wgs) drop_graph(b);
+    b->update_wgs = params[0];
+    b->cull_wgs = params[1];
+    b->use_graph = params[2] != 0;
+    return MRH_OK;
+}
+
+mrh_status mrh_batch_get_launch(const mrh_batch* b, int32_t params[3]) {
+    if (!b || !params) return MRH_ERR_INVALID_ARG;
+    params[0] = b->update_wgs;
+    params[1] = b->cull_wgs;
+    params[2] = b->use_graph;
+    return MRH_OK;
+}
+
+mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
+    if (!b || !frames) return MRH_ERR_INVALID_ARG;
+    const int n = b->n;
+    mrh_map* m0 = b->maps[0];
+    // accumulators of LiDAR maps (first scan allocates them; the device table is refreshed)
+    bool refresh = false;
+    for (int i = 0; i < n; ++i) {
+        const mrh_frame& f = frames[i];
+        if (f.kind != MRH_FRAME_NONE && f.kind != MRH_FRAME_DEPTH && f.kind != MRH_FRAME_POINTS)
+            return batch_err(b, MRH_ERR_INVALID_ARG, "batch: unknown frame kind");
+        if (f.kind == MRH_FRAME_POINTS && f.n > 0 && !b->maps[i]->lidar_ready) {
+            const mrh_status st = ensure_lidar(b->maps[i]);
+            if (st != MRH_OK) return st;
+        }
+        if ((char)b->maps[i]->lidar_ready != b->lidar_seen[i]) refresh = true;
+    }
+    if (refresh) {
+        std::vector<DevMap> dm(n);
+        for (int i = 0; i < n; ++i) {
+            dm[i] = b->maps[i]->dm;
+            b->lidar_seen[i] = (char)b->maps[i]->lidar_ready;
+        }
+        if (hipStreamSynchronize(b->stream) != hipSuccess ||
+            hipMemcpy(b->d_maps, dm.data(), sizeof(DevMap) * n, hipMemcpyHostToDevice) != hipSuccess)
+            return batch_err(b, MRH_ERR_HIP, "batch: map table upload");
+    }
+    // descriptor table and launch geometry
+    const int k = b->buf;
+    b->buf ^= 1;
+    if (hipEventSynchronize(b->copied[k]) != hipSuccess) return batch_err(b, MRH_ERR_HIP, "batch: event");
+    BatchEntry* h = b->h_ents[k];
+    std::memset(h, 0, sizeof(BatchEntry) * n);
+    std::vector<int64_t> sig;
+    sig.push_back(b->update_wgs);
+    sig.push_back(b->cull_wgs);
+    uint32_t alloc_wgs = 0, ray_wgs = 0;
+    for (int i = 0; i < n; ++i) {
+        const mrh_frame& f = frames[i];
+        BatchEntry& e = h[i];
+        e.kind = f.kind;
+        e.alloc_begin = alloc_wgs;
+        e.ray_begin = ray_wgs;
+        if (f.kind == MRH_FRAME_DEPTH) {
+            if (!f.data_dev || f.width <= 0 || f.height <= 0 ||
+                !make_depth_frame(b->maps[i]->cfg, f.data_dev, f.width, f.height, f.K, f.T_ws, e.df))
+                return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad depth frame");
+            e.tiles_x = (uint32_t)(f.width + 15) / 16;
+            e.tiles = e.tiles_x * (uint32_t)((f.height + 15) / 16);
+            alloc_wgs += e.tiles + (uint32_t)b->cull_wgs;
+        } else if (f.kind == MRH_FRAME_POINTS) {
+            if (f.n < 0 || (f.n > 0 && !f.data_dev) || !pose_from(f.T_ws, e.sp.P))
+                return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad point frame");
+            e.sp.xyz = f.data_dev;
+            e.sp.n = f.n;
+            const uint32_t chunks = (uint32_t)((f.n + 255) / 256);
+            alloc_wgs += chunks;
+            ray_wgs += chunks;
+        }
+        e.alloc_end = alloc_wgs;
+        e.ray_end = ray_wgs;
+        sig.push_back(f.kind);
+        sig.push_back((int64_t)e.alloc_end);
+        sig.push_back((int64_t)e.ray_end);
+    }
+    if (hipMemcpyAsync(b->d_ents, h, sizeof(BatchEntry) * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipEventRecord(b->copied[k], b->stream) != hipSuccess)
+        return batch_err(b, MRH_ERR_HIP, "batch: descriptor upload");
+
+    if (!b->use_graph) {
+        launch(m0, K_BATCH_GRAPH, [&] { enqueue_step(b, b->stream, alloc_wgs, ray_wgs); });
+        return check_hip(m0, hipGetLastError(), "batch_integrate");
+    }
+    if (!b->exec || b->graph_sig != sig) {
+        drop_graph(b);
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return batch_err(b, MRH_ERR_HIP, "batch: begin capture");
+        enqueue_step(b, b->capture_stream, alloc_wgs, ray_wgs);
+        const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+        if (ce != hipSuccess || !g) return batch_err(b, MRH_ERR_HIP, "batch: end capture");
+        const hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            b->exec = nullptr;
+            return batch_err(b, MRH_ERR_HIP, "batch: instantiate");
+        }
+        b->graph_sig = sig;
+    }
+    launch(m0, K_BATCH_GRAPH, [&] { (void)hipGraphLaunch(b->exec, b->stream); });
+    return check_hip(m0, hipGetLastError(), "batch_integrate");
+}
+
+mrh_status mrh_batch_autotune(mrh_batch* b, const mrh_frame* frames, int32_t reps, int32_t best[3]) {
+    if (!b || !frames || reps < 1 || !best) return MRH_ERR_INVALID_ARG;
+    static const int32_t kUpdate[] = {256, 512, 1024, 2048, 4096};
+    static const int32_t kCull[] = {16, 64};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MRH_ERR_HIP;
+    float best_ms = 1e30f;
+    int32_t keep[3] = {b->update_wgs, b->cull_wgs, b->use_graph};
+    mrh_status st = MRH_OK;
+    for (int32_t u : kUpdate) {
+        for (int32_t c : kCull) {
+            const int32_t p[3] = {u, c, 1};
+            mrh_batch_set_launch(b, p);
+            for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
+            if (st == MRH_OK) st = mrh_batch_integrate(b, frames);  // capture outside the timing
+            for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
+            if (st != MRH_OK) break;
+            (void)hipEventRecord(e0, b->stream);
+            for (int r = 0; r < reps && st == MRH_OK; ++r) st = mrh_batch_integrate(b, frames);
+            (void)hipEventRecord(e1, b->stream);
+            if (st != MRH_OK || hipEventSynchronize(e1) != hipSuccess) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                keep[0] = u, keep[1] = c, keep[2] = 1;
+            }
+        }
+        if (st != MRH_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == MRH_OK) st = mrh_batch_set_launch(b, keep);
+    for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
+    if (st == MRH_OK) st = check_hip(b->maps[0], hipStreamSynchronize(b->stream), "autotune");
+    for (int k = 0; k < 3; ++k) best[k] = keep[k];
+    return st;
+}
+
+}  // extern "C"

@@ -5,7 +5,7 @@
 #include <cstring>
 #include <vector>
 
-#include "mrh_internal.h"
+#include "mrh_update.h"
 
 namespace mrh {
 
@@ -61,38 +61,11 @@ __global__ void k_reset(DevMap m, uint32_t n_hash) {
     }
 }
 
-// End of a frame: return the slots freed by merges to their levels' stacks, publish stats.
-__global__ void k_finalize(DevMap m) {
-    DevCounters* c = m.ctr;
-    for (int n = 0; n < m.levels; ++n) {
-        const uint32_t p = c->pending[n];
-        if (p == 0) continue;
-        const int32_t top = c->top[n];
-        for (uint32_t i = threadIdx.x; i < p; i += blockDim.x) m.stack[n][top + i] = m.pend[n][i];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            c->top[n] = top + (int32_t)p;
-            c->pending[n] = 0;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < S_COUNT) {
-        unsigned long long v = 0;
-        for (int k = 0; k < kStripes; ++k) {
-            v += c->frame[k][threadIdx.x];
-            c->frame[k][threadIdx.x] = 0;
-        }
-        c->last[threadIdx.x] = v;
-        c->total[threadIdx.x] += v;
-    }
-    if (threadIdx.x == 0) {
-        c->frames += 1;
-        for (int n = 0; n < 4; ++n) c->vis_n[n] = 0;
-        c->n_prev = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
-    }
-}
+// End of a frame (one workgroup).
+__global__ void k_finalize(DevMap m) { finalize_map(m); }
 
 // Copy blocks out: keys, levels and (optionally) voxels converted from Morton to x-fastest order.
+template <int ST>
 __global__ void k_extract(DevMap m, uint32_t nb, const int64_t* __restrict__ offsets, int32_t* keys, uint8_t* levels,
                           float* D, uint32_t* W, float* S2) {
     const int lane = threadIdx.x & 63;
@@ -119,9 +92,12 @@ __global__ void k_extract(DevMap m, uint32_t nb, const int64_t* __restrict__ off
             int i, j, k;
             demorton3(p, i, j, k);
             const int64_t o = off + i + mside * (j + mside * k);
-            if (D) D[o] = m.D[lvl][base + p];
-            if (W) W[o] = m.W[lvl][base + p];
-            if (S2) S2[o] = m.S2[lvl][base + p];
+            float d, s2;
+            uint32_t w;
+            Store<ST>::get(m, lvl, base + p, d, w, s2);
+            if (D) D[o] = d;
+            if (W) W[o] = w;
+            if (S2) S2[o] = s2;
         }
     }
 }
@@ -164,7 +140,7 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     if (!(c.voxel > 0.0) || !std::isfinite(c.voxel) || c.levels < 1 || c.levels > 4 || !(c.tau > 0.0) ||
         c.min_obs < 1 || !pow2 || c.max_blocks < 1 || c.hash_slots < 2 * c.max_blocks ||
         c.hash_slots > (int64_t(1) << 31) || c.max_blocks > (int64_t(1) << 30) || !(c.var_thr >= 0.0) ||
-        c.storage != MRH_STORE_F32 || c.form < 0 || c.form > 1)
+        c.storage < MRH_STORE_F32 || c.storage > MRH_STORE_BF16 || c.form < 0 || c.form > 1)
         return MRH_ERR_INVALID_ARG;
     for (int n = 0; n < 4; ++n)
         if (c.heap_blocks[n] < 0 || c.heap_blocks[n] > (int64_t)kSlotMask + 1) return MRH_ERR_INVALID_ARG;
@@ -188,6 +164,9 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
         d.inv_nu[n] = 1.0 / d.nu[n];
     }
     d.tau = c.tau;
+    d.tau_f = (float)c.tau;
+    d.inv_tau_f = (float)(1.0 / c.tau);
+    d.tau2_f = (float)(c.tau * c.tau);
     d.var_thr = c.var_thr;
     d.max_depth = c.max_depth;
     d.r2lo = c.min_range * c.min_range;
@@ -217,9 +196,10 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
         const size_t nv = (size_t)cap * (size_t)(side_of(n) * side_of(n) * side_of(n));
         alloc((void**)&d.stack[n], (size_t)cap * 4, "free stack");
         alloc((void**)&d.pend[n], (size_t)cap * 4, "pending frees");
-        alloc((void**)&d.D[n], nv * 4, "TSDF heap");
-        alloc((void**)&d.W[n], nv * 4, "weight heap");
-        alloc((void**)&d.S2[n], nv * 4, "variance heap");
+        const size_t pb = (size_t)plane_bytes(c.storage);
+        alloc((void**)&d.D[n], nv * pb, "TSDF heap");
+        alloc((void**)&d.W[n], nv * pb, "weight heap");
+        alloc((void**)&d.S2[n], nv * pb, "variance heap");
     }
     m->partials_cap = 1024;
     alloc((void**)&m->partials, (size_t)m->partials_cap * 6 * 8, "reduction partials");
@@ -339,8 +319,11 @@ mrh_status mrh_extract_blocks(mrh_map* map, int32_t* keys_dev, uint8_t* levels_d
     st = check_hip(map, hipMemcpy(doffs, offs.data(), (nb + 1) * 8, hipMemcpyHostToDevice), "extract");
     if (st == MRH_OK) {
         const uint32_t grid = nb / 4 + 1 < 4096 ? nb / 4 + 1 : 4096;
-        hipLaunchKernelGGL(k_extract, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev,
-                           D_dev, W_dev, S2_dev);
+        switch (map->cfg.storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_extract<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_extract<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            default: hipLaunchKernelGGL(k_extract<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev);
+        }
         st = check_hip(map, hipGetLastError(), "extract");
         if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "extract");
     }

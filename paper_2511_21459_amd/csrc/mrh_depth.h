@@ -1,0 +1,348 @@
+// RGB-D fusion work units (Sec. 3.1 "Cameras", Eq. 2; Eq. 3 and Eq. 5; Sec. 3.2.1 merging
+// criterion), shared by the single-map kernels (depth.hip) and the batched kernels (batch.hip).
+//
+//   depth_alloc_tile   a 16 x 16 pixel tile (one workgroup, each wave a 16 x 4 strip): back-
+//                      projection, band walk over the block lattice, wave-deduplicated insert; new
+//                      blocks are queued for the update
+//   depth_cull         one thread per block that existed at the frame's start: conservative frustum
+//                      test, visible blocks queued per level
+//   depth_update_task  one queued level-0 or level-1 block (a wave), or 8 level-2 / 64 level-3
+//                      blocks per wave: per-voxel projection and update, block variance bookkeeping
+//                      and the merge of a block whose mean variance fell below the threshold
+#pragma once
+
+#include "mrh_update.h"
+
+namespace mrh {
+
+struct DepthFrame {
+    Pose P;
+    double fx, fy, cx, cy, ifx, ify;
+    int32_t width, height;
+    const float* depth;  // device z-depth image, row-major
+    float fxf, fyf, cxf, cyf;  // intrinsics rounded to FP32 for the fast projection
+    // conservative culling of whole blocks (camera frame): side-plane normals and a range bound
+    double plane[4][3];
+    double cull_range;
+};
+
+// Host: fill a frame descriptor; false on a non-finite pose or intrinsics or a zero focal length.
+bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, int32_t height, const double K[4],
+                      const double T_ws[16], DepthFrame& f);
+
+// Observation for the voxel whose camera-frame centre is x (Eq. 2 with the gate at -tau and
+// truncation at +tau).  Returns false when the voxel is not updated.
+__device__ inline bool project_observe(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                       double x0, double x1, double x2, float& obs) {
+    if (!(x2 > 0.0)) return false;
+    const double iz = 1.0 / x2;
+    const double uu = (f.fx * (x0 * iz)) + f.cx;
+    const double vv = (f.fy * (x1 * iz)) + f.cy;
+    const double fu = __builtin_floor(uu + 0.5), fv = __builtin_floor(vv + 0.5);
+    if (!(fu >= 0.0 && fu <= (double)(f.width - 1) && fv >= 0.0 && fv <= (double)(f.height - 1))) return false;
+    const double d = (double)depth[(int64_t)fv * f.width + (int64_t)fu];
+    if (!(__builtin_isfinite(d) && d > 0.0 && d <= m.max_depth)) return false;
+    double raw;
+    if (m.form == MRH_FORM_RANGE) {
+        const double nx = __builtin_sqrt((x0 * x0 + x1 * x1) + x2 * x2);
+        raw = nx * ((d * iz) - 1.0);
+    } else {
+        raw = d - x2;
+    }
+    if (raw < -m.tau) return false;
+    obs = (float)(raw < m.tau ? raw : m.tau);
+    return true;
+}
+
+// The same observation with the projection evaluated in FP32.  Every discrete decision (pixel index,
+// the -tau gate) is taken from the FP32 value only when it lies farther from its threshold than the
+// FP32 evaluation error can reach; otherwise the canonical FP64 expression above decides, so the
+// decisions always equal the canonical ones.  Error budget of u = fx (x0 / x2) + cx from FP64 x:
+// four roundings at 2^-24 relative of values below |u| + |cx| stay under 1e-6 (|u| + |cx| + 16).
+__device__ inline bool project_observe_fast(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                            double x0, double x1, double x2, float& obs) {
+    if (!(x2 > 0.0)) return false;
+    const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
+    if (!(xf2 > 1e-6f)) return project_observe(m, f, depth, x0, x1, x2, obs);
+    const float izf = 1.0f / xf2;
+    const float uf = f.fxf * (xf0 * izf) + f.cxf;
+    const float vf = f.fyf * (xf1 * izf) + f.cyf;
+    const float su = uf + 0.5f, sv = vf + 0.5f;
+    const float fu = __builtin_floorf(su), fv = __builtin_floorf(sv);
+    const float du = __builtin_fminf(su - fu, fu + 1.0f - su), dv = __builtin_fminf(sv - fv, fv + 1.0f - sv);
+    const float eu = 1e-6f * (__builtin_fabsf(uf) + __builtin_fabsf(f.cxf) + 16.0f);
+    const float ev = 1e-6f * (__builtin_fabsf(vf) + __builtin_fabsf(f.cyf) + 16.0f);
+    if (!(du > eu && dv > ev)) return project_observe(m, f, depth, x0, x1, x2, obs);
+    if (!(fu >= 0.0f && fu <= (float)(f.width - 1) && fv >= 0.0f && fv <= (float)(f.height - 1))) return false;
+    const float d = depth[(int64_t)fv * f.width + (int64_t)fu];
+    if (!(__builtin_isfinite(d) && d > 0.0f && (double)d <= m.max_depth)) return false;
+    const double ddiff = (double)d - x2;
+    if (m.form != MRH_FORM_RANGE) {
+        if (ddiff < -m.tau) return false;
+        obs = (float)(ddiff < m.tau ? ddiff : m.tau);
+        return true;
+    }
+    // range form: raw = ||x|| (d / x2 - 1) = (d - x2) ||x|| / x2
+    const float lam = __builtin_sqrtf((xf0 * xf0 + xf1 * xf1) + xf2 * xf2) * izf;
+    const float raw = (float)ddiff * lam;
+    if (__builtin_fabsf(raw + m.tau_f) <= 1e-5f * m.tau_f + 1e-6f * __builtin_fabsf(raw)) {
+        // near the gate: decide with the canonical expression
+        const double nx = __builtin_sqrt((x0 * x0 + x1 * x1) + x2 * x2);
+        const double raw64 = nx * (((double)d * (1.0 / x2)) - 1.0);
+        if (raw64 < -m.tau) return false;
+    } else if (raw < -m.tau_f) {
+        return false;
+    }
+    obs = raw < m.tau_f ? raw : m.tau_f;
+    return true;
+}
+
+__device__ inline bool block_visible(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz) {
+    const double hb = 0.5 * m.B;
+    const double c[3] = {(double)bx * m.B + hb, (double)by * m.B + hb, (double)bz * m.B + hb};
+    const double d0 = c[0] - f.P.t[0], d1 = c[1] - f.P.t[1], d2 = c[2] - f.P.t[2];
+    double x[3];
+    for (int r = 0; r < 3; ++r) x[r] = (f.P.R[0][r] * d0 + f.P.R[1][r] * d1) + f.P.R[2][r] * d2;
+    const double rb = m.B * 0.8660254037844387 * (1.0 + 1e-9) + 1e-9;
+    if (x[2] < -rb) return false;
+    if (__builtin_sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) - rb > f.cull_range) return false;
+    for (int p = 0; p < 4; ++p)
+        if (f.plane[p][0] * x[0] + f.plane[p][1] * x[1] + f.plane[p][2] * x[2] < -rb) return false;
+    return true;
+}
+
+// Conservative frustum cull of the blocks that existed when the frame started, one thread per
+// block: workgroup g of ng covers ids g * 256 + threadIdx, stepping by ng * 256.
+__device__ inline void depth_cull(const DevMap& m, const DepthFrame& f, uint32_t g, uint32_t ng) {
+    const uint32_t n = m.ctr->n_prev;
+    for (uint32_t base = g * blockDim.x; base < n; base += ng * blockDim.x) {
+        const uint32_t id = base + threadIdx.x;
+        int level = -1;
+        if (id < n) {
+            const uint32_t info = m.binfo[id];
+            if (!(info & kNoBlockBit)) {
+                int32_t bx, by, bz;
+                unpack_key(m.bkey[id], bx, by, bz);
+                if ((info & kNewBit) || block_visible(m, f, bx, by, bz)) level = (int)((info >> kLevelShift) & 3u);
+            }
+        }
+        queue_block(m, level, id);
+    }
+}
+
+// One 16 x 16 pixel tile per workgroup (tile index `tile`, tiles_x tiles per row).
+__device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, uint32_t tile, uint32_t tiles_x) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const float* __restrict__ depth = f.depth;
+    const int u = (int)(tile % tiles_x) * 16 + (lane & 15);
+    const int v = (int)(tile / tiles_x) * 16 + wave * 4 + (lane >> 4);
+    bool ok = u < f.width && v < f.height;
+    double d = 0.0;
+    if (ok) {
+        d = (double)depth[(int64_t)v * f.width + u];
+        ok = __builtin_isfinite(d) && d > 0.0 && d <= m.max_depth;
+    }
+    Walk w;
+    bool in_range = false;
+    if (ok) {
+        // back-projection of the pixel centre and the truncation band along the sensor ray
+        const double ps[3] = {(((double)u - f.cx) * f.ifx) * d, (((double)v - f.cy) * f.ify) * d, d};
+        double pw[3], n[3];
+        pose_apply(f.P, ps, pw);
+        unit_direction(pw, f.P.t, n);
+        const double a[3] = {pw[0] - m.tau * n[0], pw[1] - m.tau * n[1], pw[2] - m.tau * n[2]};
+        const double e[3] = {pw[0] + m.tau * n[0], pw[1] + m.tau * n[1], pw[2] + m.tau * n[2]};
+        in_range = segment_in_range(a, e, m.invB);
+        if (in_range) w.init(a, e, m.invB);
+    }
+    __shared__ uint32_t cnt[2];
+    if (threadIdx.x == 0) cnt[0] = cnt[1] = 0;
+    __syncthreads();
+    const unsigned long long vmask = __ballot(ok), dmask = __ballot(ok && !in_range);
+    if (lane == 0) {
+        atomicAdd(&cnt[0], (uint32_t)__popcll(vmask));
+        atomicAdd(&cnt[1], (uint32_t)__popcll(dmask));
+    }
+    bool active = in_range;
+    while (__ballot(active)) {
+        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
+        insert_keys(m, active, key, true);
+        if (active) active = w.next();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        stat_add(m, S_VALID, cnt[0]);
+        stat_add(m, S_DROPPED, cnt[1]);
+    }
+}
+
+
+// Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
+template <int ST>
+__device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                            uint32_t id, TaskStats& ts) {
+    const int lane = lane_id();
+    const uint32_t info = m.binfo[id];
+    int32_t bx, by, bz;
+    unpack_key(m.bkey[id], bx, by, bz);
+    const bool fresh = (info & kNewBit) != 0;
+    int I, J, K;
+    demorton3(lane, I, J, K);
+    const double nu = m.nu[0];
+    // camera-frame products of R^T (c - t), one per axis coordinate of this lane's group
+    double px[2][3], py[2][3], pz[2][3];
+    for (int s = 0; s < 2; ++s) {
+        const double cx = (double)bx * m.B + ((double)(2 * I + s) + 0.5) * nu;
+        const double cy = (double)by * m.B + ((double)(2 * J + s) + 0.5) * nu;
+        const double cz = (double)bz * m.B + ((double)(2 * K + s) + 0.5) * nu;
+        const double dx = cx - f.P.t[0], dy = cy - f.P.t[1], dz = cz - f.P.t[2];
+        for (int r = 0; r < 3; ++r) {
+            px[s][r] = f.P.R[0][r] * dx;
+            py[s][r] = f.P.R[1][r] * dy;
+            pz[s][r] = f.P.R[2][r] * dz;
+        }
+    }
+    float obs[8];
+    uint32_t upd = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, c = (q >> 2) & 1;
+        const double x0 = (px[a][0] + py[b][0]) + pz[c][0];
+        const double x1 = (px[a][1] + py[b][1]) + pz[c][1];
+        const double x2 = (px[a][2] + py[b][2]) + pz[c][2];
+        if (project_observe_fast(m, f, depth, x0, x1, x2, obs[q])) upd |= 1u << q;
+    }
+    const int nupd = wave_sum((int)__popc(upd));
+    if (nupd == 0 && !fresh) return;
+    ts.obs += (unsigned long long)nupd;
+    if (fresh) ts.fresh += (unsigned long long)nupd;
+
+    const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
+    float D[8], S2[8];
+    uint32_t W[8];
+    bool have = false;
+    if (fresh) {
+        for (int q = 0; q < 8; ++q) D[q] = 0.f, S2[q] = 0.f, W[q] = 0u;
+        have = true;
+    } else if (upd) {
+        Store<ST>::get8(m, base, D, W, S2);
+        have = true;
+    }
+    double dsum = 0.0;
+    int dcnt = 0;
+    for (int q = 0; q < 8; ++q) {
+        if (!(upd & (1u << q))) continue;
+        const double before = var_term(m, W[q], S2[q]);
+        const int cb = var_count(m, W[q]);
+        welford(obs[q], D[q], W[q], S2[q]);
+        Store<ST>::round(m, D[q], W[q], S2[q]);
+        dsum += var_term(m, W[q], S2[q]) - before;
+        dcnt += var_count(m, W[q]) - cb;
+    }
+    ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt);
+}
+
+// Camera-frame centre of voxel (i, j, k) of block b at `level`, canonical FP64.
+__device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz, int level,
+                                    int i, int j, int k, double& x0, double& x1, double& x2) {
+    const double nu = m.nu[level];
+    const double c0 = (double)bx * m.B + ((double)i + 0.5) * nu;
+    const double c1 = (double)by * m.B + ((double)j + 0.5) * nu;
+    const double c2 = (double)bz * m.B + ((double)k + 0.5) * nu;
+    const double d0 = c0 - f.P.t[0], d1 = c1 - f.P.t[1], d2 = c2 - f.P.t[2];
+    x0 = (f.P.R[0][0] * d0 + f.P.R[1][0] * d1) + f.P.R[2][0] * d2;
+    x1 = (f.P.R[0][1] * d0 + f.P.R[1][1] * d1) + f.P.R[2][1] * d2;
+    x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
+}
+
+// Level-1 block: lane l owns the voxel at Morton position l.
+template <int ST>
+__device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                              uint32_t id, TaskStats& ts) {
+    const int lane = lane_id();
+    const uint32_t info = m.binfo[id];
+    int32_t bx, by, bz;
+    unpack_key(m.bkey[id], bx, by, bz);
+    int i, j, k;
+    demorton3(lane, i, j, k);
+    double x0, x1, x2;
+    voxel_camera(m, f, bx, by, bz, 1, i, j, k, x0, x1, x2);
+    float obs = 0.f;
+    const bool upd = project_observe_fast(m, f, depth, x0, x1, x2, obs);
+    const int nupd = __popcll(__ballot(upd));
+    if (nupd == 0) return;
+    ts.obs += (unsigned long long)nupd;
+    const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
+    float D, S2;
+    uint32_t W;
+    Store<ST>::get(m, 1, at, D, W, S2);
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        welford(obs, D, W, S2);
+        Store<ST>::round(m, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    }
+    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt);
+}
+
+// 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
+template <int ST>
+__device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                               const uint32_t* list, uint32_t count, uint32_t group, int level,
+                                               TaskStats& ts) {
+    const int lane = lane_id();
+    const int seg = level == 2 ? 8 : 1;
+    const uint32_t bi = group * (uint32_t)(64 / seg) + (uint32_t)(lane / seg);
+    const bool live = bi < count;
+    uint32_t id = 0, info = 0;
+    bool upd = false;
+    float obs = 0.f;
+    if (live) {
+        id = list[bi];
+        info = m.binfo[id];
+        int32_t bx, by, bz;
+        unpack_key(m.bkey[id], bx, by, bz);
+        int i, j, k;
+        demorton3(lane % seg, i, j, k);
+        double x0, x1, x2;
+        voxel_camera(m, f, bx, by, bz, level, i, j, k, x0, x1, x2);
+        upd = project_observe_fast(m, f, depth, x0, x1, x2, obs);
+    }
+    if (!__ballot(upd)) return;
+    float D = 0.f, S2 = 0.f;
+    uint32_t W = 0;
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        Store<ST>::get(m, level, (size_t)(info & kSlotMask) * seg + (lane % seg), D, W, S2);
+        ts.lane_obs += 1;
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        welford(obs, D, W, S2);
+        Store<ST>::round(m, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    } else if (live && seg > 1) {
+        // a segment whose block merges needs all of its voxels
+        Store<ST>::get(m, level, (size_t)(info & kSlotMask) * seg + (lane % seg), D, W, S2);
+    }
+    ts.lane_merges += (unsigned long long)finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum,
+                                                      dcnt);
+}
+
+// One update task t of a frame whose queues hold n0..n3 blocks per level.
+template <int ST>
+__device__ inline void depth_update_task(const DevMap& m, const DepthFrame& f, uint32_t t, const uint32_t n[4],
+                                         TaskStats& ts) {
+    const uint32_t g2 = (n[2] + 7) / 8;
+    if (t < n[0]) integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t], ts);
+    else if (t < n[0] + n[1]) integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n[0]], ts);
+    else if (t < n[0] + n[1] + g2) integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], n[2], t - n[0] - n[1], 2, ts);
+    else integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], n[3], t - n[0] - n[1] - g2, 3, ts);
+}
+
+}  // namespace mrh

@@ -68,9 +68,9 @@ struct DevMap {
     uint32_t* stack[4];
     uint32_t* pend[4];
     int32_t heap_cap[4];
-    float* D[4];
-    uint32_t* W[4];
-    float* S2[4];
+    void* D[4];   // per level, plane of the storage format (see mrh_store.h)
+    void* W[4];
+    void* S2[4];
     // LiDAR per-frame accumulators, parallel to the heaps (zero between frames):
     // saturated (+tau) observation counts, band observation counts, and fixed-point sums of
     // (d - D) and (d - D)^2 relative to the voxel's mean at the start of the frame
@@ -84,6 +84,7 @@ struct DevMap {
     double nu[4], inv_nu[4];
     double tau, var_thr;
     double max_depth, r2lo, r2hi;
+    float tau_f, inv_tau_f, tau2_f;
     int32_t min_obs, form, carve, storage;
 };
 
@@ -320,7 +321,9 @@ inline int side_of(int level) { return 8 >> level; }
 enum KernelId { K_RESET = MRH_KERNEL_RESET, K_ALLOC_DEPTH = MRH_KERNEL_ALLOC_DEPTH, K_INTEGRATE_DEPTH = MRH_KERNEL_INTEGRATE_DEPTH,
                 K_FINALIZE = MRH_KERNEL_FINALIZE, K_ALLOC_POINTS = MRH_KERNEL_ALLOC_POINTS, K_RAYS = MRH_KERNEL_RAYS,
                 K_APPLY_POINTS = MRH_KERNEL_APPLY_POINTS, K_QUERY = MRH_KERNEL_QUERY, K_QUERY_BACKWARD = MRH_KERNEL_QUERY_BACKWARD,
-                K_REDUCE = MRH_KERNEL_REDUCE };
+                K_REDUCE = MRH_KERNEL_REDUCE, K_BATCH_ALLOC = MRH_KERNEL_BATCH_ALLOC, K_BATCH_RAYS = MRH_KERNEL_BATCH_RAYS,
+                K_BATCH_UPDATE = MRH_KERNEL_BATCH_UPDATE, K_BATCH_FINALIZE = MRH_KERNEL_BATCH_FINALIZE,
+                K_BATCH_GRAPH = MRH_KERNEL_BATCH_GRAPH };
 
 // one profiled launch: kernel id and its bracketing events on the map's stream
 struct ProfRec {

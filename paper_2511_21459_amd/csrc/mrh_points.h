@@ -1,0 +1,367 @@
+// LiDAR fusion work units (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3 and Eq. 5; Sec. 3.2.1),
+// shared by the single-map kernels (points.hip) and the batched kernels (batch.hip).
+//
+//   points_alloc_chunk  256 points: validity, segment [o, p + tau n] (carving) or the band
+//                       [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated insert
+//   points_ray_chunk    256 points: the same block walk; inside each block a walk over the block's
+//                       own voxel lattice; each crossed voxel gets clip((p - x) . n, -tau, tau).
+//                       Saturated observations (+tau) only bump an integer count; the others add to
+//                       fixed-point sums of (d - D) and (d - D)^2, D being the voxel's mean at the
+//                       start of the scan, so the accumulation is exact and order-independent.  A
+//                       block's first touch in the scan queues it on its level's list.
+//   points_update_task  one queued level-0 or level-1 block (a wave), or 8 level-2 / 64 level-3
+//                       blocks per wave: each voxel's scan statistics merge into its state (W' =
+//                       W + n, D' = D + s1 / W', S2' = S2 + s2 - s1^2 / W', the batch form of Eq. 3
+//                       and Eq. 5), then the block variance bookkeeping and the merging criterion
+#pragma once
+
+#include "mrh_update.h"
+
+namespace mrh {
+
+constexpr double kS1Scale = 16777216.0;         // 2^24 per metre
+constexpr double kS2Scale = 281474976710656.0;  // 2^48 per square metre
+
+struct ScanParams {
+    Pose P;
+    const float* xyz;  // device points, sensor frame, [n][3]
+    int64_t n;
+};
+
+__device__ inline bool point_segment(const DevMap& m, const ScanParams& sp, int64_t i, double a[3], double e[3],
+                                     double p[3], double n[3]) {
+    const float* __restrict__ xyz = sp.xyz;
+    const double ps[3] = {(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
+    if (!(__builtin_isfinite(ps[0]) && __builtin_isfinite(ps[1]) && __builtin_isfinite(ps[2]))) return false;
+    const double r2 = (ps[0] * ps[0] + ps[1] * ps[1]) + ps[2] * ps[2];
+    if (!(r2 >= m.r2lo && r2 <= m.r2hi)) return false;
+    pose_apply(sp.P, ps, p);
+    unit_direction(p, sp.P.t, n);
+    for (int k = 0; k < 3; ++k) {
+        a[k] = m.carve ? sp.P.t[k] : p[k] - m.tau * n[k];
+        e[k] = p[k] + m.tau * n[k];
+    }
+    return true;
+}
+
+// Allocation for points chunk * 256 + threadIdx.
+__device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk) {
+    const int lane = lane_id();
+    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
+    double a[3], e[3], p[3], nn[3];
+    const bool ok = i < sp.n && point_segment(m, sp, i, a, e, p, nn);
+    const unsigned long long vmask = __ballot(ok);
+    const bool in_range = ok && segment_in_range(a, e, m.invB);
+    const unsigned long long dmask = __ballot(ok && !in_range);
+    if (lane == 0) {
+        stat_add(m, S_VALID, (unsigned long long)__popcll(vmask));
+        stat_add(m, S_DROPPED, (unsigned long long)__popcll(dmask));
+    }
+    Walk w;
+    if (in_range) w.init(a, e, m.invB);
+    bool active = in_range;
+    while (__ballot(active)) {
+        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
+        insert_keys(m, active, key, false);
+        if (active) active = w.next();
+    }
+}
+
+// Accumulate one observation d of the voxel at heap position `at` of `level`.
+template <int ST>
+__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d) {
+    if (d >= m.tau) {
+        atomicAdd(&m.acc_sat[level][at], 1u);
+        return;
+    }
+    const double Dp = fresh ? 0.0 : (double)Store<ST>::getD(m, level, at);
+    const double r = d - Dp;
+    atomicAdd(&m.acc_band[level][at], 1u);
+    atomicAdd(&m.acc_s1[level][at], (unsigned long long)(long long)__builtin_rint(r * kS1Scale));
+    atomicAdd(&m.acc_s2[level][at], (unsigned long long)__builtin_rint((r * r) * kS2Scale));
+}
+
+// The block walk restricted to one block: the segment is clipped to the block's box, the walk
+// starts in the (clamped) cell of the clipped entry point and steps on the block's own lattice of
+// side^3 voxels until it leaves the block or passes the clipped exit parameter.
+struct BoxWalk {
+    double A0, A1, A2, iD0, iD1, iD2, t0, t1, t2, tout;
+    int c0, c1, c2, s0, s1, s2, side;
+
+    __device__ static inline void axis(double a, double e, double ob, double inv_nu, int side, double& A, double& D,
+                                       double& iD, int& st, double& tin, double& tout) {
+        A = (a - ob) * inv_nu;
+        const double El = (e - ob) * inv_nu;
+        D = El - A;
+        if (D != 0.0) {
+            iD = 1.0 / D;
+            const double nearb = D > 0.0 ? 0.0 : (double)side;
+            const double farb = D > 0.0 ? (double)side : 0.0;
+            const double ta = (nearb - A) * iD;
+            const double tb = (farb - A) * iD;
+            if (ta > tin) tin = ta;
+            if (tb < tout) tout = tb;
+            st = D > 0.0 ? 1 : -1;
+        } else {
+            iD = 0.0;
+            st = 0;
+        }
+    }
+    __device__ static inline void start(double A, double D, double iD, int st, double tin, int side, int& c, double& t) {
+        double fl = __builtin_floor(A + tin * D);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(side - 1)) fl = (double)(side - 1);
+        c = (int)fl;
+        t = st != 0 ? ((double)(c + (st > 0 ? 1 : 0)) - A) * iD : __builtin_inf();
+    }
+    __device__ inline void init(const double a[3], const double e[3], const int64_t b[3], double B, double inv_nu,
+                                int side_) {
+        side = side_;
+        double D0, D1, D2, tin = 0.0;
+        tout = 1.0;
+        axis(a[0], e[0], (double)b[0] * B, inv_nu, side, A0, D0, iD0, s0, tin, tout);
+        axis(a[1], e[1], (double)b[1] * B, inv_nu, side, A1, D1, iD1, s1, tin, tout);
+        axis(a[2], e[2], (double)b[2] * B, inv_nu, side, A2, D2, iD2, s2, tin, tout);
+        start(A0, D0, iD0, s0, tin, side, c0, t0);
+        start(A1, D1, iD1, s1, tin, side, c1, t1);
+        start(A2, D2, iD2, s2, tin, side, c2, t2);
+    }
+    __device__ inline bool next() {
+        double tm = t0;
+        int k = 0;
+        if (t1 < tm) tm = t1, k = 1;
+        if (t2 < tm) tm = t2, k = 2;
+        if (!(tm <= tout)) return false;
+        if (k == 0) {
+            c0 += s0;
+            if (c0 < 0 || c0 >= side) return false;
+            t0 = ((double)(c0 + (s0 > 0 ? 1 : 0)) - A0) * iD0;
+        } else if (k == 1) {
+            c1 += s1;
+            if (c1 < 0 || c1 >= side) return false;
+            t1 = ((double)(c1 + (s1 > 0 ? 1 : 0)) - A1) * iD1;
+        } else {
+            c2 += s2;
+            if (c2 < 0 || c2 >= side) return false;
+            t2 = ((double)(c2 + (s2 > 0 ? 1 : 0)) - A2) * iD2;
+        }
+        return true;
+    }
+};
+
+// Traversal and accumulation for points chunk * 256 + threadIdx.
+template <int ST>
+__device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk) {
+    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
+    double a[3], e[3], p[3], nn[3];
+    if (!(i < sp.n && point_segment(m, sp, i, a, e, p, nn) && segment_in_range(a, e, m.invB))) return;
+    Walk w;
+    w.init(a, e, m.invB);
+    do {
+        const int64_t b[3] = {w.c0, w.c1, w.c2};
+        const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
+        const uint32_t info = id == kInvalidId ? kNoBlockBit : m.binfo[id];
+        const int level = (int)((info >> kLevelShift) & 3u);
+        // first touch of the block in this scan: queue it for the update (active lanes only)
+        const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
+        if (__ballot(first)) queue_block(m, first ? level : -1, id);
+        if (info & kNoBlockBit) continue;
+        const bool fresh = (info & kNewBit) != 0;
+        const int side = 8 >> level;
+        const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
+        const double nu = m.nu[level];
+        BoxWalk bw;
+        bw.init(a, e, b, m.B, m.inv_nu[level], side);
+        for (int s = 0;; ++s) {
+            // observation of the voxel centre (Eq. 1)
+            const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
+            const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
+            const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
+            const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
+            const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
+            accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d);
+            if (s == 3 * side || !bw.next()) break;
+        }
+    } while (w.next());
+}
+
+// Batch form of Eq. 3 and Eq. 5 for n observations with sums s1, s2 of (d - D) and (d - D)^2.
+__device__ inline void apply_stats(const DevMap& m, uint32_t nsat, uint32_t nband, unsigned long long s1q,
+                                   unsigned long long s2q, float& D, uint32_t& W, float& S2) {
+    const uint32_t nobs = nsat + nband;
+    const double Dp = (double)D;
+    const double ts = m.tau - Dp;
+    const double s1 = (double)nsat * ts + (double)(long long)s1q / kS1Scale;
+    const double s2 = (double)nsat * (ts * ts) + (double)s2q / kS2Scale;
+    const double Wn = (double)W + (double)nobs;
+    const double S2n = (double)S2 + s2 - s1 * s1 / Wn;
+    D = (float)(Dp + s1 / Wn);
+    S2 = (float)(S2n > 0.0 ? S2n : 0.0);
+    W = W + nobs;
+}
+
+// Read and clear one voxel's scan accumulators.
+__device__ inline void take_accumulators(const DevMap& m, int level, size_t at, uint32_t& ns, uint32_t& nb,
+                                         unsigned long long& s1, unsigned long long& s2) {
+    ns = m.acc_sat[level][at];
+    nb = m.acc_band[level][at];
+    s1 = s2 = 0ull;
+    if (ns) m.acc_sat[level][at] = 0u;
+    if (nb) {
+        s1 = m.acc_s1[level][at];
+        s2 = m.acc_s2[level][at];
+        m.acc_band[level][at] = 0u;
+        m.acc_s1[level][at] = 0ull;
+        m.acc_s2[level][at] = 0ull;
+    }
+}
+
+template <int ST>
+__device__ inline void apply_fine(const DevMap& m, uint32_t id, TaskStats& as) {
+    const int lane = lane_id();
+    const uint32_t info = m.binfo[id];
+    const bool fresh = (info & kNewBit) != 0;
+    const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
+    uint32_t ns[8], nb[8];
+    unsigned long long s1[8], s2[8];
+    {
+        const uint4* a = reinterpret_cast<const uint4*>(m.acc_sat[0] + base);
+        const uint4* b = reinterpret_cast<const uint4*>(m.acc_band[0] + base);
+        const uint4 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
+        ns[0] = a0.x, ns[1] = a0.y, ns[2] = a0.z, ns[3] = a0.w, ns[4] = a1.x, ns[5] = a1.y, ns[6] = a1.z, ns[7] = a1.w;
+        nb[0] = b0.x, nb[1] = b0.y, nb[2] = b0.z, nb[3] = b0.w, nb[4] = b1.x, nb[5] = b1.y, nb[6] = b1.z, nb[7] = b1.w;
+    }
+    uint32_t upd = 0;
+    int nobs = 0;
+    for (int q = 0; q < 8; ++q) {
+        if (ns[q] + nb[q]) upd |= 1u << q;
+        nobs += (int)(ns[q] + nb[q]);
+    }
+    bool any_band = false;
+    for (int q = 0; q < 8; ++q) any_band |= nb[q] != 0;
+    if (any_band) {
+        const ulonglong2* s1p = reinterpret_cast<const ulonglong2*>(m.acc_s1[0] + base);
+        const ulonglong2* s2p = reinterpret_cast<const ulonglong2*>(m.acc_s2[0] + base);
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 u = s1p[h], v = s2p[h];
+            s1[2 * h] = u.x, s1[2 * h + 1] = u.y, s2[2 * h] = v.x, s2[2 * h + 1] = v.y;
+        }
+    } else {
+        for (int q = 0; q < 8; ++q) s1[q] = s2[q] = 0ull;
+    }
+    const int wobs = wave_sum(nobs);
+    as.obs += (unsigned long long)wobs;
+    if (fresh) as.fresh += (unsigned long long)wobs;
+    if (lane == 0) m.btouch[id] = 0u;
+    float D[8], S2[8];
+    uint32_t W[8];
+    bool have = false;
+    if (fresh) {
+        for (int q = 0; q < 8; ++q) D[q] = 0.f, S2[q] = 0.f, W[q] = 0u;
+        have = true;
+    } else if (upd) {
+        Store<ST>::get8(m, base, D, W, S2);
+        have = true;
+    }
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        for (int q = 0; q < 8; ++q) {
+            if (!(upd & (1u << q))) continue;
+            const double before = var_term(m, W[q], S2[q]);
+            const int cb = var_count(m, W[q]);
+            apply_stats(m, ns[q], nb[q], s1[q], s2[q], D[q], W[q], S2[q]);
+            Store<ST>::round(m, D[q], W[q], S2[q]);
+            dsum += var_term(m, W[q], S2[q]) - before;
+            dcnt += var_count(m, W[q]) - cb;
+        }
+        // leave the accumulators at zero for the next scan
+        uint4* a = reinterpret_cast<uint4*>(m.acc_sat[0] + base);
+        uint4* b = reinterpret_cast<uint4*>(m.acc_band[0] + base);
+        a[0] = a[1] = make_uint4(0, 0, 0, 0);
+        if (any_band) {
+            b[0] = b[1] = make_uint4(0, 0, 0, 0);
+            ulonglong2* s1p = reinterpret_cast<ulonglong2*>(m.acc_s1[0] + base);
+            ulonglong2* s2p = reinterpret_cast<ulonglong2*>(m.acc_s2[0] + base);
+            for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
+        }
+    }
+    as.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
+}
+
+// Level-1 block: lane l owns the voxel at Morton position l.
+template <int ST>
+__device__ inline void apply_level1(const DevMap& m, uint32_t id, TaskStats& as) {
+    const int lane = lane_id();
+    const uint32_t info = m.binfo[id];
+    const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
+    uint32_t ns, nb;
+    unsigned long long s1, s2;
+    take_accumulators(m, 1, at, ns, nb, s1, s2);
+    if (lane == 0) m.btouch[id] = 0u;
+    const bool upd = ns + nb > 0;
+    const int wobs = wave_sum((int)(ns + nb));
+    as.obs += (unsigned long long)wobs;
+    float D, S2;
+    uint32_t W;
+    Store<ST>::get(m, 1, at, D, W, S2);
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        apply_stats(m, ns, nb, s1, s2, D, W, S2);
+        Store<ST>::round(m, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    }
+    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt);
+}
+
+// 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
+template <int ST>
+__device__ inline void apply_packed(const DevMap& m, const uint32_t* list, uint32_t count, uint32_t group, int level,
+                                    TaskStats& as) {
+    const int lane = lane_id();
+    const int seg = level == 2 ? 8 : 1;
+    const uint32_t bi = group * (uint32_t)(64 / seg) + (uint32_t)(lane / seg);
+    const bool live = bi < count;
+    uint32_t id = 0, info = 0, ns = 0, nb = 0;
+    unsigned long long s1 = 0ull, s2 = 0ull;
+    float D = 0.f, S2 = 0.f;
+    uint32_t W = 0;
+    if (live) {
+        id = list[bi];
+        info = m.binfo[id];
+        const size_t at = (size_t)(info & kSlotMask) * seg + (lane % seg);
+        take_accumulators(m, level, at, ns, nb, s1, s2);
+        if (lane % seg == 0) m.btouch[id] = 0u;
+        Store<ST>::get(m, level, at, D, W, S2);
+    }
+    const bool upd = ns + nb > 0;
+    as.lane_obs += (unsigned long long)(ns + nb);
+    double dsum = 0.0;
+    int dcnt = 0;
+    if (upd) {
+        const double before = var_term(m, W, S2);
+        const int cb = var_count(m, W);
+        apply_stats(m, ns, nb, s1, s2, D, W, S2);
+        Store<ST>::round(m, D, W, S2);
+        dsum = var_term(m, W, S2) - before;
+        dcnt = var_count(m, W) - cb;
+    }
+    as.lane_merges += (unsigned long long)finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0,
+                                                            dsum, dcnt);
+}
+
+// One update task t of a scan whose queues hold n0..n3 blocks per level.
+template <int ST>
+__device__ inline void points_update_task(const DevMap& m, uint32_t t, const uint32_t n[4], TaskStats& as) {
+    const uint32_t g2 = (n[2] + 7) / 8;
+    if (t < n[0]) apply_fine<ST>(m, m.vis[0][t], as);
+    else if (t < n[0] + n[1]) apply_level1<ST>(m, m.vis[1][t - n[0]], as);
+    else if (t < n[0] + n[1] + g2) apply_packed<ST>(m, m.vis[2], n[2], t - n[0] - n[1], 2, as);
+    else apply_packed<ST>(m, m.vis[3], n[3], t - n[0] - n[1] - g2, 3, as);
+}
+
+}  // namespace mrh

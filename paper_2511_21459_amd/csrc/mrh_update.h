@@ -1,13 +1,15 @@
-// Per-block voxel-state helpers shared by the RGB-D and LiDAR update kernels: FP32 state I/O,
-// the running mean / Welford update (Eq. 3, Eq. 5), the block mean-variance bookkeeping (Eq. 6
-// averaged over a block) and the merging criterion of Sec. 3.2.1 with 2x2x2 pooling.
+// Per-block voxel-state helpers shared by the RGB-D and LiDAR update kernels: the running mean /
+// Welford update (Eq. 3, Eq. 5) in FP32 registers, the block mean-variance bookkeeping (Eq. 6
+// averaged over a block) and the merging criterion of Sec. 3.2.1 with 2x2x2 pooling, for every
+// storage format (template parameter ST, see mrh_store.h).  The variance bookkeeping always uses
+// the values as stored (after the format's rounding) so that it stays consistent across frames.
 //
 // Work split: one wave per block.  A level-0 block (8^3 voxels, Morton order) gives lane l the
 // 8 contiguous voxels 8l .. 8l+7, which are the children of coarse voxel l; a level n >= 1 block
 // (at most 64 voxels) gives lane l the voxel at Morton position l.
 #pragma once
 
-#include "mrh_internal.h"
+#include "mrh_store.h"
 
 namespace mrh {
 
@@ -46,33 +48,10 @@ __device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
     m.pend[level][p] = slot;
 }
 
-__device__ inline void load_group(const DevMap& m, size_t base, float D[8], uint32_t W[8], float S2[8]) {
-    const float4* dp = reinterpret_cast<const float4*>(m.D[0] + base);
-    const uint4* wp = reinterpret_cast<const uint4*>(m.W[0] + base);
-    const float4* sp = reinterpret_cast<const float4*>(m.S2[0] + base);
-    const float4 d0 = dp[0], d1 = dp[1], s0 = sp[0], s1 = sp[1];
-    const uint4 w0 = wp[0], w1 = wp[1];
-    D[0] = d0.x, D[1] = d0.y, D[2] = d0.z, D[3] = d0.w, D[4] = d1.x, D[5] = d1.y, D[6] = d1.z, D[7] = d1.w;
-    S2[0] = s0.x, S2[1] = s0.y, S2[2] = s0.z, S2[3] = s0.w, S2[4] = s1.x, S2[5] = s1.y, S2[6] = s1.z, S2[7] = s1.w;
-    W[0] = w0.x, W[1] = w0.y, W[2] = w0.z, W[3] = w0.w, W[4] = w1.x, W[5] = w1.y, W[6] = w1.z, W[7] = w1.w;
-}
-
-__device__ inline void store_group(const DevMap& m, size_t base, const float D[8], const uint32_t W[8],
-                                   const float S2[8]) {
-    float4* dp = reinterpret_cast<float4*>(m.D[0] + base);
-    uint4* wp = reinterpret_cast<uint4*>(m.W[0] + base);
-    float4* sp = reinterpret_cast<float4*>(m.S2[0] + base);
-    dp[0] = make_float4(D[0], D[1], D[2], D[3]);
-    dp[1] = make_float4(D[4], D[5], D[6], D[7]);
-    wp[0] = make_uint4(W[0], W[1], W[2], W[3]);
-    wp[1] = make_uint4(W[4], W[5], W[6], W[7]);
-    sp[0] = make_float4(S2[0], S2[1], S2[2], S2[3]);
-    sp[1] = make_float4(S2[4], S2[5], S2[6], S2[7]);
-}
-
 // End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
 // sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
 // written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
+template <int ST>
 __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
                                    bool have, bool dirty, int nupd, double dsum, int dcnt) {
     const int lane = lane_id();
@@ -90,7 +69,7 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
         merge = cslot >= 0;
     }
     if (!merge) {
-        if (dirty) store_group(m, base, D, W, S2);
+        if (dirty) Store<ST>::put8(m, base, D, W, S2);
         if (lane == 0) {
             m.bvsum[id] = vsum;
             m.bvcnt[id] = vcnt;
@@ -98,7 +77,7 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
         }
         return 0;
     }
-    if (!have) load_group(m, base, D, W, S2);
+    if (!have) Store<ST>::get8(m, base, D, W, S2);
     // pool the 8 children: total weight, weighted mean TSDF, summed S2
     uint32_t Wc = 0;
     float sd = 0.f, s2 = 0.f;
@@ -108,12 +87,10 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
         sd += (float)W[q] * D[q];
         s2 += S2[q];
     }
-    const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
-    const float Sc = Wc > 0 ? s2 : 0.f;
-    const size_t cb = (size_t)cslot * 64 + lane;
-    m.D[1][cb] = Dc;
-    m.W[1][cb] = Wc;
-    m.S2[1][cb] = Sc;
+    float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+    float Sc = Wc > 0 ? s2 : 0.f;
+    Store<ST>::round(m, Dc, Wc, Sc);
+    Store<ST>::put(m, 1, (size_t)cslot * 64 + lane, Dc, Wc, Sc);
     const double csum = wave_sum(var_term(m, Wc, Sc));
     const int ccnt = wave_sum(var_count(m, Wc));
     if (lane == 0) {
@@ -127,6 +104,7 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
 
 // End of a level-1 block's update (lane = Morton position).  The 8 children of a coarse voxel are
 // 8 consecutive lanes.  Returns 1 when the block merged.
+template <int ST>
 __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
                                      float S2, bool dirty, int nupd, double dsum, int dcnt) {
     const int lane = lane_id();
@@ -145,11 +123,7 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
         merge = cslot >= 0;
     }
     if (!merge) {
-        if (dirty && lane < nv) {
-            m.D[level][at] = D;
-            m.W[level][at] = W;
-            m.S2[level][at] = S2;
-        }
+        if (dirty && lane < nv) Store<ST>::put(m, level, at, D, W, S2);
         if (lane == 0) {
             m.bvsum[id] = vsum;
             m.bvcnt[id] = vcnt;
@@ -164,14 +138,10 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
         s2 += __shfl_xor(s2, o);
     }
     const bool writer = lane < nv && (lane & 7) == 0;
-    const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
-    const float Sc = Wc > 0 ? s2 : 0.f;
-    if (writer) {
-        const size_t cbase = (size_t)cslot * (size_t)(nv / 8) + (size_t)(lane >> 3);
-        m.D[level + 1][cbase] = Dc;
-        m.W[level + 1][cbase] = Wc;
-        m.S2[level + 1][cbase] = Sc;
-    }
+    float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+    float Sc = Wc > 0 ? s2 : 0.f;
+    Store<ST>::round(m, Dc, Wc, Sc);
+    if (writer) Store<ST>::put(m, level + 1, (size_t)cslot * (size_t)(nv / 8) + (size_t)(lane >> 3), Dc, Wc, Sc);
     const double csum = wave_sum(writer ? var_term(m, Wc, Sc) : 0.0);
     const int ccnt = wave_sum(writer ? var_count(m, Wc) : 0);
     if (lane == 0) {
@@ -186,6 +156,7 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
 // Packed coarse blocks: `seg` consecutive lanes (8 for level 2, 1 for level 3) hold one block's
 // voxels, lane % seg = Morton position.  All reductions stay inside the segment.  Returns, on the
 // segment's first lane, 1 when its block merged.
+template <int ST>
 __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uint32_t info, int level, int seg, float D,
                                     uint32_t W, float S2, bool dirty, int nupd, double dsum, int dcnt) {
     const int lane = lane_id();
@@ -208,12 +179,7 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
     merge = merge && cslot >= 0;
     const uint32_t slot = info & kSlotMask;
     if (!merge) {
-        if (live && dirty) {
-            const size_t at = (size_t)slot * seg + (lane % seg);
-            m.D[level][at] = D;
-            m.W[level][at] = W;
-            m.S2[level][at] = S2;
-        }
+        if (live && dirty) Store<ST>::put(m, level, (size_t)slot * seg + (lane % seg), D, W, S2);
         if (live && leader) {
             m.bvsum[id] = vsum;
             m.bvcnt[id] = vcnt;
@@ -229,11 +195,10 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
         s2 += __shfl_xor(s2, o);
     }
     if (leader) {
-        const float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
-        const float Sc = Wc > 0 ? s2 : 0.f;
-        m.D[level + 1][cslot] = Dc;
-        m.W[level + 1][cslot] = Wc;
-        m.S2[level + 1][cslot] = Sc;
+        float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+        float Sc = Wc > 0 ? s2 : 0.f;
+        Store<ST>::round(m, Dc, Wc, Sc);
+        Store<ST>::put(m, level + 1, (size_t)cslot, Dc, Wc, Sc);
         m.bvsum[id] = var_term(m, Wc, Sc);
         m.bvcnt[id] = (uint32_t)var_count(m, Wc);
         m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
@@ -241,6 +206,73 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
         return 1;
     }
     return 0;
+}
+
+// Statistics gathered by one wave over its tasks: obs / fresh / merges[0..1] are wave-uniform,
+// lane_obs / lane_merges (packed blocks) are per lane.
+struct TaskStats {
+    unsigned long long obs = 0, fresh = 0, merges[2] = {0, 0}, lane_obs = 0, lane_merges = 0;
+};
+
+__device__ inline uint32_t update_task_count(const uint32_t n[4]) { return n[0] + n[1] + (n[2] + 7) / 8 + (n[3] + 63) / 64; }
+
+// flush one wave's statistics (lane 0 adds wave-uniform and lane-summed parts)
+__device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
+    const unsigned long long lane_obs = wave_sum(ts.lane_obs), lane_merges = wave_sum(ts.lane_merges);
+    if (lane_id() == 0) {
+        stat_add(m, S_OBS, ts.obs + lane_obs);
+        stat_add(m, S_OBS_FRESH, ts.fresh);
+        stat_add(m, S_MERGE0, ts.merges[0]);
+        stat_add(m, S_MERGE1, ts.merges[1]);
+        stat_add(m, S_MERGE2, lane_merges);
+    }
+}
+
+// Queue block `id` for this frame's update on the list of its level (lanes with level < 0 queue
+// nothing).  Called by every lane of the wave; one atomic per level per wave.
+__device__ inline void queue_block(const DevMap& m, int level, uint32_t id) {
+    const int lane = lane_id();
+    for (int lv = 0; lv < 4; ++lv) {
+        const unsigned long long msk = __ballot(level == lv);
+        if (!msk) continue;
+        const int f0 = __ffsll((long long)msk) - 1;
+        uint32_t vb = 0;
+        if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[lv], (uint32_t)__popcll(msk));
+        vb = (uint32_t)__shfl((int)vb, f0);
+        if (level == lv) m.vis[lv][vb + rank_in_mask(msk)] = id;
+    }
+}
+
+// End of a frame for one map, by one workgroup: return the slots freed by merges to their levels'
+// stacks, publish the frame's statistics, empty the update queues, note the block count.
+__device__ inline void finalize_map(const DevMap& m) {
+    DevCounters* c = m.ctr;
+    for (int n = 0; n < m.levels; ++n) {
+        const uint32_t p = c->pending[n];
+        if (p == 0) continue;
+        const int32_t top = c->top[n];
+        for (uint32_t i = threadIdx.x; i < p; i += blockDim.x) m.stack[n][top + i] = m.pend[n][i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            c->top[n] = top + (int32_t)p;
+            c->pending[n] = 0;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < S_COUNT) {
+        unsigned long long v = 0;
+        for (int k = 0; k < kStripes; ++k) {
+            v += c->frame[k][threadIdx.x];
+            c->frame[k][threadIdx.x] = 0;
+        }
+        c->last[threadIdx.x] = v;
+        c->total[threadIdx.x] += v;
+    }
+    if (threadIdx.x == 0) {
+        c->frames += 1;
+        for (int n = 0; n < 4; ++n) c->vis_n[n] = 0;
+        c->n_prev = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
+    }
 }
 
 // Wave-cooperative insert of one key per lane (has_key).  Keys found by a read-only probe need

@@ -1,345 +1,34 @@
-// LiDAR fusion (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3 and Eq. 5; Sec. 3.2.1 merging criterion).
+// LiDAR fusion of one map (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3, Eq. 5; Sec. 3.2.1).
 //
-// One scan is four launches on the map's stream:
-//   k_alloc_points  one thread per point: validity, segment [o, p + tau n] (carving) or the band
-//                   [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated insert
-//   k_rays          one thread per point: the same block walk; inside each block a walk over the
-//                   block's own voxel lattice; each crossed voxel gets clip((p - x) . n, -tau, tau).
-//                   Saturated observations (+tau) only bump an integer count; the others add to
-//                   fixed-point sums of (d - D) and (d - D)^2, D being the voxel's mean at the start
-//                   of the scan, so the accumulation is exact and order-independent
-//   k_apply_points  one wave per touched block: merges each voxel's scan statistics into its state
-//                   (W' = W + n, D' = D + s1 / W', S2' = S2 + s2 - s1^2 / W', the batch form of
-//                   Eq. 3 and Eq. 5), then the block variance bookkeeping and the merging criterion
-//   k_finalize      freed slots back to their stacks, statistics
+// One scan is four launches on the map's stream: k_alloc_points, k_rays, k_apply_points (update
+// tasks over the per-level queues of touched blocks), k_finalize.
 #include <cmath>
 
-#include "mrh_update.h"
+#include "mrh_points.h"
 
 namespace mrh {
 
 void launch_finalize(mrh_map* m);
 
-constexpr double kS1Scale = 16777216.0;                 // 2^24 per metre
-constexpr double kS2Scale = 281474976710656.0;          // 2^48 per square metre
+__global__ __launch_bounds__(256) void k_alloc_points(DevMap m, ScanParams sp) { points_alloc_chunk(m, sp, blockIdx.x); }
 
-struct ScanParams {
-    Pose P;
-};
-
-__device__ inline bool point_segment(const DevMap& m, const ScanParams& sp, const float* __restrict__ xyz, int64_t i,
-                                     double a[3], double e[3], double p[3], double n[3]) {
-    const double ps[3] = {(double)xyz[3 * i], (double)xyz[3 * i + 1], (double)xyz[3 * i + 2]};
-    if (!(__builtin_isfinite(ps[0]) && __builtin_isfinite(ps[1]) && __builtin_isfinite(ps[2]))) return false;
-    const double r2 = (ps[0] * ps[0] + ps[1] * ps[1]) + ps[2] * ps[2];
-    if (!(r2 >= m.r2lo && r2 <= m.r2hi)) return false;
-    pose_apply(sp.P, ps, p);
-    unit_direction(p, sp.P.t, n);
-    for (int k = 0; k < 3; ++k) {
-        a[k] = m.carve ? sp.P.t[k] : p[k] - m.tau * n[k];
-        e[k] = p[k] + m.tau * n[k];
-    }
-    return true;
+template <int ST>
+__global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp) {
+    points_ray_chunk<ST>(m, sp, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_alloc_points(DevMap m, ScanParams sp, const float* __restrict__ xyz,
-                                                      int64_t n) {
-    const int lane = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double a[3], e[3], p[3], nn[3];
-    bool ok = i < n && point_segment(m, sp, xyz, i, a, e, p, nn);
-    const unsigned long long vmask = __ballot(ok);
-    bool in_range = ok && segment_in_range(a, e, m.invB);
-    const unsigned long long dmask = __ballot(ok && !in_range);
-    if (lane == 0) {
-        stat_add(m, S_VALID, (unsigned long long)__popcll(vmask));
-        stat_add(m, S_DROPPED, (unsigned long long)__popcll(dmask));
-    }
-    Walk w;
-    if (in_range) w.init(a, e, m.invB);
-    bool active = in_range;
-    while (__ballot(active)) {
-        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
-        insert_keys(m, active, key, false);
-        if (active) active = w.next();
-    }
-}
-
-// Accumulate one observation d of the voxel at heap position `at` of `level`.
-__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d) {
-    if (d >= m.tau) {
-        atomicAdd(&m.acc_sat[level][at], 1u);
-        return;
-    }
-    const double Dp = fresh ? 0.0 : (double)m.D[level][at];
-    const double r = d - Dp;
-    atomicAdd(&m.acc_band[level][at], 1u);
-    atomicAdd(&m.acc_s1[level][at], (unsigned long long)(long long)__builtin_rint(r * kS1Scale));
-    atomicAdd(&m.acc_s2[level][at], (unsigned long long)__builtin_rint((r * r) * kS2Scale));
-}
-
-// The block walk restricted to one block: the segment is clipped to the block's box, the walk
-// starts in the (clamped) cell of the clipped entry point and steps on the block's own lattice of
-// side^3 voxels until it leaves the block or passes the clipped exit parameter.
-struct BoxWalk {
-    double A0, A1, A2, iD0, iD1, iD2, t0, t1, t2, tout;
-    int c0, c1, c2, s0, s1, s2, side;
-
-    __device__ static inline void axis(double a, double e, double ob, double inv_nu, int side, double& A, double& D,
-                                       double& iD, int& st, double& tin, double& tout) {
-        A = (a - ob) * inv_nu;
-        const double El = (e - ob) * inv_nu;
-        D = El - A;
-        if (D != 0.0) {
-            iD = 1.0 / D;
-            const double nearb = D > 0.0 ? 0.0 : (double)side;
-            const double farb = D > 0.0 ? (double)side : 0.0;
-            const double ta = (nearb - A) * iD;
-            const double tb = (farb - A) * iD;
-            if (ta > tin) tin = ta;
-            if (tb < tout) tout = tb;
-            st = D > 0.0 ? 1 : -1;
-        } else {
-            iD = 0.0;
-            st = 0;
-        }
-    }
-    __device__ static inline void start(double A, double D, double iD, int st, double tin, int side, int& c, double& t) {
-        double fl = __builtin_floor(A + tin * D);
-        if (fl < 0.0) fl = 0.0;
-        if (fl > (double)(side - 1)) fl = (double)(side - 1);
-        c = (int)fl;
-        t = st != 0 ? ((double)(c + (st > 0 ? 1 : 0)) - A) * iD : __builtin_inf();
-    }
-    __device__ inline void init(const double a[3], const double e[3], const int64_t b[3], double B, double inv_nu,
-                                int side_) {
-        side = side_;
-        double D0, D1, D2, tin = 0.0;
-        tout = 1.0;
-        axis(a[0], e[0], (double)b[0] * B, inv_nu, side, A0, D0, iD0, s0, tin, tout);
-        axis(a[1], e[1], (double)b[1] * B, inv_nu, side, A1, D1, iD1, s1, tin, tout);
-        axis(a[2], e[2], (double)b[2] * B, inv_nu, side, A2, D2, iD2, s2, tin, tout);
-        start(A0, D0, iD0, s0, tin, side, c0, t0);
-        start(A1, D1, iD1, s1, tin, side, c1, t1);
-        start(A2, D2, iD2, s2, tin, side, c2, t2);
-    }
-    __device__ inline bool next() {
-        double tm = t0;
-        int k = 0;
-        if (t1 < tm) tm = t1, k = 1;
-        if (t2 < tm) tm = t2, k = 2;
-        if (!(tm <= tout)) return false;
-        if (k == 0) {
-            c0 += s0;
-            if (c0 < 0 || c0 >= side) return false;
-            t0 = ((double)(c0 + (s0 > 0 ? 1 : 0)) - A0) * iD0;
-        } else if (k == 1) {
-            c1 += s1;
-            if (c1 < 0 || c1 >= side) return false;
-            t1 = ((double)(c1 + (s1 > 0 ? 1 : 0)) - A1) * iD1;
-        } else {
-            c2 += s2;
-            if (c2 < 0 || c2 >= side) return false;
-            t2 = ((double)(c2 + (s2 > 0 ? 1 : 0)) - A2) * iD2;
-        }
-        return true;
-    }
-};
-
-__global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp, const float* __restrict__ xyz, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double a[3], e[3], p[3], nn[3];
-    if (!(i < n && point_segment(m, sp, xyz, i, a, e, p, nn) && segment_in_range(a, e, m.invB))) return;
-    Walk w;
-    w.init(a, e, m.invB);
-    do {
-        const int64_t b[3] = {w.c0, w.c1, w.c2};
-        const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
-        if (id == kInvalidId) continue;
-        const uint32_t info = m.binfo[id];
-        if (info & kNoBlockBit) continue;
-        m.btouch[id] = 1u;
-        const int level = (int)((info >> kLevelShift) & 3u);
-        const bool fresh = (info & kNewBit) != 0;
-        const int side = 8 >> level;
-        const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
-        const double nu = m.nu[level];
-        BoxWalk bw;
-        bw.init(a, e, b, m.B, m.inv_nu[level], side);
-        for (int s = 0;; ++s) {
-            // observation of the voxel centre (Eq. 1)
-            const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
-            const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
-            const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
-            const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
-            const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
-            accumulate(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d);
-            if (s == 3 * side || !bw.next()) break;
-        }
-    } while (w.next());
-}
-
-// Batch form of Eq. 3 and Eq. 5 for n observations with sums s1, s2 of (d - D) and (d - D)^2.
-__device__ inline void apply_stats(const DevMap& m, uint32_t nsat, uint32_t nband, unsigned long long s1q,
-                                   unsigned long long s2q, float& D, uint32_t& W, float& S2) {
-    const uint32_t nobs = nsat + nband;
-    const double Dp = (double)D;
-    const double ts = m.tau - Dp;
-    const double s1 = (double)nsat * ts + (double)(long long)s1q / kS1Scale;
-    const double s2 = (double)nsat * (ts * ts) + (double)s2q / kS2Scale;
-    const double Wn = (double)W + (double)nobs;
-    const double S2n = (double)S2 + s2 - s1 * s1 / Wn;
-    D = (float)(Dp + s1 / Wn);
-    S2 = (float)(S2n > 0.0 ? S2n : 0.0);
-    W = W + nobs;
-}
-
-// Statistics gathered by one wave over its blocks (wave-uniform).
-struct ApplyStats {
-    unsigned long long obs = 0, fresh = 0, merges[3] = {0, 0, 0};
-};
-
-__device__ inline void apply_fine(const DevMap& m, uint32_t id, uint32_t info, ApplyStats& as) {
-    const int lane = lane_id();
-    const bool fresh = (info & kNewBit) != 0;
-    const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
-    uint32_t ns[8], nb[8];
-    unsigned long long s1[8], s2[8];
-    {
-        const uint4* a = reinterpret_cast<const uint4*>(m.acc_sat[0] + base);
-        const uint4* b = reinterpret_cast<const uint4*>(m.acc_band[0] + base);
-        const uint4 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
-        ns[0] = a0.x, ns[1] = a0.y, ns[2] = a0.z, ns[3] = a0.w, ns[4] = a1.x, ns[5] = a1.y, ns[6] = a1.z, ns[7] = a1.w;
-        nb[0] = b0.x, nb[1] = b0.y, nb[2] = b0.z, nb[3] = b0.w, nb[4] = b1.x, nb[5] = b1.y, nb[6] = b1.z, nb[7] = b1.w;
-    }
-    uint32_t upd = 0;
-    int nobs = 0;
-    for (int q = 0; q < 8; ++q) {
-        if (ns[q] + nb[q]) upd |= 1u << q;
-        nobs += (int)(ns[q] + nb[q]);
-    }
-    bool any_band = false;
-    for (int q = 0; q < 8; ++q) any_band |= nb[q] != 0;
-    if (any_band) {
-        const ulonglong2* s1p = reinterpret_cast<const ulonglong2*>(m.acc_s1[0] + base);
-        const ulonglong2* s2p = reinterpret_cast<const ulonglong2*>(m.acc_s2[0] + base);
-        for (int h = 0; h < 4; ++h) {
-            const ulonglong2 u = s1p[h], v = s2p[h];
-            s1[2 * h] = u.x, s1[2 * h + 1] = u.y, s2[2 * h] = v.x, s2[2 * h + 1] = v.y;
-        }
-    } else {
-        for (int q = 0; q < 8; ++q) s1[q] = s2[q] = 0ull;
-    }
-    const int wobs = wave_sum(nobs);
-    as.obs += (unsigned long long)wobs;
-    if (fresh) as.fresh += (unsigned long long)wobs;
-    float D[8], S2[8];
-    uint32_t W[8];
-    bool have = false;
-    if (fresh) {
-        for (int q = 0; q < 8; ++q) D[q] = 0.f, S2[q] = 0.f, W[q] = 0u;
-        have = true;
-    } else if (upd) {
-        load_group(m, base, D, W, S2);
-        have = true;
-    }
-    double dsum = 0.0;
-    int dcnt = 0;
-    if (upd) {
-        for (int q = 0; q < 8; ++q) {
-            if (!(upd & (1u << q))) continue;
-            const double before = var_term(m, W[q], S2[q]);
-            const int cb = var_count(m, W[q]);
-            apply_stats(m, ns[q], nb[q], s1[q], s2[q], D[q], W[q], S2[q]);
-            dsum += var_term(m, W[q], S2[q]) - before;
-            dcnt += var_count(m, W[q]) - cb;
-        }
-        // leave the accumulators at zero for the next scan
-        uint4* a = reinterpret_cast<uint4*>(m.acc_sat[0] + base);
-        uint4* b = reinterpret_cast<uint4*>(m.acc_band[0] + base);
-        a[0] = a[1] = make_uint4(0, 0, 0, 0);
-        if (any_band) {
-            b[0] = b[1] = make_uint4(0, 0, 0, 0);
-            ulonglong2* s1p = reinterpret_cast<ulonglong2*>(m.acc_s1[0] + base);
-            ulonglong2* s2p = reinterpret_cast<ulonglong2*>(m.acc_s2[0] + base);
-            for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
-        }
-    }
-    as.merges[0] += (unsigned long long)finish_fine(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
-}
-
-// A level >= 1 block, one voxel per lane (lanes beyond the block's voxel count idle).
-__device__ inline void apply_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, ApplyStats& as) {
-    const int lane = lane_id();
-    const int side = 8 >> level, nv = side * side * side;
-    const size_t at = (size_t)(info & kSlotMask) * nv + lane;
-    uint32_t ns = 0, nb = 0;
-    if (lane < nv) {
-        ns = m.acc_sat[level][at];
-        nb = m.acc_band[level][at];
-    }
-    const bool upd = ns + nb > 0;
-    const int wobs = wave_sum((int)(ns + nb));
-    if (wobs == 0) return;
-    as.obs += (unsigned long long)wobs;
-    float D = 0.f, S2 = 0.f;
-    uint32_t W = 0;
-    if (lane < nv) {
-        D = m.D[level][at];
-        W = m.W[level][at];
-        S2 = m.S2[level][at];
-    }
-    double dsum = 0.0;
-    int dcnt = 0;
-    if (upd) {
-        unsigned long long s1 = 0ull, s2 = 0ull;
-        if (nb) {
-            s1 = m.acc_s1[level][at];
-            s2 = m.acc_s2[level][at];
-            m.acc_band[level][at] = 0u;
-            m.acc_s1[level][at] = 0ull;
-            m.acc_s2[level][at] = 0ull;
-        }
-        m.acc_sat[level][at] = 0u;
-        const double before = var_term(m, W, S2);
-        const int cb = var_count(m, W);
-        apply_stats(m, ns, nb, s1, s2, D, W, S2);
-        dsum = var_term(m, W, S2) - before;
-        dcnt = var_count(m, W) - cb;
-    }
-    if (level == 1) {
-        as.merges[1] += (unsigned long long)finish_coarse(m, id, info, level, D, W, S2, upd, wobs, dsum, dcnt);
-    } else {
-        const int seg = level == 2 ? 8 : 1;
-        // lanes beyond the block's voxels carry no state; only the first segment is live
-        const int merged = finish_packed(m, lane < seg, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum, dcnt);
-        as.merges[2] += (unsigned long long)__shfl(merged, 0);
-    }
-}
-
+template <int ST>
 __global__ __launch_bounds__(256) void k_apply_points(DevMap m) {
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t nb0 = m.ctr->n_blocks;
-    const uint32_t nb = nb0 < m.max_blocks ? nb0 : m.max_blocks;
-    ApplyStats as;
-    for (uint32_t id = wave; id < nb; id += nwaves) {
-        if (m.btouch[id] == 0u) continue;
-        const uint32_t info = m.binfo[id];
-        if (lane_id() == 0) m.btouch[id] = 0u;
-        if (info & kNoBlockBit) continue;
-        const int level = (int)((info >> kLevelShift) & 3u);
-        if (level == 0) apply_fine(m, id, info, as);
-        else apply_coarse(m, id, info, level, as);
-    }
-    if (lane_id() == 0) {
-        stat_add(m, S_OBS, as.obs);
-        stat_add(m, S_OBS_FRESH, as.fresh);
-        for (int n = 0; n < 3; ++n) stat_add(m, S_MERGE0 + n, as.merges[n]);
-    }
+    const uint32_t n[4] = {m.ctr->vis_n[0], m.ctr->vis_n[1], m.ctr->vis_n[2], m.ctr->vis_n[3]};
+    const uint32_t ntask = update_task_count(n);
+    TaskStats as;
+    for (uint32_t t = wave; t < ntask; t += nwaves) points_update_task<ST>(m, t, n, as);
+    flush_task_stats(m, as);
 }
 
-static mrh_status ensure_lidar(mrh_map* map) {
+mrh_status ensure_lidar(mrh_map* map) {
     if (map->lidar_ready) return MRH_OK;
     DevMap& d = map->dm;
     mrh_status st = MRH_OK;
@@ -368,18 +57,43 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
     if (!map || !T_ws || n < 0 || (n > 0 && !xyz_dev)) return MRH_ERR_INVALID_ARG;
     ScanParams sp;
     if (!pose_from(T_ws, sp.P)) return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose");
+    sp.xyz = xyz_dev;
+    sp.n = n;
     mrh_status st = ensure_lidar(map);
     if (st != MRH_OK) return st;
     if (n > 0) {
         const unsigned grid = (unsigned)((n + 255) / 256);
-        launch(map, K_ALLOC_POINTS, [&] {
-            hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dm, sp, xyz_dev, n);
+        launch(map, K_ALLOC_POINTS,
+               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); });
+        launch(map, K_RAYS, [&] {
+            switch (map->cfg.storage) {
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_rays<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); break;
+                default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp);
+            }
         });
-        launch(map, K_RAYS,
-               [&] { hipLaunchKernelGGL(k_rays, dim3(grid), dim3(256), 0, map->stream, map->dm, sp, xyz_dev, n); });
-        launch(map, K_APPLY_POINTS,
-               [&] { hipLaunchKernelGGL(k_apply_points, dim3(2048), dim3(256), 0, map->stream, map->dm); });
+        launch(map, K_APPLY_POINTS, [&] {
+            const dim3 g(1024), b(256);
+            switch (map->cfg.storage) {
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F16>, g, b, 0, map->stream, map->dm); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_BF16>, g, b, 0, map->stream, map->dm); break;
+                default: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F32>, g, b, 0, map->stream, map->dm);
+            }
+        });
     }
     launch_finalize(map);
     return check_hip(map, hipGetLastError(), "integrate_points");
+}
+
+extern "C" mrh_status mrh_integrate_points_sequence(mrh_map* map, const float* xyz_dev, int32_t n_frames, int64_t n,
+                                                    const double* T_ws) {
+    if (!map || !T_ws || n_frames < 0 || n < 0 || (n > 0 && !xyz_dev)) return MRH_ERR_INVALID_ARG;
+    Pose P;
+    for (int32_t k = 0; k < n_frames; ++k)
+        if (!pose_from(T_ws + 16 * k, P)) return set_error(map, MRH_ERR_INVALID_ARG, "scan %d: non-finite pose", k);
+    for (int32_t k = 0; k < n_frames; ++k) {
+        const mrh_status st = mrh_integrate_points(map, xyz_dev + (size_t)3 * (size_t)n * (size_t)k, n, T_ws + 16 * k);
+        if (st != MRH_OK) return st;
+    }
+    return MRH_OK;
 }

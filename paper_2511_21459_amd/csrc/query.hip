@@ -6,7 +6,7 @@
 // remaining trilinear weights are renormalised.  Lattice indices and weights are FP64.
 #include <cmath>
 
-#include "mrh_internal.h"
+#include "mrh_store.h"
 
 namespace mrh {
 
@@ -22,6 +22,7 @@ struct QueryResult {
     double grad[3];  // d sdf / d x (world)
 };
 
+template <int ST>
 __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bool strict) {
     QueryResult q;
     q.valid = false;
@@ -86,9 +87,9 @@ __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bo
         }
         const int m2 = 8 >> n2;
         const size_t at = (size_t)(binf & kSlotMask) * (size_t)(m2 * m2 * m2) + (size_t)morton3(idx[0], idx[1], idx[2]);
-        const uint32_t W = m.W[n2][at];
+        const uint32_t W = Store<ST>::getW(m, n2, at);
         if (W == 0) continue;
-        cd[c] = (double)m.D[n2][at];
+        cd[c] = (double)Store<ST>::getD(m, n2, at);
         valid_mask |= 1u << c;
         wsum += cw[c];
         num += cw[c] * cd[c];
@@ -121,13 +122,14 @@ __device__ inline void world_point(const QueryParams& qp, const float* pts, int6
     }
 }
 
+template <int ST>
 __global__ __launch_bounds__(256) void k_query(DevMap m, QueryParams qp, const float* __restrict__ pts, int64_t n,
                                                float* sdf, uint8_t* valid, float* grad) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double x[3];
         world_point(qp, pts, i, x);
-        const QueryResult q = query_point(m, x, qp.strict != 0);
+        const QueryResult q = query_point<ST>(m, x, qp.strict != 0);
         sdf[i] = (float)q.sdf;
         valid[i] = q.valid ? 1 : 0;
         if (grad) {
@@ -140,6 +142,7 @@ __global__ __launch_bounds__(256) void k_query(DevMap m, QueryParams qp, const f
 
 // Backward: per point dL/dx = g_i * d sdf / dx; dL/dp = R^T dL/dx; pose terms (dL/dx, x cross
 // dL/dx) summed per thread, then per workgroup in a fixed order into FP64 partials.
+template <int ST>
 __global__ __launch_bounds__(256) void k_query_backward(DevMap m, QueryParams qp, const float* __restrict__ pts,
                                                         int64_t n, const float* __restrict__ gsdf, float* gpts,
                                                         double* partials) {
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(256) void k_query_backward(DevMap m, QueryParams qp
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double x[3];
         world_point(qp, pts, i, x);
-        const QueryResult q = query_point(m, x, qp.strict != 0);
+        const QueryResult q = query_point<ST>(m, x, qp.strict != 0);
         double g[3] = {0.0, 0.0, 0.0};
         if (q.valid) {
             const double gs = (double)gsdf[i];
@@ -213,8 +216,11 @@ extern "C" mrh_status mrh_query_sdf(mrh_map* map, const float* pts_dev, int64_t 
     const int64_t blocks = (n + 255) / 256;
     const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
     launch(map, K_QUERY, [&] {
-        hipLaunchKernelGGL(k_query, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev,
-                           valid_dev, grad_dev);
+        switch (map->cfg.storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_query<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
+            default: hipLaunchKernelGGL(k_query<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev);
+        }
     });
     return check_hip(map, hipGetLastError(), "query_sdf");
 }
@@ -231,8 +237,11 @@ extern "C" mrh_status mrh_query_sdf_backward(mrh_map* map, const float* pts_dev,
     const int64_t blocks = (n + 255) / 256;
     const int grid = (int)(blocks < map->partials_cap ? blocks : map->partials_cap);
     launch(map, K_QUERY_BACKWARD, [&] {
-        hipLaunchKernelGGL(k_query_backward, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n,
-                           grad_sdf_dev, grad_pts_dev, map->partials);
+        switch (map->cfg.storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
+            default: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials);
+        }
     });
     launch(map, K_REDUCE, [&] {
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, map->stream, map->partials, grid, map->pose_out);

@@ -40,9 +40,11 @@ def gpu_sorted(fmap) -> Sorted:
     return Sorted(keys[order], levels[order], new_offs, D[idx], W[idx], S2[idx])
 
 
-def excused_keys(orc_map) -> set:
-    keys, _, _ = orc_map.near_threshold()
-    return {tuple(k) for k in keys.tolist()}
+def excused_keys(orc_map, margin: float = 1e-3) -> set:
+    """Blocks whose merge decision the oracle took within `margin` (relative) of the threshold:
+    FP32 state decides such blocks within rounding, 1e-3; 16-bit state within its precision."""
+    keys, _, margins = orc_map.near_threshold()
+    return {tuple(k) for k, mg in zip(keys.tolist(), margins.tolist()) if mg < margin}
 
 
 def compare_maps(g: Sorted, o, tol_d: float = 1e-5, excused: set | None = None, tau: float = 0.15) -> dict:

@@ -1,0 +1,107 @@
+"""Batched fusion of independent maps: results identical to fusing each map alone (the per-map
+work is the same and deterministic), with and without graph replay; the autotuner resets maps."""
+import numpy as np
+import pytest
+import torch
+
+from parity_util import announce, gpu_sorted
+from workloads import configs, room_sequence, sphere_plane_frame, street_sequence
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mrh():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2511_21459_amd as mrh
+
+    return mrh
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _streams():
+    """Two RGB-D rooms of different sizes, one sphere-plane, two LiDAR streets of different sizes."""
+    r1 = room_sequence(width=320, height=240, f=262.5, frames=[0, 3, 6], scene_seed=101, noise_seed=201)
+    r2 = room_sequence(width=416, height=312, f=341.25, frames=[0, 3, 6], scene_seed=102, noise_seed=202)
+    sp = sphere_plane_frame(seed=3)
+    s1 = street_sequence(rings=16, azimuths=512, scans=[0, 1, 2], scene_seed=103, noise_seed=203)
+    s2 = street_sequence(rings=8, azimuths=1024, scans=[5, 6, 7], scene_seed=104, noise_seed=204)
+    room_cfg = dict(configs.ROOM, max_blocks=1 << 16, hash_slots=1 << 17)
+    street_cfg = dict(configs.STREET, max_blocks=1 << 18, hash_slots=1 << 19)
+    cfgs = [room_cfg, room_cfg, configs.SPHERE_PLANE, street_cfg, street_cfg]
+    frames = []
+    for k in range(3):
+        fr = [("depth", _dev(r1[0][k]), r1[1].K, r1[2][k]),
+              ("depth", _dev(r2[0][k]), r2[1].K, r2[2][k]),
+              ("depth", _dev(sp[0]), sp[1].K, sp[2]) if k != 1 else None,
+              ("points", _dev(s1[0][k]), s1[1][k]),
+              ("points", _dev(s2[0][k]), s2[1][k])]
+        frames.append(fr)
+    return cfgs, frames
+
+
+def _single(mrh, cfg, frames_of_map, storage="f32"):
+    m = mrh.Map(**dict(cfg, storage=storage))
+    for fr in frames_of_map:
+        if fr is None:
+            continue
+        if fr[0] == "depth":
+            m.integrate_depth(fr[1], fr[2], fr[3])
+        else:
+            m.integrate_points(fr[1], fr[2])
+    m.sync()
+    return gpu_sorted(m)
+
+
+def _same(a, b):
+    assert np.array_equal(a.keys, b.keys)
+    assert np.array_equal(a.levels, b.levels)
+    assert np.array_equal(a.W, b.W)
+    assert np.array_equal(a.D, b.D)
+    assert np.array_equal(a.S2, b.S2)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_single_maps(mrh, graph):
+    announce(f"batch of 5 maps (3 RGB-D, 2 LiDAR), graph={graph}")
+    cfgs, frames = _streams()
+    maps = [mrh.Map(**c) for c in cfgs]
+    b = mrh.Batch(maps)
+    b.set_launch(512, 16, graph)
+    for fr in frames:
+        b.integrate(fr)
+    for i, c in enumerate(cfgs):
+        maps[i].sync()
+        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames]))
+
+
+def test_batch_f16_equals_single_f16(mrh):
+    announce("batch f16")
+    cfgs, frames = _streams()
+    maps = [mrh.Map(**dict(c, storage="f16")) for c in cfgs]
+    b = mrh.Batch(maps)
+    for fr in frames:
+        b.integrate(fr)
+    for i, c in enumerate(cfgs):
+        maps[i].sync()
+        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames], storage="f16"))
+
+
+def test_batch_autotune_resets_maps(mrh):
+    announce("batch autotune")
+    cfgs, frames = _streams()
+    maps = [mrh.Map(**c) for c in cfgs]
+    b = mrh.Batch(maps)
+    best = b.autotune(frames[0], reps=2)
+    assert best[0] in (256, 512, 1024, 2048, 4096) and best[1] in (16, 64) and best[2] == 1
+    assert b.get_launch() == best
+    for m in maps:
+        assert m.counts() == (0, 0)
+    for fr in frames:
+        b.integrate(fr)
+    for i, c in enumerate(cfgs):
+        maps[i].sync()
+        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames]))

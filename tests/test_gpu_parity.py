@@ -272,3 +272,26 @@ def test_table_full_before_block_limit(mrh):
     assert ei.value.code == -3
     nb, _ = g.counts()
     assert nb == 512
+
+
+def test_sequence_entry_points_equal_frame_calls(mrh):
+    """The library-side frame loop gives the same map as one call per frame."""
+    announce("sequence entry points")
+    depths, cam, poses, _ = room_sequence(width=320, height=240, f=262.5, frames=[0, 5, 10, 15])
+    cfg = dict(configs.ROOM, max_blocks=1 << 16, hash_slots=1 << 17)
+    a, b = mrh.Map(**cfg), mrh.Map(**cfg)
+    d = _dev(depths)
+    for k in range(4):
+        a.integrate_depth(d[k], cam.K, poses[k])
+    b.integrate_depth_sequence(d, cam.K, np.ascontiguousarray(poses))
+    ga, gb = gpu_sorted(a), gpu_sorted(b)
+    assert np.array_equal(ga.keys, gb.keys) and np.array_equal(ga.D, gb.D) and np.array_equal(ga.W, gb.W)
+    pts, sposes, _ = street_sequence(rings=8, azimuths=256, scans=[0, 1, 2])
+    cfgs = dict(configs.STREET, max_blocks=1 << 16, hash_slots=1 << 17)
+    c, e = mrh.Map(**cfgs), mrh.Map(**cfgs)
+    x = _dev(pts)
+    for k in range(3):
+        c.integrate_points(x[k], sposes[k])
+    e.integrate_points_sequence(x, np.ascontiguousarray(sposes))
+    gc, ge = gpu_sorted(c), gpu_sorted(e)
+    assert np.array_equal(gc.keys, ge.keys) and np.array_equal(gc.D, ge.D) and np.array_equal(gc.W, ge.W)

@@ -1,0 +1,118 @@
+"""Precision variants: TSDF stored as FP16 / BF16 of D / tau (weights uint16 / FP16, variance FP16),
+FP32 arithmetic in registers.  Block key sets stay bit-exact (allocation does not read the state);
+TSDF errors are reported against the FP64 oracle and the FP32 GPU map and checked against bounds
+derived from the storage precision."""
+import numpy as np
+import pytest
+import torch
+
+from parity_util import announce, excused_keys, gpu_sorted
+from workloads import configs, room_sequence, sphere_plane_frame
+
+pytestmark = pytest.mark.gpu
+
+# half-ulp of D / tau near 1 times tau: FP16 2^-11, BF16 2^-8 (relative)
+ULP = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.fixture(scope="module")
+def mrh():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2511_21459_amd as mrh
+
+    return mrh
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _zero_cross_flips(keys_lv_ok, ref_D, ref_W, got_D, offsets, got_offsets, levels):
+    """Fraction of voxels on the reference zero crossing (a 6-neighbour inside the same block with
+    the opposite sign, sign(0) = +) whose stored sign differs from the reference sign."""
+    flips = total = 0
+    for i in np.flatnonzero(keys_lv_ok):
+        m = 8 >> int(levels[i])
+        sl = slice(offsets[i], offsets[i + 1])
+        r = ref_D[sl].reshape(m, m, m)
+        w = ref_W[sl].reshape(m, m, m) > 0
+        g = got_D[got_offsets[i]:got_offsets[i + 1]].reshape(m, m, m)
+        sr = r >= 0
+        cross = np.zeros_like(sr)
+        for ax in range(3):
+            a = np.swapaxes(sr, 0, ax)
+            wa = np.swapaxes(w, 0, ax)
+            c = np.swapaxes(cross, 0, ax)
+            diff = (a[1:] != a[:-1]) & wa[1:] & wa[:-1]
+            c[1:] |= diff
+            c[:-1] |= diff
+        cross &= w
+        total += int(cross.sum())
+        flips += int((cross & ((g >= 0) != sr)).sum())
+    return flips, total
+
+
+def _compare(g, o, excused, tau):
+    assert np.array_equal(g.keys, o.keys), "block key sets differ"
+    same = (g.levels == o.levels) & np.array([tuple(k) not in excused for k in o.keys.tolist()], bool)
+    idx_g = np.concatenate([np.arange(g.offsets[i], g.offsets[i + 1]) for i in np.flatnonzero(same)])
+    idx_o = np.concatenate([np.arange(o.offsets[i], o.offsets[i + 1]) for i in np.flatnonzero(same)])
+    W_o = o.W[idx_o]
+    obs = W_o > 0
+    dD = np.abs(g.D[idx_g] - o.D[idx_o])[obs]
+    return {"blocks": len(o.keys), "compared": int(same.sum()), "max_abs_dD": float(dD.max()),
+            "rms_dD": float(np.sqrt(np.mean(dD ** 2))), "w_equal_frac": float(np.mean(g.W[idx_g][obs] == W_o[obs])),
+            "same": same}
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_sphere_plane_precision(mrh, orc, storage):
+    announce(f"precision sphere_plane {storage}")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    o.integrate_depth(depth, cam.K, T)
+    ref = o.extract()
+    g = mrh.Map(**dict(configs.SPHERE_PLANE, storage=storage))
+    g.integrate_depth(_dev(depth), cam.K, T)
+    g.sync()
+    rep = _compare(gpu_sorted(g), ref, set(), 0.06)
+    print(storage, {k: v for k, v in rep.items() if k != "same"})
+    assert rep["w_equal_frac"] == 1.0
+    # one observation per voxel: the only error is the final rounding of D / tau
+    assert rep["max_abs_dD"] <= 0.06 * ULP[storage] * 1.01 + 1e-7
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_room_sequence_precision(mrh, orc, storage):
+    """12 frames of the 4-level room at 320x240 against the FP64 oracle and the FP32 GPU map."""
+    announce(f"precision room 320x240 x12 {storage}")
+    frames = list(range(0, 100, 8))[:12]
+    depths, cam, poses, _ = room_sequence(width=320, height=240, f=262.5, frames=frames)
+    cfg = dict(configs.ROOM, max_blocks=1 << 17, hash_slots=1 << 18)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    g = mrh.Map(**dict(cfg, storage=storage))
+    g32 = mrh.Map(**cfg)
+    for k in range(len(frames)):
+        o.integrate_depth(depths[k], cam.K, poses[k])
+        d = _dev(depths[k])
+        g.integrate_depth(d, cam.K, poses[k])
+        g32.integrate_depth(d, cam.K, poses[k])
+    g.sync()
+    g32.sync()
+    ref = o.extract()
+    gs, g32s = gpu_sorted(g), gpu_sorted(g32)
+    ex = excused_keys(o, margin=5e-2)
+    rep = _compare(gs, ref, ex, cfg["tau"])
+    rep32 = _compare(gs, g32s, ex, cfg["tau"])
+    flips, cross = _zero_cross_flips(rep["same"], ref.D, ref.W, gs.D, ref.offsets, gs.offsets, ref.levels)
+    level_diff = int(np.sum(gs.levels != ref.levels))
+    print(storage, "vs oracle", {k: v for k, v in rep.items() if k != "same"}, "vs fp32 gpu",
+          {k: v for k, v in rep32.items() if k != "same"}, "flipped", flips, "of", cross,
+          "level mismatches", level_diff, "excused", len(ex))
+    # stagnation bound: a running mean stored with half-ulp u drifts by at most u W / 2 over W
+    # updates; W <= 12 per fine voxel here, pooled coarse voxels restart from a rounded mean
+    tau = cfg["tau"]
+    assert rep["max_abs_dD"] <= tau * ULP[storage] * 8
+    assert rep["rms_dD"] <= tau * ULP[storage]
+    assert flips <= max(2, 0.02 * cross)
+    assert level_diff <= len(ex)

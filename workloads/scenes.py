@@ -15,9 +15,21 @@ Newer College / Oxford Spires streets for LiDAR; Sec. 4.1), which are not availa
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
+
+
+def _map_frames(fn, items):
+    """Evaluate fn over frame indices on a thread pool (NumPy releases the GIL in its kernels);
+    every frame draws from its own seeded generator, so the result does not depend on the pool."""
+    workers = min(len(items), max(1, min(16, os.cpu_count() or 1)))
+    if workers <= 1:
+        return [fn(k) for k in items]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
 
 
 @dataclass(frozen=True)
@@ -204,16 +216,18 @@ def room_sequence(n_frames: int = 100, width: int = 640, height: int = 480, f: f
     scene = room_scene(scene_seed)
     r = cam.rays()
     idx = list(range(n_frames)) if frames is None else list(frames)
-    depths = np.empty((len(idx), height, width), dtype=np.float32)
-    poses = np.empty((len(idx), 4, 4))
-    for j, k in enumerate(idx):
+
+    def one(k):
         T = orbit_pose(k, n_frames)
         w = r @ T[:3, :3].T
         z = scene.raycast(T[:3, 3], w)
         rng = np.random.default_rng([noise_seed, k])
         z = z + rng.normal(0.0, 1.0, size=z.shape) * (noise_k * z * z)
-        depths[j] = z.astype(np.float32)
-        poses[j] = T
+        return z.astype(np.float32), T
+
+    out = _map_frames(one, idx)
+    depths = np.stack([o[0] for o in out]) if out else np.empty((0, height, width), np.float32)
+    poses = np.stack([o[1] for o in out]) if out else np.empty((0, 4, 4))
     return depths, cam, poses, scene
 
 
@@ -294,19 +308,22 @@ def street_sequence(n_scans: int = 200, rings: int = 64, azimuths: int = 2048,
     sc = street_scene(scene_seed)
     dirs = lidar_directions(rings, azimuths)
     idx = list(range(n_scans)) if scans is None else list(scans)
-    pts = np.empty((len(idx), dirs.shape[0], 3), dtype=np.float32)
-    poses = np.empty((len(idx), 4, 4))
-    for j, k in enumerate(idx):
+
+    def one(k):
         T = street_pose(k)
         w = dirs @ T[:3, :3].T
         r = sc.raycast(T[:3, 3], w)
         rng = np.random.default_rng([noise_seed, k])
         r = r + rng.normal(0.0, noise, size=r.shape)
         keep = (r >= min_range) & (r <= max_range)
-        p = dirs * r[:, None]
+        with np.errstate(invalid="ignore"):
+            p = dirs * r[:, None]
         p[~keep] = np.nan
-        pts[j] = p.astype(np.float32)
-        poses[j] = T
+        return p.astype(np.float32), T
+
+    out = _map_frames(one, idx)
+    pts = np.stack([o[0] for o in out]) if out else np.empty((0, dirs.shape[0], 3), np.float32)
+    poses = np.stack([o[1] for o in out]) if out else np.empty((0, 4, 4))
     return pts, poses, sc
 
 
