@@ -116,7 +116,9 @@ mrh_status mrh_map_reset(mrh_map* map);
  * pixel, update every voxel of every allocated block that projects onto a valid pixel and lies
  * no more than tau behind it, then merge every updated block whose mean voxel variance is below
  * var_thr one level coarser.  Asynchronous.  Errors: MRH_ERR_INVALID_ARG (NULL pointers, sizes
- * <= 0, non-finite K or T_ws); kernel-side capacity errors are latched (see top). */
+ * <= 0 or >= 2^24, width * height >= 2^31, non-finite K or T_ws); MRH_ERR_OOM when the map's
+ * per-tile depth summary (4 bytes per 16 x 16 pixels) cannot grow to a larger frame; kernel-side
+ * capacity errors are latched (see top). */
 mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
                                const double K[4], const double T_ws[16]);
 

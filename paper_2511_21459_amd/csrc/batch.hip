@@ -19,6 +19,8 @@
 namespace mrh {
 
 mrh_status ensure_lidar(mrh_map* map);
+bool depth_size_ok(int32_t width, int32_t height);
+mrh_status attach_tiles(mrh_map* map, int32_t width, int32_t height, DepthFrame& f);
 
 constexpr int kMaxBatch = 64;
 
@@ -57,9 +59,10 @@ __global__ __launch_bounds__(256) void k_batch_alloc(const DevMap* __restrict__ 
 template <int ST>
 __global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
                                                     int n) {
+    __shared__ unsigned long long tab[kSatSlots];
     const int i = entry_of(ents, n, blockIdx.x, true);
-    if (i < 0) return;
-    points_ray_chunk<ST>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin);
+    if (i < 0) return;  // uniform across the workgroup
+    points_ray_chunk<ST>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
 }
 
 template <int ST>
@@ -268,9 +271,11 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         e.alloc_begin = alloc_wgs;
         e.ray_begin = ray_wgs;
         if (f.kind == MRH_FRAME_DEPTH) {
-            if (!f.data_dev || f.width <= 0 || f.height <= 0 ||
+            if (!f.data_dev || !depth_size_ok(f.width, f.height) ||
                 !make_depth_frame(b->maps[i]->cfg, f.data_dev, f.width, f.height, f.K, f.T_ws, e.df))
                 return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad depth frame");
+            if (attach_tiles(b->maps[i], f.width, f.height, e.df) != MRH_OK)
+                return batch_err(b, MRH_ERR_OOM, "batch: tile buffer");
             e.tiles_x = (uint32_t)(f.width + 15) / 16;
             e.tiles = e.tiles_x * (uint32_t)((f.height + 15) / 16);
             alloc_wgs += e.tiles + (uint32_t)b->cull_wgs;

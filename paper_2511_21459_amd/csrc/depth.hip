@@ -11,6 +11,33 @@ namespace mrh {
 
 void launch_finalize(mrh_map* m);
 
+// Frame sizes the kernels accept: pixel indices are 32-bit and pixel coordinates exact in FP32.
+bool depth_size_ok(int32_t width, int32_t height) {
+    return width > 0 && height > 0 && width < (1 << 24) && height < (1 << 24) &&
+           (int64_t)width * (int64_t)height <= (int64_t)INT32_MAX;
+}
+
+// Point the frame at the map's tile-maximum buffer, growing it when the frame has more tiles.
+mrh_status attach_tiles(mrh_map* map, int32_t width, int32_t height, DepthFrame& f) {
+    f.tiles_x = (width + 15) / 16;
+    f.tiles_y = (height + 15) / 16;
+    const size_t need = (size_t)f.tiles_x * (size_t)f.tiles_y;
+    if (need > map->tile_cap) {
+        if (map->tile_max) {
+            mrh_status st = check_hip(map, hipStreamSynchronize(map->stream), "tile buffer");
+            if (st != MRH_OK) return st;
+            (void)hipFree(map->tile_max);
+            map->tile_max = nullptr;
+            map->tile_cap = 0;
+        }
+        mrh_status st = check_hip(map, hipMalloc((void**)&map->tile_max, need * sizeof(float)), "tile buffer");
+        if (st != MRH_OK) return st;
+        map->tile_cap = need;
+    }
+    f.tile_max = map->tile_max;
+    return MRH_OK;
+}
+
 bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, int32_t height, const double K[4],
                       const double T_ws[16], DepthFrame& f) {
     if (!pose_from(T_ws, f.P)) return false;
@@ -53,13 +80,15 @@ bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, 
 }
 
 // Workgroups [0, tiles): pixel tiles; [tiles, gridDim): cull.
-__global__ __launch_bounds__(256) void k_alloc_depth(DevMap m, DepthFrame f, uint32_t tiles_x, uint32_t tiles) {
+__global__ __launch_bounds__(256) void k_alloc_depth(const DevMap* __restrict__ pm, DepthFrame f, uint32_t tiles_x, uint32_t tiles) {
+    const DevMap& m = *pm;
     if (blockIdx.x >= tiles) depth_cull(m, f, blockIdx.x - tiles, gridDim.x - tiles);
     else depth_alloc_tile(m, f, blockIdx.x, tiles_x);
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_integrate_depth(DevMap m, DepthFrame f) {
+__global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restrict__ pm, DepthFrame f) {
+    const DevMap& m = *pm;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t n[4] = {m.ctr->vis_n[0], m.ctr->vis_n[1], m.ctr->vis_n[2], m.ctr->vis_n[3]};
@@ -75,22 +104,24 @@ using namespace mrh;
 
 extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
                                           const double K[4], const double T_ws[16]) {
-    if (!map || !depth_dev || !K || !T_ws || width <= 0 || height <= 0) return MRH_ERR_INVALID_ARG;
+    if (!map || !depth_dev || !K || !T_ws || !depth_size_ok(width, height)) return MRH_ERR_INVALID_ARG;
     DepthFrame f;
     if (!make_depth_frame(map->cfg, depth_dev, width, height, K, T_ws, f))
         return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose or intrinsics, or zero focal length");
+    const mrh_status ts = attach_tiles(map, width, height, f);
+    if (ts != MRH_OK) return ts;
     const uint32_t tiles_x = (uint32_t)(width + 15) / 16, tiles = tiles_x * (uint32_t)((height + 15) / 16);
     const uint32_t cull_groups = 128;
     launch(map, K_ALLOC_DEPTH, [&] {
-        hipLaunchKernelGGL(k_alloc_depth, dim3(tiles + cull_groups), dim3(256), 0, map->stream, map->dm, f, tiles_x,
+        hipLaunchKernelGGL(k_alloc_depth, dim3(tiles + cull_groups), dim3(256), 0, map->stream, map->dmd, f, tiles_x,
                            tiles);
     });
     launch(map, K_INTEGRATE_DEPTH, [&] {
         const dim3 g(1024), b(256);
         switch (map->cfg.storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F16>, g, b, 0, map->stream, map->dm, f); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_BF16>, g, b, 0, map->stream, map->dm, f); break;
-            default: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F32>, g, b, 0, map->stream, map->dm, f);
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F16>, g, b, 0, map->stream, map->dmd, f); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_BF16>, g, b, 0, map->stream, map->dmd, f); break;
+            default: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd, f);
         }
     });
     launch_finalize(map);
@@ -99,7 +130,7 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
 
 extern "C" mrh_status mrh_integrate_depth_sequence(mrh_map* map, const float* depth_dev, int32_t n_frames, int32_t width,
                                                    int32_t height, const double K[4], const double* T_ws) {
-    if (!map || !depth_dev || !K || !T_ws || n_frames < 0 || width <= 0 || height <= 0) return MRH_ERR_INVALID_ARG;
+    if (!map || !depth_dev || !K || !T_ws || n_frames < 0 || !depth_size_ok(width, height)) return MRH_ERR_INVALID_ARG;
     DepthFrame f;
     for (int32_t k = 0; k < n_frames; ++k)
         if (!make_depth_frame(map->cfg, depth_dev, width, height, K, T_ws + 16 * k, f))

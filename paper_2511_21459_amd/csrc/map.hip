@@ -24,6 +24,15 @@ mrh_status check_hip(mrh_map* m, hipError_t e, const char* what) {
     return set_error(m, e == hipErrorOutOfMemory ? MRH_ERR_OOM : MRH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Kernels read the map descriptor through a pointer: a ~900-byte by-value argument would not fit
+// the scalar register file and would be spilled into vector lanes on every launch.
+mrh_status upload_descriptor(mrh_map* m) {
+    mrh_status st = check_hip(m, hipMemcpyAsync(m->dmd, &m->dm, sizeof(DevMap), hipMemcpyHostToDevice, m->stream),
+                              "descriptor upload");
+    if (st == MRH_OK) st = check_hip(m, hipStreamSynchronize(m->stream), "descriptor upload");
+    return st;
+}
+
 bool pose_from(const double* T, Pose& P) {
     if (!T) return false;
     for (int i = 0; i < 16; ++i)
@@ -36,7 +45,8 @@ bool pose_from(const double* T, Pose& P) {
 }
 
 // Empty table, full free stacks, zero counters.
-__global__ void k_reset(DevMap m, uint32_t n_hash) {
+__global__ void k_reset(const DevMap* __restrict__ pm, uint32_t n_hash) {
+    const DevMap& m = *pm;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     for (uint32_t i = tid; i < n_hash; i += stride) m.hkeys[i] = kEmptyKey;
     for (int n = 0; n < m.levels; ++n) {
@@ -62,12 +72,13 @@ __global__ void k_reset(DevMap m, uint32_t n_hash) {
 }
 
 // End of a frame (one workgroup).
-__global__ void k_finalize(DevMap m) { finalize_map(m); }
+__global__ void k_finalize(const DevMap* __restrict__ pm) { finalize_map(*pm); }
 
 // Copy blocks out: keys, levels and (optionally) voxels converted from Morton to x-fastest order.
 template <int ST>
-__global__ void k_extract(DevMap m, uint32_t nb, const int64_t* __restrict__ offsets, int32_t* keys, uint8_t* levels,
-                          float* D, uint32_t* W, float* S2) {
+__global__ void k_extract(const DevMap* __restrict__ pm, uint32_t nb, const int64_t* __restrict__ offsets, int32_t* keys,
+                          uint8_t* levels, float* D, uint32_t* W, float* S2) {
+    const DevMap& m = *pm;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -119,10 +130,11 @@ const char* mrh_last_error(const mrh_map* map) { return map ? map->err : "null m
 
 static void free_all(mrh_map* m) {
     DevMap& d = m->dm;
-    void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out};
+    void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out, m->dmd};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);
+    if (m->tile_max) (void)hipFree(m->tile_max);
     for (int n = 0; n < 4; ++n)
         if (d.vis[n]) (void)hipFree(d.vis[n]);
     for (int n = 0; n < 4; ++n) {
@@ -167,6 +179,11 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     d.tau_f = (float)c.tau;
     d.inv_tau_f = (float)(1.0 / c.tau);
     d.tau2_f = (float)(c.tau * c.tau);
+    {
+        float mf = (float)c.max_depth;
+        if ((double)mf > c.max_depth) mf = std::nextafter(mf, -INFINITY);
+        d.max_depth_f = mf;
+    }
     d.var_thr = c.var_thr;
     d.max_depth = c.max_depth;
     d.r2lo = c.min_range * c.min_range;
@@ -204,7 +221,9 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     m->partials_cap = 1024;
     alloc((void**)&m->partials, (size_t)m->partials_cap * 6 * 8, "reduction partials");
     alloc((void**)&m->pose_out, 6 * 8, "pose gradient");
+    alloc((void**)&m->dmd, sizeof(DevMap), "map descriptor");
     d.ctr = m->ctr;
+    if (st == MRH_OK) st = upload_descriptor(m);
     if (st != MRH_OK) {
         free_all(m);
         delete m;
@@ -236,7 +255,7 @@ void mrh_map_destroy(mrh_map* map) {
 mrh_status mrh_map_reset(mrh_map* map) {
     if (!map) return MRH_ERR_INVALID_ARG;
     const uint32_t n_hash = map->dm.hmask + 1;
-    launch(map, K_RESET, [&] { hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, map->stream, map->dm, n_hash); });
+    launch(map, K_RESET, [&] { hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, map->stream, map->dmd, n_hash); });
     return check_hip(map, hipGetLastError(), "reset");
 }
 
@@ -320,9 +339,9 @@ mrh_status mrh_extract_blocks(mrh_map* map, int32_t* keys_dev, uint8_t* levels_d
     if (st == MRH_OK) {
         const uint32_t grid = nb / 4 + 1 < 4096 ? nb / 4 + 1 : 4096;
         switch (map->cfg.storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL(k_extract<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL(k_extract<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
-            default: hipLaunchKernelGGL(k_extract<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev);
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_extract<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_extract<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            default: hipLaunchKernelGGL(k_extract<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev);
         }
         st = check_hip(map, hipGetLastError(), "extract");
         if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "extract");
@@ -371,6 +390,6 @@ hipEvent_t take_event(mrh_map* m) {
 
 // launched by the integrate entry points after each frame
 void launch_finalize(mrh_map* m) {
-    launch(m, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, m->stream, m->dm); });
+    launch(m, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, m->stream, m->dmd); });
 }
 }  // namespace mrh

@@ -24,6 +24,10 @@ struct DepthFrame {
     // conservative culling of whole blocks (camera frame): side-plane normals and a range bound
     double plane[4][3];
     double cull_range;
+    // largest valid depth per 16 x 16 pixel tile (written by the allocation launch, -1 when the
+    // tile holds no valid sample), tiles_x tiles per row
+    float* tile_max;
+    int32_t tiles_x, tiles_y;
 };
 
 // Host: fill a frame descriptor; false on a non-finite pose or intrinsics or a zero focal length.
@@ -54,17 +58,20 @@ __device__ inline bool project_observe(const DevMap& m, const DepthFrame& f, con
     return true;
 }
 
-// The same observation with the projection evaluated in FP32.  Every discrete decision (pixel index,
-// the -tau gate) is taken from the FP32 value only when it lies farther from its threshold than the
-// FP32 evaluation error can reach; otherwise the canonical FP64 expression above decides, so the
-// decisions always equal the canonical ones.  Error budget of u = fx (x0 / x2) + cx from FP64 x:
-// four roundings at 2^-24 relative of values below |u| + |cx| stay under 1e-6 (|u| + |cx| + 16).
-__device__ inline bool project_observe_fast(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            double x0, double x1, double x2, float& obs) {
-    if (!(x2 > 0.0)) return false;
+// The same observation with the projection evaluated in FP32.  Returns 1 (update with obs), 0 (no
+// update) or 2 (undecided: the canonical FP64 expression above must decide).  Every discrete
+// decision (pixel index, the -tau gate) is taken from the FP32 value only when it lies farther from
+// its threshold than the FP32 evaluation error can reach, so the decisions always equal the
+// canonical ones.  Error budget of u = fx (x0 / x2) + cx from FP64 x: the roundings of x0, x2, fx,
+// cx, the product and the sum (2^-24 relative each) and the hardware reciprocal (1 ulp) stay below
+// 6e-7 (|u| + |cx|), under the margin 1e-6 (|u| + |cx| + 16).  The range-form value carries about
+// 8 ulps (squares, sums, square root, reciprocal), far inside the 1e-5 tau gate band.
+__device__ inline int observe_fast(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth, double x0,
+                                   double x1, double x2, float& obs) {
+    if (!(x2 > 0.0)) return 0;
     const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
-    if (!(xf2 > 1e-6f)) return project_observe(m, f, depth, x0, x1, x2, obs);
-    const float izf = 1.0f / xf2;
+    if (!(xf2 > 1e-6f)) return 2;
+    const float izf = __builtin_amdgcn_rcpf(xf2);
     const float uf = f.fxf * (xf0 * izf) + f.cxf;
     const float vf = f.fyf * (xf1 * izf) + f.cyf;
     const float su = uf + 0.5f, sv = vf + 0.5f;
@@ -72,29 +79,75 @@ __device__ inline bool project_observe_fast(const DevMap& m, const DepthFrame& f
     const float du = __builtin_fminf(su - fu, fu + 1.0f - su), dv = __builtin_fminf(sv - fv, fv + 1.0f - sv);
     const float eu = 1e-6f * (__builtin_fabsf(uf) + __builtin_fabsf(f.cxf) + 16.0f);
     const float ev = 1e-6f * (__builtin_fabsf(vf) + __builtin_fabsf(f.cyf) + 16.0f);
-    if (!(du > eu && dv > ev)) return project_observe(m, f, depth, x0, x1, x2, obs);
-    if (!(fu >= 0.0f && fu <= (float)(f.width - 1) && fv >= 0.0f && fv <= (float)(f.height - 1))) return false;
-    const float d = depth[(int64_t)fv * f.width + (int64_t)fu];
-    if (!(__builtin_isfinite(d) && d > 0.0f && (double)d <= m.max_depth)) return false;
+    if (!(du > eu && dv > ev)) return 2;
+    if (!(fu >= 0.0f && fu <= (float)(f.width - 1) && fv >= 0.0f && fv <= (float)(f.height - 1))) return 0;
+    const float d = depth[(int)fv * f.width + (int)fu];
+    if (!(__builtin_isfinite(d) && d > 0.0f && d <= m.max_depth_f)) return 0;
     const double ddiff = (double)d - x2;
     if (m.form != MRH_FORM_RANGE) {
-        if (ddiff < -m.tau) return false;
+        if (ddiff < -m.tau) return 0;
         obs = (float)(ddiff < m.tau ? ddiff : m.tau);
-        return true;
+        return 1;
     }
     // range form: raw = ||x|| (d / x2 - 1) = (d - x2) ||x|| / x2
-    const float lam = __builtin_sqrtf((xf0 * xf0 + xf1 * xf1) + xf2 * xf2) * izf;
+    const float lam = __builtin_amdgcn_sqrtf((xf0 * xf0 + xf1 * xf1) + xf2 * xf2) * izf;
     const float raw = (float)ddiff * lam;
-    if (__builtin_fabsf(raw + m.tau_f) <= 1e-5f * m.tau_f + 1e-6f * __builtin_fabsf(raw)) {
-        // near the gate: decide with the canonical expression
-        const double nx = __builtin_sqrt((x0 * x0 + x1 * x1) + x2 * x2);
-        const double raw64 = nx * (((double)d * (1.0 / x2)) - 1.0);
-        if (raw64 < -m.tau) return false;
-    } else if (raw < -m.tau_f) {
-        return false;
-    }
+    if (__builtin_fabsf(raw + m.tau_f) <= 1e-5f * m.tau_f + 1e-6f * __builtin_fabsf(raw)) return 2;
+    if (raw < -m.tau_f) return 0;
     obs = raw < m.tau_f ? raw : m.tau_f;
-    return true;
+    return 1;
+}
+
+// One voxel: the FP32 evaluation, and the canonical one where that is undecided.
+__device__ inline bool observe(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth, double x0,
+                               double x1, double x2, float& obs) {
+    const int r = observe_fast(m, f, depth, x0, x1, x2, obs);
+    if (r == 2) return project_observe(m, f, depth, x0, x1, x2, obs);
+    return r == 1;
+}
+
+// Wave-uniform test (all lanes active): true when no voxel of block (bx, by, bz) can be updated by
+// this frame.  With every block corner in front of the camera, each voxel centre projects inside the
+// rectangle spanned by the projected corners (padded by a pixel against rounding) and lies at least
+// as deep as the shallowest corner, zmin.  If zmin exceeds every valid depth of the tiles that the
+// rectangle touches by more than tau, each voxel has x_z - d > tau for the depth d of its own pixel,
+// so raw < -tau under both readings of Eq. 2 (the range reading scales x_z - d by |x| / x_z >= 1)
+// and the gate rejects it; pixels outside the image or without a valid depth are never updated.
+__device__ inline bool block_hidden(const DevMap& m, const DepthFrame& f, int32_t bx, int32_t by, int32_t bz) {
+    const int lane = lane_id(), c = lane & 7;
+    const double w0 = ((double)bx + (double)(c & 1)) * m.B - f.P.t[0];
+    const double w1 = ((double)by + (double)((c >> 1) & 1)) * m.B - f.P.t[1];
+    const double w2 = ((double)bz + (double)(c >> 2)) * m.B - f.P.t[2];
+    const double x0 = (f.P.R[0][0] * w0 + f.P.R[1][0] * w1) + f.P.R[2][0] * w2;
+    const double x1 = (f.P.R[0][1] * w0 + f.P.R[1][1] * w1) + f.P.R[2][1] * w2;
+    const double x2 = (f.P.R[0][2] * w0 + f.P.R[1][2] * w1) + f.P.R[2][2] * w2;
+    // every group of 8 lanes holds the 8 corners, so these reductions are wave-uniform
+    double zmin = x2;
+    for (int o = 1; o < 8; o <<= 1) zmin = __builtin_fmin(zmin, __shfl_xor(zmin, o));
+    if (!(zmin > 1e-3)) return false;
+    const double iz = 1.0 / x2;
+    const double u = __builtin_fmin(__builtin_fmax(f.fx * (x0 * iz) + f.cx, -1e8), 1e8);
+    const double v = __builtin_fmin(__builtin_fmax(f.fy * (x1 * iz) + f.cy, -1e8), 1e8);
+    int u0 = (int)__builtin_floor(u) - 1, u1 = (int)__builtin_ceil(u) + 1;
+    int v0 = (int)__builtin_floor(v) - 1, v1 = (int)__builtin_ceil(v) + 1;
+    for (int o = 1; o < 8; o <<= 1) {
+        u0 = min(u0, __shfl_xor(u0, o));
+        u1 = max(u1, __shfl_xor(u1, o));
+        v0 = min(v0, __shfl_xor(v0, o));
+        v1 = max(v1, __shfl_xor(v1, o));
+    }
+    if (u1 < 0 || v1 < 0 || u0 > f.width - 1 || v0 > f.height - 1) return true;
+    const int tu0 = max(u0, 0) >> 4, tu1 = min(u1, f.width - 1) >> 4;
+    const int tv0 = max(v0, 0) >> 4, tv1 = min(v1, f.height - 1) >> 4;
+    const int ntu = tu1 - tu0 + 1, nt = ntu * (tv1 - tv0 + 1);
+    if (nt > 256) return false;
+    float dmax = -1.0f;
+    for (int k = lane; k < nt; k += 64) {
+        const int ty = k / ntu;
+        dmax = __builtin_fmaxf(dmax, f.tile_max[(tv0 + ty) * f.tiles_x + tu0 + (k - ty * ntu)]);
+    }
+    dmax = wave_max(dmax);
+    return zmin > (double)dmax + m.tau * (1.0 + 1e-6) + 1e-9;
 }
 
 __device__ inline bool block_visible(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz) {
@@ -156,7 +209,10 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
         if (in_range) w.init(a, e, m.invB);
     }
     __shared__ uint32_t cnt[2];
+    __shared__ float tmx[4];
     if (threadIdx.x == 0) cnt[0] = cnt[1] = 0;
+    const float wmax = wave_max(ok ? (float)d : -1.0f);
+    if (lane == 0) tmx[wave] = wmax;
     __syncthreads();
     const unsigned long long vmask = __ballot(ok), dmask = __ballot(ok && !in_range);
     if (lane == 0) {
@@ -173,9 +229,23 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
     if (threadIdx.x == 0) {
         stat_add(m, S_VALID, cnt[0]);
         stat_add(m, S_DROPPED, cnt[1]);
+        f.tile_max[tile] = __builtin_fmaxf(__builtin_fmaxf(tmx[0], tmx[1]), __builtin_fmaxf(tmx[2], tmx[3]));
     }
 }
 
+
+// Camera-frame centre of voxel (i, j, k) of block b at `level`, canonical FP64.
+__device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz, int level,
+                                    int i, int j, int k, double& x0, double& x1, double& x2) {
+    const double nu = m.nu[level];
+    const double c0 = (double)bx * m.B + ((double)i + 0.5) * nu;
+    const double c1 = (double)by * m.B + ((double)j + 0.5) * nu;
+    const double c2 = (double)bz * m.B + ((double)k + 0.5) * nu;
+    const double d0 = c0 - f.P.t[0], d1 = c1 - f.P.t[1], d2 = c2 - f.P.t[2];
+    x0 = (f.P.R[0][0] * d0 + f.P.R[1][0] * d1) + f.P.R[2][0] * d2;
+    x1 = (f.P.R[0][1] * d0 + f.P.R[1][1] * d1) + f.P.R[2][1] * d2;
+    x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
+}
 
 // Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
 template <int ST>
@@ -186,6 +256,7 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
     int32_t bx, by, bz;
     unpack_key(m.bkey[id], bx, by, bz);
     const bool fresh = (info & kNewBit) != 0;
+    if (!fresh && block_hidden(m, f, bx, by, bz)) return;
     int I, J, K;
     demorton3(lane, I, J, K);
     const double nu = m.nu[0];
@@ -203,14 +274,30 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         }
     }
     float obs[8];
-    uint32_t upd = 0;
+    uint32_t upd = 0, slow = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int a = q & 1, b = (q >> 1) & 1, c = (q >> 2) & 1;
         const double x0 = (px[a][0] + py[b][0]) + pz[c][0];
         const double x1 = (px[a][1] + py[b][1]) + pz[c][1];
         const double x2 = (px[a][2] + py[b][2]) + pz[c][2];
-        if (project_observe_fast(m, f, depth, x0, x1, x2, obs[q])) upd |= 1u << q;
+        const int r = observe_fast(m, f, depth, x0, x1, x2, obs[q]);
+        upd |= (r == 1 ? 1u : 0u) << q;
+        slow |= (r == 2 ? 1u : 0u) << q;
+    }
+    // voxels the FP32 evaluation left undecided, one canonical evaluation per pass
+    while (slow) {
+        const int q = __builtin_ctz(slow);
+        slow &= slow - 1;
+        double x0, x1, x2;
+        voxel_camera(m, f, bx, by, bz, 0, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2), x0, x1, x2);
+        float o = 0.f;
+        if (project_observe(m, f, depth, x0, x1, x2, o)) {
+            upd |= 1u << q;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k == q) obs[k] = o;
+        }
     }
     const int nupd = wave_sum((int)__popc(upd));
     if (nupd == 0 && !fresh) return;
@@ -242,19 +329,6 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
     ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt);
 }
 
-// Camera-frame centre of voxel (i, j, k) of block b at `level`, canonical FP64.
-__device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_t bx, int64_t by, int64_t bz, int level,
-                                    int i, int j, int k, double& x0, double& x1, double& x2) {
-    const double nu = m.nu[level];
-    const double c0 = (double)bx * m.B + ((double)i + 0.5) * nu;
-    const double c1 = (double)by * m.B + ((double)j + 0.5) * nu;
-    const double c2 = (double)bz * m.B + ((double)k + 0.5) * nu;
-    const double d0 = c0 - f.P.t[0], d1 = c1 - f.P.t[1], d2 = c2 - f.P.t[2];
-    x0 = (f.P.R[0][0] * d0 + f.P.R[1][0] * d1) + f.P.R[2][0] * d2;
-    x1 = (f.P.R[0][1] * d0 + f.P.R[1][1] * d1) + f.P.R[2][1] * d2;
-    x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
-}
-
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
 __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
@@ -263,12 +337,13 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
     const uint32_t info = m.binfo[id];
     int32_t bx, by, bz;
     unpack_key(m.bkey[id], bx, by, bz);
+    if (block_hidden(m, f, bx, by, bz)) return;
     int i, j, k;
     demorton3(lane, i, j, k);
     double x0, x1, x2;
     voxel_camera(m, f, bx, by, bz, 1, i, j, k, x0, x1, x2);
     float obs = 0.f;
-    const bool upd = project_observe_fast(m, f, depth, x0, x1, x2, obs);
+    const bool upd = observe(m, f, depth, x0, x1, x2, obs);
     const int nupd = __popcll(__ballot(upd));
     if (nupd == 0) return;
     ts.obs += (unsigned long long)nupd;
@@ -310,7 +385,7 @@ __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame
         demorton3(lane % seg, i, j, k);
         double x0, x1, x2;
         voxel_camera(m, f, bx, by, bz, level, i, j, k, x0, x1, x2);
-        upd = project_observe_fast(m, f, depth, x0, x1, x2, obs);
+        upd = observe(m, f, depth, x0, x1, x2, obs);
     }
     if (!__ballot(upd)) return;
     float D = 0.f, S2 = 0.f;

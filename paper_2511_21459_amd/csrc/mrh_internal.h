@@ -85,6 +85,7 @@ struct DevMap {
     double tau, var_thr;
     double max_depth, r2lo, r2hi;
     float tau_f, inv_tau_f, tau2_f;
+    float max_depth_f;  // largest float <= max_depth: (double)d <= max_depth  <=>  d <= max_depth_f
     int32_t min_obs, form, carve, storage;
 };
 
@@ -185,6 +186,11 @@ __device__ inline unsigned long long shfl_u64(unsigned long long v, int src) {
 
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = __builtin_fmaxf(v, __shfl_xor(v, o));
     return v;
 }
 
@@ -338,11 +344,14 @@ struct mrh_map {
     hipStream_t stream = nullptr;
     int device = 0;
     mrh::DevMap dm{};
+    mrh::DevMap* dmd = nullptr;  // device copy of dm, passed to every kernel by pointer
     mrh::DevCounters* ctr = nullptr;
     double* partials = nullptr;  // query-backward per-workgroup FP64 partial sums
     double* pose_out = nullptr;  // 6 doubles, final reduction
     int32_t partials_cap = 0;
     bool lidar_ready = false;    // accumulators allocated
+    float* tile_max = nullptr;   // per 16 x 16 pixel tile of the current depth frame: largest valid depth
+    size_t tile_cap = 0;
     bool profiling = false;      // bracket every launch with events (mrh_profile_enable)
     std::vector<mrh::ProfRec> prof;
     std::vector<hipEvent_t> event_pool;
@@ -353,6 +362,7 @@ namespace mrh {
 mrh_status set_error(mrh_map* m, mrh_status code, const char* fmt, ...);
 mrh_status check_hip(mrh_map* m, hipError_t e, const char* what);
 bool pose_from(const double* T, Pose& P);
+mrh_status upload_descriptor(mrh_map* m);
 
 // Launch through `fn` (a callable that enqueues one kernel on m->stream), bracketed by events
 // when profiling is on.

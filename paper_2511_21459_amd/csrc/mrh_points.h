@@ -67,11 +67,65 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
     }
 }
 
-// Accumulate one observation d of the voxel at heap position `at` of `level`.
+// Saturated (+tau) observations of voxels near the sensor origin are first counted in a
+// workgroup-private LDS table: every ray of a scan starts at the origin, so near it thousands of
+// rays cross the same voxels and direct global atomics on those addresses serialise.  The table is
+// flushed with one global atomic per distinct voxel once the workgroup's rays are done.  The counts
+// are integers, so the result equals adding them one at a time.  An entry is (key + 1) << 32 | count
+// with key = level << 30 | heap position; keys are never removed while rays run.
+constexpr int kSatBits = 12;
+constexpr int kSatSlots = 1 << kSatBits;
+constexpr double kSatNear2 = 1024.0;  // voxels within 32 voxel edges of the origin use the table
+
+__device__ inline void sat_table_clear(unsigned long long* tab) {
+    for (int k = threadIdx.x; k < kSatSlots; k += blockDim.x) tab[k] = 0ull;
+    __syncthreads();
+}
+
+// Count one saturated observation in the table; false when the voxel must go to global memory
+// (heap position too large for a key, or no free entry within 8 probes).
+__device__ inline bool sat_table_add(unsigned long long* tab, int level, size_t at) {
+    if (at >= (size_t)((1u << 30) - 1u)) return false;
+    const uint32_t key = (((uint32_t)level << 30) | (uint32_t)at) + 1u;
+    uint32_t h = (key * 2654435761u) >> (32 - kSatBits);
+    for (int p = 0; p < 8; ++p) {
+        const uint32_t k = (uint32_t)(__hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> 32);
+        if (k == key) {
+            atomicAdd(&tab[h], 1ull);
+            return true;
+        }
+        if (k == 0u) {
+            const unsigned long long old = atomicCAS(&tab[h], 0ull, ((unsigned long long)key << 32) | 1ull);
+            if (old == 0ull) return true;
+            if ((uint32_t)(old >> 32) == key) {
+                atomicAdd(&tab[h], 1ull);
+                return true;
+            }
+        }
+        h = (h + 1) & (kSatSlots - 1);
+    }
+    return false;
+}
+
+// All threads of the workgroup: add the table's counts to the global accumulators.
+__device__ inline void sat_table_flush(const DevMap& m, unsigned long long* tab) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSatSlots; k += blockDim.x) {
+        const unsigned long long e = tab[k];
+        if (e) {
+            const uint32_t code = (uint32_t)(e >> 32) - 1u;
+            atomicAdd(&m.acc_sat[code >> 30][code & ((1u << 30) - 1u)], (uint32_t)e);
+        }
+    }
+}
+
+// Accumulate one observation d of the voxel at heap position `at` of `level`; `near` routes a
+// saturated one through the workgroup table.
 template <int ST>
-__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d) {
+__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d, bool near,
+                                  unsigned long long* tab) {
     if (d >= m.tau) {
-        atomicAdd(&m.acc_sat[level][at], 1u);
+        if (!(near && sat_table_add(tab, level, at))) atomicAdd(&m.acc_sat[level][at], 1u);
         return;
     }
     const double Dp = fresh ? 0.0 : (double)Store<ST>::getD(m, level, at);
@@ -149,12 +203,10 @@ struct BoxWalk {
     }
 };
 
-// Traversal and accumulation for points chunk * 256 + threadIdx.
+// Traversal and accumulation of one ray (segment a..e, surface point p, direction nn).
 template <int ST>
-__device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk) {
-    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
-    double a[3], e[3], p[3], nn[3];
-    if (!(i < sp.n && point_segment(m, sp, i, a, e, p, nn) && segment_in_range(a, e, m.invB))) return;
+__device__ inline void ray_walk(const DevMap& m, const ScanParams& sp, const double a[3], const double e[3],
+                                const double p[3], const double nn[3], unsigned long long* tab) {
     Walk w;
     w.init(a, e, m.invB);
     do {
@@ -179,10 +231,28 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
             const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
             const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
             const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
-            accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d);
+            bool near = false;
+            if (d >= m.tau) {
+                const double r0 = x0 - sp.P.t[0], r1 = x1 - sp.P.t[1], r2 = x2 - sp.P.t[2];
+                const double il = m.inv_nu[level];
+                near = ((r0 * r0 + r1 * r1) + r2 * r2) * (il * il) < kSatNear2;
+            }
+            accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d, near, tab);
             if (s == 3 * side || !bw.next()) break;
         }
     } while (w.next());
+}
+
+// Traversal and accumulation for points chunk * 256 + threadIdx (all threads of the workgroup;
+// tab is the workgroup's LDS table of kSatSlots entries).
+template <int ST>
+__device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk, unsigned long long* tab) {
+    sat_table_clear(tab);
+    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
+    double a[3], e[3], p[3], nn[3];
+    if (i < sp.n && point_segment(m, sp, i, a, e, p, nn) && segment_in_range(a, e, m.invB))
+        ray_walk<ST>(m, sp, a, e, p, nn, tab);
+    sat_table_flush(m, tab);
 }
 
 // Batch form of Eq. 3 and Eq. 5 for n observations with sums s1, s2 of (d - D) and (d - D)^2.

@@ -13,19 +13,21 @@
 
 namespace mrh {
 
-// Eq. 3 with w_k = 1 and Eq. 5 (Welford) in FP32.
+// Eq. 3 with w_k = 1 and Eq. 5 (Welford) in FP32; 1 / W from the hardware reciprocal (1 ulp).
 __device__ inline void welford(float obs, float& D, uint32_t& W, float& S2) {
     const uint32_t Wn = W + 1;
     const float Dold = D;
-    const float Dnew = Dold + (obs - Dold) / (float)Wn;
+    const float Dnew = Dold + (obs - Dold) * __builtin_amdgcn_rcpf((float)Wn);
     S2 = S2 + (obs - Dold) * (obs - Dnew);
     D = Dnew;
     W = Wn;
 }
 
-// A voxel's term of the block mean variance: sigma^2 = S2 / W (Eq. 6) for voxels with W >= min_obs.
+// A voxel's term of the block mean variance: sigma^2 = S2 / W (Eq. 6) for voxels with W >= min_obs,
+// evaluated in FP32 (a fixed function of the stored S2 and W, so that the incremental block sums
+// stay consistent) and summed in FP64.
 __device__ inline double var_term(const DevMap& m, uint32_t W, float S2) {
-    return W >= (uint32_t)m.min_obs ? (double)S2 / (double)W : 0.0;
+    return W >= (uint32_t)m.min_obs ? (double)(S2 * __builtin_amdgcn_rcpf((float)W)) : 0.0;
 }
 
 __device__ inline int var_count(const DevMap& m, uint32_t W) { return W >= (uint32_t)m.min_obs ? 1 : 0; }

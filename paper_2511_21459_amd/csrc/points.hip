@@ -10,15 +10,17 @@ namespace mrh {
 
 void launch_finalize(mrh_map* m);
 
-__global__ __launch_bounds__(256) void k_alloc_points(DevMap m, ScanParams sp) { points_alloc_chunk(m, sp, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_alloc_points(const DevMap* __restrict__ pm, ScanParams sp) { points_alloc_chunk(*pm, sp, blockIdx.x); }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_rays(DevMap m, ScanParams sp) {
-    points_ray_chunk<ST>(m, sp, blockIdx.x);
+__global__ __launch_bounds__(256) void k_rays(const DevMap* __restrict__ pm, ScanParams sp) {
+    __shared__ unsigned long long tab[kSatSlots];
+    points_ray_chunk<ST>(*pm, sp, blockIdx.x, tab);
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_apply_points(DevMap m) {
+__global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__ pm) {
+    const DevMap& m = *pm;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const uint32_t n[4] = {m.ctr->vis_n[0], m.ctr->vis_n[1], m.ctr->vis_n[2], m.ctr->vis_n[3]};
@@ -45,6 +47,7 @@ mrh_status ensure_lidar(mrh_map* map) {
         alloc((void**)&d.acc_s1[n], nv * 8, "scan accumulators");
         alloc((void**)&d.acc_s2[n], nv * 8, "scan accumulators");
     }
+    if (st == MRH_OK) st = upload_descriptor(map);
     if (st == MRH_OK) map->lidar_ready = true;
     return st;
 }
@@ -64,20 +67,20 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
     if (n > 0) {
         const unsigned grid = (unsigned)((n + 255) / 256);
         launch(map, K_ALLOC_POINTS,
-               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); });
+               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); });
         launch(map, K_RAYS, [&] {
             switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_rays<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp); break;
-                default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, sp);
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_rays<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); break;
+                default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp);
             }
         });
         launch(map, K_APPLY_POINTS, [&] {
             const dim3 g(1024), b(256);
             switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F16>, g, b, 0, map->stream, map->dm); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_BF16>, g, b, 0, map->stream, map->dm); break;
-                default: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F32>, g, b, 0, map->stream, map->dm);
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F16>, g, b, 0, map->stream, map->dmd); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_BF16>, g, b, 0, map->stream, map->dmd); break;
+                default: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd);
             }
         });
     }

@@ -123,8 +123,9 @@ __device__ inline void world_point(const QueryParams& qp, const float* pts, int6
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_query(DevMap m, QueryParams qp, const float* __restrict__ pts, int64_t n,
-                                               float* sdf, uint8_t* valid, float* grad) {
+__global__ __launch_bounds__(256) void k_query(const DevMap* __restrict__ pm, QueryParams qp, const float* __restrict__ pts,
+                                               int64_t n, float* sdf, uint8_t* valid, float* grad) {
+    const DevMap& m = *pm;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double x[3];
@@ -143,9 +144,10 @@ __global__ __launch_bounds__(256) void k_query(DevMap m, QueryParams qp, const f
 // Backward: per point dL/dx = g_i * d sdf / dx; dL/dp = R^T dL/dx; pose terms (dL/dx, x cross
 // dL/dx) summed per thread, then per workgroup in a fixed order into FP64 partials.
 template <int ST>
-__global__ __launch_bounds__(256) void k_query_backward(DevMap m, QueryParams qp, const float* __restrict__ pts,
+__global__ __launch_bounds__(256) void k_query_backward(const DevMap* __restrict__ pm, QueryParams qp, const float* __restrict__ pts,
                                                         int64_t n, const float* __restrict__ gsdf, float* gpts,
                                                         double* partials) {
+    const DevMap& m = *pm;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -217,9 +219,9 @@ extern "C" mrh_status mrh_query_sdf(mrh_map* map, const float* pts_dev, int64_t 
     const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
     launch(map, K_QUERY, [&] {
         switch (map->cfg.storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL(k_query<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
-            default: hipLaunchKernelGGL(k_query<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev);
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_query<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev); break;
+            default: hipLaunchKernelGGL(k_query<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, sdf_dev, valid_dev, grad_dev);
         }
     });
     return check_hip(map, hipGetLastError(), "query_sdf");
@@ -238,9 +240,9 @@ extern "C" mrh_status mrh_query_sdf_backward(mrh_map* map, const float* pts_dev,
     const int grid = (int)(blocks < map->partials_cap ? blocks : map->partials_cap);
     launch(map, K_QUERY_BACKWARD, [&] {
         switch (map->cfg.storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
-            default: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dm, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials);
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_query_backward<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials); break;
+            default: hipLaunchKernelGGL(k_query_backward<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, qp, pts_dev, n, grad_sdf_dev, grad_pts_dev, map->partials);
         }
     });
     launch(map, K_REDUCE, [&] {

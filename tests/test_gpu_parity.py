@@ -60,6 +60,42 @@ def test_room_sequence_multires(mrh, orc, form):
     assert merges > 100
 
 
+def _occlusion_frames():
+    """A far plane, then occluders in front of it: blocks behind an occluder by more than the
+    truncation distance receive no update, also where whole blocks are rejected at once."""
+    h, w, f = 120, 160, 150.0
+    K = np.array([f, f, w / 2.0, h / 2.0])
+    far = np.full((h, w), 2.0, np.float32)
+    half = far.copy()
+    half[:, : w // 2] = 1.0
+    near = np.full((h, w), 1.0, np.float32)
+    holes = near.copy()
+    holes[30:90, 40:120] = np.nan
+    holes[0:20, :] = 0.0
+    step = np.where(np.arange(w)[None, :] < w // 3, np.float32(2.07), np.float32(2.0)).repeat(h, 0)
+    T = np.eye(4)
+    T2 = np.eye(4)
+    T2[0, 3] = 0.3  # shifted camera: part of the map leaves the image
+    return K, [(far, T), (half, T), (near, T), (holes, T), (step, T), (far, T2), (near, T2)]
+
+
+@pytest.mark.parametrize("form", ["range", "zdiff"])
+def test_occluded_blocks(mrh, orc, form):
+    announce(f"occlusion planes 160x120 x7 frames form={form}")
+    K, frames = _occlusion_frames()
+    cfg = dict(configs.SPHERE_PLANE, levels=2, var_thr=1e-6, form=form)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for k, (d, T) in enumerate(frames):
+        g.integrate_depth(_dev(d), K, T)
+        last, _ = g.sync()
+        st = o.integrate_depth(d, K, T)
+        assert last["observations"] == st["observations"], k
+        assert last["new_blocks"] == st["new_blocks"], k
+    rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"])
+    print(rep)
+
+
 def test_room_full_size_first_frames(mrh, orc):
     """640x480 at the full configuration, first 3 frames."""
     announce("room 640x480 x3 frames full config")
