@@ -13,9 +13,12 @@ Also reported on the same JSON line:
   * `batched`: 16 independent streams (8 RGB-D 320x240..640x480, 8 LiDAR 32x1024..64x2048), 20
     launches, fused by the batched FP16 graph path against plain FP32 per-map calls;
   * `query`: 1M trilinear queries near the room's surfaces, forward and adjoint;
-  * `cpu_baseline`: the FP64 oracle on a bounded sample of the headline workload.
+  * `street`: 20 full-size LiDAR scans (64 x 2048) with carving, throughput and per-kernel times;
+  * `cpu_baseline`: the FP64 oracle on the headline workload (one thread), and the FP32 / FP16 /
+    BF16 GPU maps' accuracy against the oracle's map (max / RMS |dD|, zero-crossing sign flips).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +28,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per k_integrate_depth launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
+# plain-copy calibration), valid only for the kernel sources they were taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "room_integrate_traffic.json")
+
+
+def kernel_source_hash():
+    csrc = os.path.join(ROOT, "paper_2511_21459_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(frames):
+    """Counter-measured bytes per launch, or None when the kernel changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash() or t.get("frames") != frames:
+        return None
+    return int(t["bytes_per_launch"])
+
+
+def calibrate_copy():
+    """A plain device copy of known size (3 x 64 MiB) for scaling the HBM byte counters."""
+    import torch
+
+    n = 64 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x 64 MiB", flush=True)
 STATE_BYTES = {"f32": 12, "f16": 6, "bf16": 6}
 
 
@@ -54,28 +95,58 @@ def timed(fn, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def compare_maps(a, b):
-    """max / RMS |dD| over observed voxels of blocks present in both maps at the same level."""
+def map_arrays(m):
+    """(block codes, levels, offsets, D, W) of a GPU map as numpy, blocks in table order."""
     import numpy as np
 
-    ea, eb = a.extract(), b.extract()
-    out = []
-    for e in (ea, eb):
-        k = e["keys"].cpu().numpy().astype(np.int64)
-        code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
-        out.append((code, e["levels"].cpu().numpy(), e["offsets"].cpu().numpy(), e["D"].cpu().numpy(),
-                    e["W"].cpu().numpy()))
-    (ca, la, oa, Da, Wa), (cb, lb, ob, Db, Wb) = out
+    e = m.extract()
+    k = e["keys"].cpu().numpy().astype(np.int64)
+    code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
+    return (code, e["levels"].cpu().numpy(), e["offsets"].cpu().numpy(), e["D"].cpu().numpy().astype(np.float64),
+            e["W"].cpu().numpy().view(np.uint32))
+
+
+def compare_arrays(ref, got, flips=False):
+    """max / RMS |dD| over voxels observed in both maps, in blocks present in both at the same level;
+    optionally the sign flips on the reference's zero crossing (voxels with a 6-neighbour of the
+    opposite reference sign inside the block, sign(0) = +, whose sign in `got` differs)."""
+    import numpy as np
+
+    (ca, la, oa, Da, Wa), (cb, lb, ob, Db, Wb) = ref, got
     common, ia, ib = np.intersect1d(ca, cb, return_indices=True)
     same = la[ia] == lb[ib]
     ia, ib = ia[same], ib[same]
     sa = np.concatenate([np.arange(oa[i], oa[i + 1]) for i in ia]) if len(ia) else np.zeros(0, int)
     sb = np.concatenate([np.arange(ob[i], ob[i + 1]) for i in ib]) if len(ib) else np.zeros(0, int)
     obs = (Wa[sa] > 0) & (Wb[sb] > 0)
-    d = np.abs(Da[sa] - Db[sb])[obs].astype(np.float64)
-    return {"blocks_compared": int(len(ia)), "blocks_level_differs": int((~same).sum()),
-            "max_abs_dD_m": float(d.max()) if d.size else 0.0,
-            "rms_dD_m": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
+    d = np.abs(Da[sa] - Db[sb])[obs]
+    out = {"blocks_compared": int(len(ia)), "blocks_level_differs": int((~same).sum()),
+           "blocks_only_in_one": int(len(ca) + len(cb) - 2 * len(common)),
+           "max_abs_dD_m": float(d.max()) if d.size else 0.0,
+           "rms_dD_m": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
+    if flips:
+        nf = nc = 0
+        for i, j in zip(ia, ib):
+            mside = 8 >> int(la[i])
+            r = Da[oa[i]:oa[i + 1]].reshape(mside, mside, mside)
+            w = Wa[oa[i]:oa[i + 1]].reshape(mside, mside, mside) > 0
+            g = Db[ob[j]:ob[j + 1]].reshape(mside, mside, mside)
+            sr = r >= 0
+            cross = np.zeros_like(sr)
+            for ax in range(3):
+                a, wa, c = np.swapaxes(sr, 0, ax), np.swapaxes(w, 0, ax), np.swapaxes(cross, 0, ax)
+                diff = (a[1:] != a[:-1]) & wa[1:] & wa[:-1]
+                c[1:] |= diff
+                c[:-1] |= diff
+            cross &= w
+            nc += int(cross.sum())
+            nf += int((cross & ((g >= 0) != sr)).sum())
+        out.update(zero_crossing_voxels=nc, flipped=nf, flipped_frac=round(nf / nc, 6) if nc else 0.0)
+    return out
+
+
+def compare_maps(a, b):
+    return compare_arrays(map_arrays(b), map_arrays(a))
 
 
 def run_room(args, torch, np, mrh, configs, room_sequence):
@@ -127,22 +198,37 @@ def run_room(args, torch, np, mrh, configs, room_sequence):
     k_ms, k_launches = prof["integrate_depth"]
     avg_launch_s = k_ms / k_launches / 1e3
     bytes_per_launch = algorithmic_bytes_integrate(census, W, H) / args.frames
+    # per-frame latency: events around each frame's calls on the map's stream
+    fmap.reset()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.frames + 1)]
+    evs[0].record(fmap.stream)
+    for k in range(args.frames):
+        fmap.integrate_depth(frames[k], cam.K, poses[k])
+        evs[k + 1].record(fmap.stream)
+    torch.cuda.synchronize()
+    per_frame = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.frames)])
+    frame_ms = {"median": round(float(np.median(per_frame)), 4), "p90": round(float(np.percentile(per_frame, 90)), 4),
+                "sum": round(float(per_frame.sum()), 3)}
 
     # precision variants of the same sequence
     precision = {}
+    fmap.reset()
+    fmap.integrate_depth_sequence(dev, cam.K, poses)
+    arrays = {"f32": map_arrays(fmap)}
     for st in ("f16", "bf16"):
         pm = mrh.Map(**dict(configs.ROOM, storage=st))
         pstep = make_step(pm)
         pstep()
         t = timed(pstep, args.steps, torch)
-        acc = compare_maps(pm, fmap)  # both hold the whole sequence
+        arrays[st] = map_arrays(pm)  # both maps hold the whole sequence
+        acc = compare_arrays(arrays["f32"], arrays[st], flips=True)
         precision[st] = dict(m_points_per_s=round(sum(f["valid_points"] for f in census) / t / 1e6, 3),
                              ms_per_step=round(t * 1e3, 3), speedup_vs_f32=round(wall / t, 3),
-                             state_bytes_per_voxel=STATE_BYTES[st], **acc)
+                             state_bytes_per_voxel=STATE_BYTES[st], vs_f32_gpu=acc)
         pm.close()
     return dict(depths=depths, cam=cam, poses=poses, scene=scene, W=W, H=H, census=census, wall=wall,
                 gpu_ms=gpu_ms, prof=prof, avg_launch_s=avg_launch_s, bytes_per_launch=bytes_per_launch,
-                tot=tot, precision=precision, fmap=fmap)
+                tot=tot, precision=precision, fmap=fmap, frame_ms=frame_ms, arrays=arrays)
 
 
 RGBD_STREAMS = [(320, 240), (384, 288), (416, 312), (480, 360), (512, 384), (560, 420), (608, 456), (640, 480)]
@@ -236,6 +322,48 @@ def run_batched(args, torch, np, mrh, configs):
             "blocks_level_differs": sum(a["blocks_level_differs"] for a in accs)}
 
 
+def run_street(args, torch, np, mrh, configs):
+    """LiDAR street (64 x 2048 rings x azimuths, carving, 5/10/20/40 cm levels): the first
+    `--scans` scans fused as one sequence per step."""
+    from workloads import street_sequence
+
+    n = args.scans
+    pts, poses, _ = street_sequence(rings=64, azimuths=2048, scans=range(n))
+    poses = np.ascontiguousarray(poses)
+    dev = torch.from_numpy(pts).cuda()
+    cfg = dict(configs.STREET, max_blocks=1 << 22, hash_slots=1 << 23,
+               heap_blocks=[1 << 21, 1 << 21, 1 << 21, 1 << 22])
+    m = mrh.Map(**cfg)
+    m.reset()
+    census = []
+    for k in range(n):
+        m.integrate_points(dev[k], poses[k])
+        census.append(m.sync()[0])
+
+    def step():
+        m.reset()
+        m.integrate_points_sequence(dev, poses)
+
+    step()
+    t = timed(step, args.steps, torch)
+    m.profile(True)
+    step()
+    prof = m.profile_collect()
+    m.profile(False)
+    m.close()
+    valid = sum(f["valid_points"] for f in census)
+    obs = sum(f["observations"] for f in census)
+    rays_ms = prof["rays"][0] / prof["rays"][1]
+    return dict(pts=pts, poses=poses, n=n, out={
+        "workload": f"street LiDAR, {n} scans of 64x2048 points, 5/10/20/40 cm levels, carving, tau 15 cm",
+        "valid_points_per_step": valid, "observations_per_step": obs, "blocks_at_end": census[-1]["blocks"],
+        "ms_per_step": round(t * 1e3, 3), "ms_per_scan": round(t * 1e3 / n, 3),
+        "m_points_per_s": round(valid / t / 1e6, 3), "g_observations_per_s": round(obs / t / 1e9, 4),
+        "kernels_ms_per_scan": {k: round(v[0] / n, 4) for k, v in prof.items()},
+        "rays_kernel": {"bound": "atomics/latency", "avg_launch_ms": round(rays_ms, 4),
+                        "observations_per_s_g": round(obs / n / (rays_ms / 1e3) / 1e9, 3)}})
+
+
 def run_query(room, torch, np, mrh):
     from workloads import surface_query_points
 
@@ -261,10 +389,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--launches", type=int, default=20, help="batched workload: frames per stream")
-    ap.add_argument("--cpu-frames", type=int, default=40, help="oracle sample: first N frames")
+    ap.add_argument("--cpu-frames", type=int, default=100, help="oracle sample: first N frames")
+    ap.add_argument("--scans", type=int, default=20, help="LiDAR street workload: scans per step")
+    ap.add_argument("--cpu-scans", type=int, default=3, help="LiDAR oracle sample: first N scans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the fusion of one map runs "
               "on one device; the sharding plan is documented, not measured)", file=sys.stderr)
@@ -303,10 +437,11 @@ def main():
                    "merges_per_step": [sum(f["merges"][n] for f in census) for n in range(4)]},
         "g_voxel_updates_per_s": round(updates / wall / 1e9, 4),
         "gpu_event_ms_per_step": round(room["gpu_ms"], 3),
+        "frame_ms": room["frame_ms"],
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "roofline": {"kernel": "k_integrate_depth", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(room["bytes_per_launch"]),
+                     "traffic": measured_traffic(args.frames), "bytes_per_launch": int(room["bytes_per_launch"]),
                      "avg_launch_us": round(room["avg_launch_s"] * 1e6, 3)},
         "precision": room["precision"],
         "cpu_baseline": None,
@@ -316,6 +451,8 @@ def main():
     if not args.no_extras:
         result["batched"] = run_batched(args, torch, np, mrh, configs)
         result["query"] = run_query(room, torch, np, mrh)
+        street = run_street(args, torch, np, mrh, configs)
+        result["street"] = street["out"]
 
     if not args.no_cpu_baseline:
         import oracle
@@ -331,6 +468,25 @@ def main():
                                   "kind": "oracle",
                                   "sample": f"first {n} of the {args.frames} frames, FP64 oracle, one thread "
                                             f"({dt:.1f} s)"}
+        if n == args.frames:
+            # the whole sequence: the GPU maps' accuracy against the FP64 oracle map
+            ex = o.extract()
+            k = ex.keys.astype(np.int64)
+            code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
+            ref = (code, ex.levels, ex.offsets, ex.D, ex.W)
+            result["cpu_baseline"]["gpu_vs_oracle"] = {
+                st: compare_arrays(ref, arr, flips=True) for st, arr in room["arrays"].items()}
+        if not args.no_extras:
+            ns = min(args.cpu_scans, street["n"])
+            o = oracle.OracleMap(**configs.oracle_kwargs(configs.STREET))
+            t0 = time.perf_counter()
+            pts = 0
+            for k in range(ns):
+                pts += o.integrate_points(street["pts"][k], street["poses"][k])["valid_points"]
+            dt = time.perf_counter() - t0
+            result["street"]["cpu_baseline"] = {
+                "value": round(pts / dt / 1e6, 4), "unit": "M points/s", "cores": 1, "kind": "oracle",
+                "sample": f"first {ns} of the {street['n']} scans, FP64 oracle, one thread ({dt:.1f} s)"}
     print(json.dumps(result), flush=True)
 
 

@@ -68,11 +68,11 @@ __global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ m
 template <int ST>
 __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
                                                       int n) {
-    __shared__ uint32_t cnt[kMaxBatch][4];
+    __shared__ TaskCounts cnt[kMaxBatch];
     __shared__ uint32_t pre[kMaxBatch + 1];
-    for (int k = threadIdx.x; k < 4 * n; k += blockDim.x) {
-        const int i = k >> 2;
-        cnt[i][k & 3] = ents[i].kind == MRH_FRAME_NONE ? 0u : maps[i].ctr->vis_n[k & 3];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        if (ents[i].kind == MRH_FRAME_NONE) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
+        else cnt[i] = frame_task_counts(maps[i], ents[i].kind == MRH_FRAME_DEPTH);
     }
     __syncthreads();
     if (threadIdx.x == 0) {

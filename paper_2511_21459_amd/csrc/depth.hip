@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restric
     const DevMap& m = *pm;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t n[4] = {m.ctr->vis_n[0], m.ctr->vis_n[1], m.ctr->vis_n[2], m.ctr->vis_n[3]};
+    const TaskCounts n = frame_task_counts(m, true);
     const uint32_t ntask = update_task_count(n);
     TaskStats ts;
     for (uint32_t t = wave; t < ntask; t += nwaves) depth_update_task<ST>(m, f, t, n, ts);

@@ -56,6 +56,8 @@ __global__ void k_reset(const DevMap* __restrict__ pm, uint32_t n_hash) {
     if (tid == 0) {
         DevCounters* c = m.ctr;
         c->n_blocks = 0;
+        c->pops0 = 0;
+        c->nb_start = 0;
         c->error_flags = 0;
         for (int n = 0; n < 4; ++n) {
             c->top[n] = n < m.levels ? m.heap_cap[n] : 0;

@@ -179,11 +179,15 @@ __device__ inline void depth_cull(const DevMap& m, const DepthFrame& f, uint32_t
                 if ((info & kNewBit) || block_visible(m, f, bx, by, bz)) level = (int)((info >> kLevelShift) & 3u);
             }
         }
-        queue_block(m, level, id);
+        queue_block_wg(m, level, id);
     }
 }
 
-// One 16 x 16 pixel tile per workgroup (tile index `tile`, tiles_x tiles per row).
+constexpr int kTileNew = 512;  // new blocks a tile registers with one allocation atomic
+
+// One 16 x 16 pixel tile per workgroup (tile index `tile`, tiles_x tiles per row).  The keys a
+// wave inserts are collected in LDS and registered with one atomic on the allocation word per
+// workgroup; a key that finds the list full is registered by its wave directly.
 __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, uint32_t tile, uint32_t tiles_x) {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const float* __restrict__ depth = f.depth;
@@ -210,7 +214,11 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
     }
     __shared__ uint32_t cnt[2];
     __shared__ float tmx[4];
-    if (threadIdx.x == 0) cnt[0] = cnt[1] = 0;
+    __shared__ unsigned long long nkey[kTileNew];
+    __shared__ uint32_t nslot[kTileNew];
+    __shared__ uint32_t ncount;
+    __shared__ unsigned long long nold;
+    if (threadIdx.x == 0) cnt[0] = cnt[1] = ncount = 0;
     const float wmax = wave_max(ok ? (float)d : -1.0f);
     if (lane == 0) tmx[wave] = wmax;
     __syncthreads();
@@ -222,10 +230,33 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
     bool active = in_range;
     while (__ballot(active)) {
         const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
-        insert_keys(m, active, key, true);
+        uint32_t slot = 0;
+        const bool is_new = claim_keys(m, active, key, &slot);
+        const unsigned long long newmask = __ballot(is_new);
+        bool spill = false;
+        if (newmask) {
+            const int first = __ffsll((long long)newmask) - 1;
+            uint32_t at = 0;
+            if (lane == first) at = atomicAdd(&ncount, (uint32_t)__popcll(newmask));
+            at = (uint32_t)__shfl((int)at, first) + (uint32_t)rank_in_mask(newmask);
+            if (is_new) {
+                if (at < (uint32_t)kTileNew) {
+                    nkey[at] = key;
+                    nslot[at] = slot;
+                } else {
+                    spill = true;
+                }
+            }
+            register_new(m, spill, key, slot);
+        }
         if (active) active = w.next();
     }
     __syncthreads();
+    const uint32_t nnew = ncount < (uint32_t)kTileNew ? ncount : (uint32_t)kTileNew;
+    if (threadIdx.x == 0 && nnew) nold = take_new_blocks(m, nnew);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nnew; i += blockDim.x)
+        register_block(m, nkey[i], nslot[i], (uint32_t)nold + i, (uint32_t)(nold >> 32) + i);
     if (threadIdx.x == 0) {
         stat_add(m, S_VALID, cnt[0]);
         stat_add(m, S_DROPPED, cnt[1]);
@@ -253,6 +284,7 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
                                             uint32_t id, TaskStats& ts) {
     const int lane = lane_id();
     const uint32_t info = m.binfo[id];
+    if (info & kNoBlockBit) return;
     int32_t bx, by, bz;
     unpack_key(m.bkey[id], bx, by, bz);
     const bool fresh = (info & kNewBit) != 0;
@@ -409,15 +441,16 @@ __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame
                                                       dcnt);
 }
 
-// One update task t of a frame whose queues hold n0..n3 blocks per level.
+// One update task t of the frame's task space (see TaskCounts).
 template <int ST>
-__device__ inline void depth_update_task(const DevMap& m, const DepthFrame& f, uint32_t t, const uint32_t n[4],
+__device__ inline void depth_update_task(const DevMap& m, const DepthFrame& f, uint32_t t, const TaskCounts& c,
                                          TaskStats& ts) {
-    const uint32_t g2 = (n[2] + 7) / 8;
-    if (t < n[0]) integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t], ts);
-    else if (t < n[0] + n[1]) integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n[0]], ts);
-    else if (t < n[0] + n[1] + g2) integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], n[2], t - n[0] - n[1], 2, ts);
-    else integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], n[3], t - n[0] - n[1] - g2, 3, ts);
+    const uint32_t n0 = c.n[0] + c.n_new, g2 = (c.n[2] + 7) / 8;
+    if (t < c.n[0]) integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t], ts);
+    else if (t < n0) integrate_fine_block<ST>(m, f, f.depth, c.new_base + (t - c.n[0]), ts);
+    else if (t < n0 + c.n[1]) integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n0], ts);
+    else if (t < n0 + c.n[1] + g2) integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], c.n[2], t - n0 - c.n[1], 2, ts);
+    else integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], c.n[3], t - n0 - c.n[1] - g2, 3, ts);
 }
 
 }  // namespace mrh

@@ -39,13 +39,17 @@ enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, 
 constexpr int kStripes = 32;
 
 struct DevCounters {
-    uint32_t n_blocks;
+    // allocation word: one 64-bit atomic adds k to both halves for k new blocks
+    uint32_t n_blocks;   // block ids handed out (keys inserted), low half
+    uint32_t pops0;      // level-0 slots taken by this frame's new blocks, high half; applied to
+                         // top[0] at the frame's end (level-0 slots are only taken by allocation)
     uint32_t error_flags;
     int32_t top[4];
     uint32_t pending[4];
-    uint32_t vis_n[4];   // blocks queued for the projective update this frame, per level
-    uint32_t n_prev;     // blocks that existed when the frame started
-    uint32_t pad[13];
+    uint32_t vis_n[4];   // blocks queued for the update this frame, per level
+    uint32_t n_prev;     // min(n_blocks, max_blocks) when the frame started: ids >= n_prev are new
+    uint32_t nb_start;   // n_blocks when the frame started
+    uint32_t pad[11];
     unsigned long long frame[kStripes][16];
     unsigned long long last[16];
     unsigned long long total[16];

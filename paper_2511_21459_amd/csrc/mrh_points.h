@@ -62,7 +62,7 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
     bool active = in_range;
     while (__ballot(active)) {
         const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
-        insert_keys(m, active, key, false);
+        insert_keys(m, active, key);
         if (active) active = w.next();
     }
 }
@@ -426,7 +426,8 @@ __device__ inline void apply_packed(const DevMap& m, const uint32_t* list, uint3
 
 // One update task t of a scan whose queues hold n0..n3 blocks per level.
 template <int ST>
-__device__ inline void points_update_task(const DevMap& m, uint32_t t, const uint32_t n[4], TaskStats& as) {
+__device__ inline void points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, TaskStats& as) {
+    const uint32_t* n = c.n;  // LiDAR frames queue their new blocks like the others (n_new = 0)
     const uint32_t g2 = (n[2] + 7) / 8;
     if (t < n[0]) apply_fine<ST>(m, m.vis[0][t], as);
     else if (t < n[0] + n[1]) apply_level1<ST>(m, m.vis[1][t - n[0]], as);

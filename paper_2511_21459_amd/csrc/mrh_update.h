@@ -216,7 +216,27 @@ struct TaskStats {
     unsigned long long obs = 0, fresh = 0, merges[2] = {0, 0}, lane_obs = 0, lane_merges = 0;
 };
 
-__device__ inline uint32_t update_task_count(const uint32_t n[4]) { return n[0] + n[1] + (n[2] + 7) / 8 + (n[3] + 63) / 64; }
+// A frame's update task space: [queued level-0 blocks | blocks allocated this frame (ids
+// new_base ..) | level-1 blocks | level-2 blocks in groups of 8 | level-3 blocks in groups of 64].
+struct TaskCounts {
+    uint32_t n[4];
+    uint32_t new_base, n_new;
+};
+
+__device__ inline uint32_t update_task_count(const TaskCounts& c) {
+    return c.n[0] + c.n_new + c.n[1] + (c.n[2] + 7) / 8 + (c.n[3] + 63) / 64;
+}
+
+// Counts of the current frame; with_new: the blocks allocated this frame are update tasks of their
+// own (RGB-D); otherwise they are queued like every other block (LiDAR first touch).
+__device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new) {
+    TaskCounts c;
+    for (int l = 0; l < 4; ++l) c.n[l] = m.ctr->vis_n[l];
+    c.new_base = m.ctr->n_prev;
+    const uint32_t nb = m.ctr->n_blocks < m.max_blocks ? m.ctr->n_blocks : m.max_blocks;
+    c.n_new = with_new && nb > c.new_base ? nb - c.new_base : 0u;
+    return c;
+}
 
 // flush one wave's statistics (lane 0 adds wave-uniform and lane-summed parts)
 __device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
@@ -245,24 +265,30 @@ __device__ inline void queue_block(const DevMap& m, int level, uint32_t id) {
     }
 }
 
-// End of a frame for one map, by one workgroup: return the slots freed by merges to their levels'
-// stacks, publish the frame's statistics, empty the update queues, note the block count.
+// End of a frame for one map, by one workgroup: take this frame's level-0 pops off the stack,
+// return the slots freed by merges to their levels' stacks, publish the frame's statistics (the
+// new-block count is the growth of n_blocks), empty the update queues, note the block count.
+// Every counter is read once by thread 0 and shared through LDS, and written once by thread 0.
 __device__ inline void finalize_map(const DevMap& m) {
     DevCounters* c = m.ctr;
-    for (int n = 0; n < m.levels; ++n) {
-        const uint32_t p = c->pending[n];
-        if (p == 0) continue;
-        const int32_t top = c->top[n];
-        for (uint32_t i = threadIdx.x; i < p; i += blockDim.x) m.stack[n][top + i] = m.pend[n][i];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            c->top[n] = top + (int32_t)p;
-            c->pending[n] = 0;
+    __shared__ int32_t s_top[4];
+    __shared__ uint32_t s_pend[4];
+    __shared__ unsigned long long s_new;
+    if (threadIdx.x == 0) {
+        for (int n = 0; n < 4; ++n) {
+            s_top[n] = c->top[n];
+            s_pend[n] = n < m.levels ? c->pending[n] : 0u;
         }
-        __syncthreads();
+        const uint32_t avail = s_top[0] > 0 ? (uint32_t)s_top[0] : 0u;
+        const uint32_t pops = c->pops0;
+        s_top[0] -= (int32_t)(pops < avail ? pops : avail);
+        s_new = (unsigned long long)(c->n_blocks - c->nb_start);
     }
+    __syncthreads();
+    for (int n = 0; n < m.levels; ++n)
+        for (uint32_t i = threadIdx.x; i < s_pend[n]; i += blockDim.x) m.stack[n][s_top[n] + i] = m.pend[n][i];
     if (threadIdx.x < S_COUNT) {
-        unsigned long long v = 0;
+        unsigned long long v = threadIdx.x == S_NEW ? s_new : 0ull;
         for (int k = 0; k < kStripes; ++k) {
             v += c->frame[k][threadIdx.x];
             c->frame[k][threadIdx.x] = 0;
@@ -271,23 +297,87 @@ __device__ inline void finalize_map(const DevMap& m) {
         c->total[threadIdx.x] += v;
     }
     if (threadIdx.x == 0) {
+        for (int n = 0; n < 4; ++n) {
+            c->top[n] = s_top[n] + (int32_t)s_pend[n];
+            c->pending[n] = 0;
+            c->vis_n[n] = 0;
+        }
+        c->pops0 = 0;
         c->frames += 1;
-        for (int n = 0; n < 4; ++n) c->vis_n[n] = 0;
         c->n_prev = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
+        c->nb_start = c->n_blocks;
     }
 }
 
-// Wave-cooperative insert of one key per lane (has_key).  Keys found by a read-only probe need
-// nothing; the missing ones are deduplicated across the wave (one leader per distinct key does
-// the CAS insert), and the new entries get block ids and level-0 heap slots from one atomic each
-// per wave, ranked by a ballot prefix count.
-__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key, bool list_new) {
+// Queue block `id` on the update list of `level` (level < 0 queues nothing).  Called by every
+// thread of the workgroup (a barrier inside): positions come from LDS counters and one global
+// atomic per level per workgroup, since same-address device atomics serialise chip-wide.
+__device__ inline void queue_block_wg(const DevMap& m, int level, uint32_t id) {
+    __shared__ uint32_t lcnt[4], lbase[4];
+    if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t local = 0;
+    if (level >= 0) local = atomicAdd(&lcnt[level], 1u);
+    __syncthreads();
+    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[threadIdx.x], lcnt[threadIdx.x]);
+    __syncthreads();
+    if (level >= 0) m.vis[level][lbase[level] + local] = id;
+}
+
+// The block table entry of a new key that took hash slot `slot`: block id `id` and, as the
+// frame's `pop`-th level-0 slot, the slot below the stack top of the frame's start (top[0] does
+// not change while allocation runs).  Ids beyond max_blocks or pops beyond the stack latch errors.
+__device__ inline void register_block(const DevMap& m, unsigned long long key, uint32_t slot, uint32_t id,
+                                      uint32_t pop) {
+    if (id >= m.max_blocks) {
+        m.hvals[slot] = kInvalidId;
+        atomicOr(&m.ctr->error_flags, kErrBlockLimit);
+        stat_add(m, S_FAILED, 1ull);
+        return;
+    }
+    const int32_t t0 = m.ctr->top[0];
+    uint32_t info;
+    if ((int64_t)pop < (int64_t)t0) {
+        info = m.stack[0][(uint32_t)t0 - 1u - pop] | kNewBit;
+    } else {
+        info = kNoBlockBit;
+        atomicOr(&m.ctr->error_flags, kErrHeapFull);
+        stat_add(m, S_FAILED, 1ull);
+    }
+    m.bkey[id] = key;
+    m.binfo[id] = info;
+    m.bvsum[id] = 0.0;
+    m.bvcnt[id] = 0;
+    m.hvals[slot] = id;
+}
+
+// k new blocks: one atomic on the allocation word; returns the old word (ids and pops start there).
+__device__ inline unsigned long long take_new_blocks(const DevMap& m, uint32_t k) {
+    return atomicAdd(reinterpret_cast<unsigned long long*>(&m.ctr->n_blocks),
+                     (unsigned long long)k | ((unsigned long long)k << 32));
+}
+
+// Wave-cooperative registration of the lanes that inserted a new key (is_new).
+__device__ inline void register_new(const DevMap& m, bool is_new, unsigned long long key, uint32_t slot) {
+    const unsigned long long newmask = __ballot(is_new);
+    if (!newmask) return;
+    const int first = __ffsll((long long)newmask) - 1;
+    unsigned long long old = 0;
+    if (lane_id() == first) old = take_new_blocks(m, (uint32_t)__popcll(newmask));
+    old = shfl_u64(old, first);
+    const uint32_t rank = (uint32_t)rank_in_mask(newmask);
+    if (is_new) register_block(m, key, slot, (uint32_t)old + rank, (uint32_t)(old >> 32) + rank);
+}
+
+// Wave-cooperative claim of one key per lane (has_key): keys found by a read-only probe need
+// nothing; the missing ones are deduplicated across the wave and one leader per distinct key does
+// the CAS insert.  Returns true on the lane that inserted a new key (its hash slot in *slot).
+__device__ inline bool claim_keys(const DevMap& m, bool has_key, unsigned long long key, uint32_t* slot) {
     const int lane = lane_id();
     uint32_t stop = kInvalidId;
     bool need = false;
     if (has_key) need = probe_find(m, key, &stop) == kInvalidId;
     bool is_new = false;
-    uint32_t slot = 0;
     unsigned long long pending = __ballot(need);
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
@@ -295,7 +385,7 @@ __device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long 
         const bool same = need && key == lkey;
         pending &= ~__ballot(same);
         if (lane == leader) {
-            const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, &slot);
+            const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, slot);
             if (r == INS_NEW) {
                 is_new = true;
             } else if (r == INS_FULL) {
@@ -304,56 +394,14 @@ __device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long 
             }
         }
     }
-    const unsigned long long newmask = __ballot(is_new);
-    if (!newmask) return;
-    const int cnt = __popcll(newmask);
-    const int first = __ffsll((long long)newmask) - 1;
-    uint32_t base = 0;
-    int32_t top = 0;
-    if (lane == first) {
-        base = atomicAdd(&m.ctr->n_blocks, (uint32_t)cnt);
-        top = atomicSub(&m.ctr->top[0], cnt);
-        if (top < cnt) atomicAdd(&m.ctr->top[0], cnt - (top > 0 ? top : 0));  // undo the over-draw
-        stat_add(m, S_NEW, (unsigned long long)cnt);
-    }
-    base = (uint32_t)__shfl((int)base, first);
-    top = __shfl(top, first);
-    const int rank = rank_in_mask(newmask);
-    const uint32_t id = base + (uint32_t)rank;
-    bool stored = false;
-    if (is_new) {
-        if (id >= m.max_blocks) {
-            m.hvals[slot] = kInvalidId;
-            atomicOr(&m.ctr->error_flags, kErrBlockLimit);
-            stat_add(m, S_FAILED, 1ull);
-        } else {
-            uint32_t info;
-            if (rank < top) {
-                info = m.stack[0][top - 1 - rank] | kNewBit;
-                stored = true;
-            } else {
-                info = kNoBlockBit;
-                atomicOr(&m.ctr->error_flags, kErrHeapFull);
-                stat_add(m, S_FAILED, 1ull);
-            }
-            m.bkey[id] = key;
-            m.binfo[id] = info;
-            m.bvsum[id] = 0.0;
-            m.bvcnt[id] = 0;
-            m.hvals[slot] = id;
-        }
-    }
-    if (list_new) {
-        // new blocks are always visited by this frame's projective update
-        const unsigned long long smask = __ballot(stored);
-        if (smask) {
-            const int f2 = __ffsll((long long)smask) - 1;
-            uint32_t vb = 0;
-            if (lane == f2) vb = atomicAdd(&m.ctr->vis_n[0], (uint32_t)__popcll(smask));
-            vb = (uint32_t)__shfl((int)vb, f2);
-            if (stored) m.vis[0][vb + rank_in_mask(smask)] = id;
-        }
-    }
+    return is_new;
+}
+
+// Wave-cooperative insert of one key per lane (has_key): claim, then register the new blocks.
+__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key) {
+    uint32_t slot = 0;
+    const bool is_new = claim_keys(m, has_key, key, &slot);
+    register_new(m, is_new, key, slot);
 }
 
 }  // namespace mrh

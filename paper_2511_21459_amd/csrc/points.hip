@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__
     const DevMap& m = *pm;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t n[4] = {m.ctr->vis_n[0], m.ctr->vis_n[1], m.ctr->vis_n[2], m.ctr->vis_n[3]};
+    const TaskCounts n = frame_task_counts(m, false);
     const uint32_t ntask = update_task_count(n);
     TaskStats as;
     for (uint32_t t = wave; t < ntask; t += nwaves) points_update_task<ST>(m, t, n, as);

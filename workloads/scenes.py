@@ -24,7 +24,9 @@ import numpy as np
 
 def _map_frames(fn, items):
     """Evaluate fn over frame indices on a thread pool (NumPy releases the GIL in its kernels);
-    every frame draws from its own seeded generator, so the result does not depend on the pool."""
+    every frame draws from its own seeded generator, so the result does not depend on the pool.
+    fn must not call BLAS (matrix products): concurrent BLAS calls from several threads are not
+    safe in every build and have returned wrong values; use _rotate and elementwise sums."""
     workers = min(len(items), max(1, min(16, os.cpu_count() or 1)))
     if workers <= 1:
         return [fn(k) for k in items]
@@ -57,11 +59,16 @@ class Pinhole:
 # ray/primitive intersection helpers (vectorised over rays; return +inf where there is no hit)
 # --------------------------------------------------------------------------------------------
 
+def _rotate(v, R):
+    """v @ R.T for float64[..., 3] vectors, by elementwise products (no BLAS)."""
+    return v[..., 0:1] * R[:, 0] + v[..., 1:2] * R[:, 1] + v[..., 2:3] * R[:, 2]
+
+
 def _hit_sphere(o, w, centre, radius):
     oc = o - centre
     a = np.einsum("...i,...i->...", w, w)
     b = np.einsum("...i,...i->...", w, oc)
-    c = np.dot(oc, oc) - radius * radius
+    c = float(np.sum(oc * oc)) - radius * radius
     disc = b * b - a * c
     t = np.full(a.shape, np.inf)
     ok = disc >= 0
@@ -219,7 +226,7 @@ def room_sequence(n_frames: int = 100, width: int = 640, height: int = 480, f: f
 
     def one(k):
         T = orbit_pose(k, n_frames)
-        w = r @ T[:3, :3].T
+        w = _rotate(r, T[:3, :3])
         z = scene.raycast(T[:3, 3], w)
         rng = np.random.default_rng([noise_seed, k])
         z = z + rng.normal(0.0, 1.0, size=z.shape) * (noise_k * z * z)
@@ -254,7 +261,7 @@ class StreetScene:
         for lo, hi in self.boxes:
             # skip boxes far outside any 80 m return (cheap bounding-sphere reject)
             c = 0.5 * (lo + hi)
-            if np.linalg.norm(c - o) - 0.5 * np.linalg.norm(hi - lo) > 90.0:
+            if math.sqrt(float(np.sum((c - o) ** 2))) - 0.5 * math.sqrt(float(np.sum((hi - lo) ** 2))) > 90.0:
                 continue
             t = np.minimum(t, _hit_box_outside(o, w, lo, hi))
         return t
@@ -311,7 +318,7 @@ def street_sequence(n_scans: int = 200, rings: int = 64, azimuths: int = 2048,
 
     def one(k):
         T = street_pose(k)
-        w = dirs @ T[:3, :3].T
+        w = _rotate(dirs, T[:3, :3])
         r = sc.raycast(T[:3, 3], w)
         rng = np.random.default_rng([noise_seed, k])
         r = r + rng.normal(0.0, noise, size=r.shape)
