@@ -58,11 +58,11 @@ __global__ void k_reset(const DevMap* __restrict__ pm, uint32_t n_hash) {
         c->n_blocks = 0;
         c->pops0 = 0;
         c->nb_start = 0;
-        c->error_flags = 0;
+        c->error_flags.v = 0;
         for (int n = 0; n < 4; ++n) {
-            c->top[n] = n < m.levels ? m.heap_cap[n] : 0;
-            c->pending[n] = 0;
-            c->vis_n[n] = 0;
+            c->top[n].v = n < m.levels ? m.heap_cap[n] : 0;
+            c->pending[n].v = 0;
+            c->vis_n[n].v = 0;
         }
         c->n_prev = 0;
         for (int s = 0; s < 16; ++s) {
@@ -208,7 +208,7 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     alloc((void**)&d.bvsum, nb * 8, "block variance sums");
     alloc((void**)&d.bvcnt, nb * 4, "block variance counts");
     alloc((void**)&m->ctr, sizeof(DevCounters), "counters");
-    for (int n = 0; n < c.levels; ++n) alloc((void**)&d.vis[n], nb * 4, "visible-block lists");
+    for (int n = 0; n < c.levels; ++n) alloc((void**)&d.vis[n], nb * 16, "visible-block lists");
     for (int n = 0; n < c.levels; ++n) {
         const int64_t cap = c.heap_blocks[n] > 0 ? c.heap_blocks[n] : c.max_blocks;
         d.heap_cap[n] = (int32_t)cap;
@@ -283,17 +283,17 @@ mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals) {
     if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "sync");
     if (st != MRH_OK) return st;
     const uint32_t nb = h.n_blocks < map->dm.max_blocks ? h.n_blocks : map->dm.max_blocks;
-    if (last) fill_stats(h.last, h.frames ? 1 : 0, nb, h.error_flags, last);
-    if (totals) fill_stats(h.total, h.frames, nb, h.error_flags, totals);
-    if (h.error_flags) {
+    if (last) fill_stats(h.last, h.frames ? 1 : 0, nb, h.error_flags.v, last);
+    if (totals) fill_stats(h.total, h.frames, nb, h.error_flags.v, totals);
+    if (h.error_flags.v) {
         const uint32_t zero = 0;
-        st = check_hip(map, hipMemcpyAsync(&map->ctr->error_flags, &zero, 4, hipMemcpyHostToDevice, map->stream),
+        st = check_hip(map, hipMemcpyAsync(&map->ctr->error_flags.v, &zero, 4, hipMemcpyHostToDevice, map->stream),
                        "clear errors");
         if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "clear errors");
         if (st != MRH_OK) return st;
-        if (h.error_flags & kErrTableFull)
+        if (h.error_flags.v & kErrTableFull)
             return set_error(map, MRH_ERR_TABLE_FULL, "hash table full (probe limit %d)", map->dm.max_probe);
-        if (h.error_flags & kErrHeapFull) return set_error(map, MRH_ERR_HEAP_FULL, "a level heap ran out of blocks");
+        if (h.error_flags.v & kErrHeapFull) return set_error(map, MRH_ERR_HEAP_FULL, "a level heap ran out of blocks");
         return set_error(map, MRH_ERR_BLOCK_LIMIT, "more than %u blocks", map->dm.max_blocks);
     }
     return MRH_OK;

@@ -171,15 +171,18 @@ __device__ inline void depth_cull(const DevMap& m, const DepthFrame& f, uint32_t
     for (uint32_t base = g * blockDim.x; base < n; base += ng * blockDim.x) {
         const uint32_t id = base + threadIdx.x;
         int level = -1;
+        uint32_t info = 0;
+        unsigned long long key = 0;
         if (id < n) {
-            const uint32_t info = m.binfo[id];
+            info = m.binfo[id];
             if (!(info & kNoBlockBit)) {
+                key = m.bkey[id];
                 int32_t bx, by, bz;
-                unpack_key(m.bkey[id], bx, by, bz);
+                unpack_key(key, bx, by, bz);
                 if ((info & kNewBit) || block_visible(m, f, bx, by, bz)) level = (int)((info >> kLevelShift) & 3u);
             }
         }
-        queue_block_wg(m, level, id);
+        queue_block_wg(m, level, id, info, key);
     }
 }
 
@@ -281,13 +284,15 @@ __device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_
 // Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
 template <int ST>
 __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            uint32_t id, TaskStats& ts) {
+                                            const uint4 e, TaskStats& ts) {
     const int lane = lane_id();
-    const uint32_t info = m.binfo[id];
+    const uint32_t id = e.x, info = e.y;
     if (info & kNoBlockBit) return;
     int32_t bx, by, bz;
-    unpack_key(m.bkey[id], bx, by, bz);
+    unpack_key(entry_key(e), bx, by, bz);
     const bool fresh = (info & kNewBit) != 0;
+    const double bvs = m.bvsum[id];
+    const uint32_t bvc = m.bvcnt[id];
     if (!fresh && block_hidden(m, f, bx, by, bz)) return;
     int I, J, K;
     demorton3(lane, I, J, K);
@@ -358,17 +363,20 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         dsum += var_term(m, W[q], S2[q]) - before;
         dcnt += var_count(m, W[q]) - cb;
     }
-    ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt);
+    ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt,
+                                                        bvs, bvc);
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
 __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                              uint32_t id, TaskStats& ts) {
+                                              const uint4 e, TaskStats& ts) {
     const int lane = lane_id();
-    const uint32_t info = m.binfo[id];
+    const uint32_t id = e.x, info = e.y;
     int32_t bx, by, bz;
-    unpack_key(m.bkey[id], bx, by, bz);
+    unpack_key(entry_key(e), bx, by, bz);
+    const double bvs = m.bvsum[id];
+    const uint32_t bvc = m.bvcnt[id];
     if (block_hidden(m, f, bx, by, bz)) return;
     int i, j, k;
     demorton3(lane, i, j, k);
@@ -393,13 +401,13 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt);
+    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt, bvs, bvc);
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
 template <int ST>
 __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                               const uint32_t* list, uint32_t count, uint32_t group, int level,
+                                               const uint4* list, uint32_t count, uint32_t group, int level,
                                                TaskStats& ts) {
     const int lane = lane_id();
     const int seg = level == 2 ? 8 : 1;
@@ -409,10 +417,11 @@ __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame
     bool upd = false;
     float obs = 0.f;
     if (live) {
-        id = list[bi];
-        info = m.binfo[id];
+        const uint4 e = list[bi];
+        id = e.x;
+        info = e.y;
         int32_t bx, by, bz;
-        unpack_key(m.bkey[id], bx, by, bz);
+        unpack_key(entry_key(e), bx, by, bz);
         int i, j, k;
         demorton3(lane % seg, i, j, k);
         double x0, x1, x2;
@@ -447,7 +456,10 @@ __device__ inline void depth_update_task(const DevMap& m, const DepthFrame& f, u
                                          TaskStats& ts) {
     const uint32_t n0 = c.n[0] + c.n_new, g2 = (c.n[2] + 7) / 8;
     if (t < c.n[0]) integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t], ts);
-    else if (t < n0) integrate_fine_block<ST>(m, f, f.depth, c.new_base + (t - c.n[0]), ts);
+    else if (t < n0) {
+        const uint32_t id = c.new_base + (t - c.n[0]);
+        integrate_fine_block<ST>(m, f, f.depth, make_entry(id, m.binfo[id], m.bkey[id]), ts);
+    }
     else if (t < n0 + c.n[1]) integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n0], ts);
     else if (t < n0 + c.n[1] + g2) integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], c.n[2], t - n0 - c.n[1], 2, ts);
     else integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], c.n[3], t - n0 - c.n[1] - g2, 3, ts);

@@ -38,18 +38,24 @@ enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, 
 // end-of-frame kernel sums the stripes.
 constexpr int kStripes = 32;
 
-struct DevCounters {
+// A counter alone on a 128-byte line.  Device-scope atomics are performed beyond the per-XCD L2s,
+// so plain loads of a line that other waves update atomically keep missing; counters that are
+// updated atomically each get their own line, apart from the ones every wave reads.
+template <typename T>
+struct alignas(128) Line {
+    T v;
+};
+
+struct alignas(128) DevCounters {
     // allocation word: one 64-bit atomic adds k to both halves for k new blocks
     uint32_t n_blocks;   // block ids handed out (keys inserted), low half
-    uint32_t pops0;      // level-0 slots taken by this frame's new blocks, high half; applied to
-                         // top[0] at the frame's end (level-0 slots are only taken by allocation)
-    uint32_t error_flags;
-    int32_t top[4];
-    uint32_t pending[4];
-    uint32_t vis_n[4];   // blocks queued for the update this frame, per level
+    uint32_t pops0;      // level-0 slots taken by this frame's new blocks, high half
     uint32_t n_prev;     // min(n_blocks, max_blocks) when the frame started: ids >= n_prev are new
     uint32_t nb_start;   // n_blocks when the frame started
-    uint32_t pad[11];
+    Line<uint32_t> error_flags;
+    Line<int32_t> top[4];
+    Line<uint32_t> pending[4];
+    Line<uint32_t> vis_n[4];   // blocks queued for the update this frame, per level
     unsigned long long frame[kStripes][16];
     unsigned long long last[16];
     unsigned long long total[16];
@@ -83,7 +89,7 @@ struct DevMap {
     unsigned long long* acc_s1[4];
     unsigned long long* acc_s2[4];
     uint32_t* btouch;  // per block: touched by a ray this frame
-    uint32_t* vis[4];  // per level: ids of the blocks the projective update visits this frame
+    uint4* vis[4];     // per level: the blocks the update visits this frame, (id, info, key lo, key hi)
     double B, invB;
     double nu[4], inv_nu[4];
     double tau, var_thr;
@@ -92,6 +98,15 @@ struct DevMap {
     float max_depth_f;  // largest float <= max_depth: (double)d <= max_depth  <=>  d <= max_depth_f
     int32_t min_obs, form, carve, storage;
 };
+
+// An update-queue entry carries the block's table row, so an update task needs no second lookup.
+__device__ inline uint4 make_entry(uint32_t id, uint32_t info, unsigned long long key) {
+    return make_uint4(id, info, (uint32_t)key, (uint32_t)(key >> 32));
+}
+
+__device__ inline unsigned long long entry_key(const uint4& e) {
+    return (unsigned long long)e.z | ((unsigned long long)e.w << 32);
+}
 
 // world <- sensor rigid transform, FP64
 struct Pose {

@@ -216,7 +216,7 @@ __device__ inline void ray_walk(const DevMap& m, const ScanParams& sp, const dou
         const int level = (int)((info >> kLevelShift) & 3u);
         // first touch of the block in this scan: queue it for the update (active lanes only)
         const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
-        if (__ballot(first)) queue_block(m, first ? level : -1, id);
+        if (__ballot(first)) queue_block(m, first ? level : -1, id, info, pack_key(b[0], b[1], b[2]));
         if (info & kNoBlockBit) continue;
         const bool fresh = (info & kNewBit) != 0;
         const int side = 8 >> level;
@@ -287,9 +287,11 @@ __device__ inline void take_accumulators(const DevMap& m, int level, size_t at, 
 }
 
 template <int ST>
-__device__ inline void apply_fine(const DevMap& m, uint32_t id, TaskStats& as) {
+__device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as) {
     const int lane = lane_id();
-    const uint32_t info = m.binfo[id];
+    const uint32_t id = e.x, info = e.y;
+    const double bvs = m.bvsum[id];
+    const uint32_t bvc = m.bvcnt[id];
     const bool fresh = (info & kNewBit) != 0;
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
     uint32_t ns[8], nb[8];
@@ -356,14 +358,17 @@ __device__ inline void apply_fine(const DevMap& m, uint32_t id, TaskStats& as) {
             for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
         }
     }
-    as.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt);
+    as.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
+                                                        bvs, bvc);
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
-__device__ inline void apply_level1(const DevMap& m, uint32_t id, TaskStats& as) {
+__device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& as) {
     const int lane = lane_id();
-    const uint32_t info = m.binfo[id];
+    const uint32_t id = e.x, info = e.y;
+    const double bvs = m.bvsum[id];
+    const uint32_t bvc = m.bvcnt[id];
     const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
     uint32_t ns, nb;
     unsigned long long s1, s2;
@@ -385,12 +390,12 @@ __device__ inline void apply_level1(const DevMap& m, uint32_t id, TaskStats& as)
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt);
+    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc);
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
 template <int ST>
-__device__ inline void apply_packed(const DevMap& m, const uint32_t* list, uint32_t count, uint32_t group, int level,
+__device__ inline void apply_packed(const DevMap& m, const uint4* list, uint32_t count, uint32_t group, int level,
                                     TaskStats& as) {
     const int lane = lane_id();
     const int seg = level == 2 ? 8 : 1;
@@ -401,8 +406,9 @@ __device__ inline void apply_packed(const DevMap& m, const uint32_t* list, uint3
     float D = 0.f, S2 = 0.f;
     uint32_t W = 0;
     if (live) {
-        id = list[bi];
-        info = m.binfo[id];
+        const uint4 e = list[bi];
+        id = e.x;
+        info = e.y;
         const size_t at = (size_t)(info & kSlotMask) * seg + (lane % seg);
         take_accumulators(m, level, at, ns, nb, s1, s2);
         if (lane % seg == 0) m.btouch[id] = 0u;

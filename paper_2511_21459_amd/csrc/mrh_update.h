@@ -34,10 +34,10 @@ __device__ inline int var_count(const DevMap& m, uint32_t W) { return W >= (uint
 
 // Pop one slot from a level's free stack (single lane).  Returns -1 when the heap is exhausted.
 __device__ inline int64_t pop_slot(const DevMap& m, int level) {
-    const int32_t top = atomicSub(&m.ctr->top[level], 1);
+    const int32_t top = atomicSub(&m.ctr->top[level].v, 1);
     if (top <= 0) {
-        atomicAdd(&m.ctr->top[level], 1);
-        atomicOr(&m.ctr->error_flags, kErrHeapFull);
+        atomicAdd(&m.ctr->top[level].v, 1);
+        atomicOr(&m.ctr->error_flags.v, kErrHeapFull);
         return -1;
     }
     return (int64_t)m.stack[level][top - 1];
@@ -46,7 +46,7 @@ __device__ inline int64_t pop_slot(const DevMap& m, int level) {
 // Slots freed by a merge wait in a pending list until the frame's end (a stack that is popped
 // in the same launch is never pushed).
 __device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
-    const uint32_t p = atomicAdd(&m.ctr->pending[level], 1u);
+    const uint32_t p = atomicAdd(&m.ctr->pending[level].v, 1u);
     m.pend[level][p] = slot;
 }
 
@@ -55,14 +55,14 @@ __device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
 // written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
 template <int ST>
 __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
-                                   bool have, bool dirty, int nupd, double dsum, int dcnt) {
+                                   bool have, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc) {
     const int lane = lane_id();
     const uint32_t slot = info & kSlotMask;
     const size_t base = (size_t)slot * 512 + (size_t)lane * 8;
     dsum = wave_sum(dsum);
     dcnt = wave_sum(dcnt);
-    const double vsum = m.bvsum[id] + dsum;
-    const uint32_t vcnt = m.bvcnt[id] + (uint32_t)dcnt;
+    const double vsum = bvs + dsum;
+    const uint32_t vcnt = bvc + (uint32_t)dcnt;
     bool merge = nupd > 0 && m.levels > 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
     int64_t cslot = -1;
     if (merge) {
@@ -108,15 +108,15 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
 // 8 consecutive lanes.  Returns 1 when the block merged.
 template <int ST>
 __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
-                                     float S2, bool dirty, int nupd, double dsum, int dcnt) {
+                                     float S2, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc) {
     const int lane = lane_id();
     const int side = 8 >> level, nv = side * side * side;
     const uint32_t slot = info & kSlotMask;
     const size_t at = (size_t)slot * nv + lane;
     dsum = wave_sum(dsum);
     dcnt = wave_sum(dcnt);
-    const double vsum = m.bvsum[id] + dsum;
-    const uint32_t vcnt = m.bvcnt[id] + (uint32_t)dcnt;
+    const double vsum = bvs + dsum;
+    const uint32_t vcnt = bvc + (uint32_t)dcnt;
     bool merge = nupd > 0 && level < m.levels - 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
     int64_t cslot = -1;
     if (merge) {
@@ -231,7 +231,7 @@ __device__ inline uint32_t update_task_count(const TaskCounts& c) {
 // own (RGB-D); otherwise they are queued like every other block (LiDAR first touch).
 __device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new) {
     TaskCounts c;
-    for (int l = 0; l < 4; ++l) c.n[l] = m.ctr->vis_n[l];
+    for (int l = 0; l < 4; ++l) c.n[l] = m.ctr->vis_n[l].v;
     c.new_base = m.ctr->n_prev;
     const uint32_t nb = m.ctr->n_blocks < m.max_blocks ? m.ctr->n_blocks : m.max_blocks;
     c.n_new = with_new && nb > c.new_base ? nb - c.new_base : 0u;
@@ -252,16 +252,16 @@ __device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
 
 // Queue block `id` for this frame's update on the list of its level (lanes with level < 0 queue
 // nothing).  Called by every lane of the wave; one atomic per level per wave.
-__device__ inline void queue_block(const DevMap& m, int level, uint32_t id) {
+__device__ inline void queue_block(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key) {
     const int lane = lane_id();
     for (int lv = 0; lv < 4; ++lv) {
         const unsigned long long msk = __ballot(level == lv);
         if (!msk) continue;
         const int f0 = __ffsll((long long)msk) - 1;
         uint32_t vb = 0;
-        if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[lv], (uint32_t)__popcll(msk));
+        if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[lv].v, (uint32_t)__popcll(msk));
         vb = (uint32_t)__shfl((int)vb, f0);
-        if (level == lv) m.vis[lv][vb + rank_in_mask(msk)] = id;
+        if (level == lv) m.vis[lv][vb + rank_in_mask(msk)] = make_entry(id, info, key);
     }
 }
 
@@ -276,8 +276,8 @@ __device__ inline void finalize_map(const DevMap& m) {
     __shared__ unsigned long long s_new;
     if (threadIdx.x == 0) {
         for (int n = 0; n < 4; ++n) {
-            s_top[n] = c->top[n];
-            s_pend[n] = n < m.levels ? c->pending[n] : 0u;
+            s_top[n] = c->top[n].v;
+            s_pend[n] = n < m.levels ? c->pending[n].v : 0u;
         }
         const uint32_t avail = s_top[0] > 0 ? (uint32_t)s_top[0] : 0u;
         const uint32_t pops = c->pops0;
@@ -298,9 +298,9 @@ __device__ inline void finalize_map(const DevMap& m) {
     }
     if (threadIdx.x == 0) {
         for (int n = 0; n < 4; ++n) {
-            c->top[n] = s_top[n] + (int32_t)s_pend[n];
-            c->pending[n] = 0;
-            c->vis_n[n] = 0;
+            c->top[n].v = s_top[n] + (int32_t)s_pend[n];
+            c->pending[n].v = 0;
+            c->vis_n[n].v = 0;
         }
         c->pops0 = 0;
         c->frames += 1;
@@ -312,16 +312,16 @@ __device__ inline void finalize_map(const DevMap& m) {
 // Queue block `id` on the update list of `level` (level < 0 queues nothing).  Called by every
 // thread of the workgroup (a barrier inside): positions come from LDS counters and one global
 // atomic per level per workgroup, since same-address device atomics serialise chip-wide.
-__device__ inline void queue_block_wg(const DevMap& m, int level, uint32_t id) {
+__device__ inline void queue_block_wg(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key) {
     __shared__ uint32_t lcnt[4], lbase[4];
     if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
     __syncthreads();
     uint32_t local = 0;
     if (level >= 0) local = atomicAdd(&lcnt[level], 1u);
     __syncthreads();
-    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[threadIdx.x], lcnt[threadIdx.x]);
+    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[threadIdx.x].v, lcnt[threadIdx.x]);
     __syncthreads();
-    if (level >= 0) m.vis[level][lbase[level] + local] = id;
+    if (level >= 0) m.vis[level][lbase[level] + local] = make_entry(id, info, key);
 }
 
 // The block table entry of a new key that took hash slot `slot`: block id `id` and, as the
@@ -331,17 +331,17 @@ __device__ inline void register_block(const DevMap& m, unsigned long long key, u
                                       uint32_t pop) {
     if (id >= m.max_blocks) {
         m.hvals[slot] = kInvalidId;
-        atomicOr(&m.ctr->error_flags, kErrBlockLimit);
+        atomicOr(&m.ctr->error_flags.v, kErrBlockLimit);
         stat_add(m, S_FAILED, 1ull);
         return;
     }
-    const int32_t t0 = m.ctr->top[0];
+    const int32_t t0 = m.ctr->top[0].v;
     uint32_t info;
     if ((int64_t)pop < (int64_t)t0) {
         info = m.stack[0][(uint32_t)t0 - 1u - pop] | kNewBit;
     } else {
         info = kNoBlockBit;
-        atomicOr(&m.ctr->error_flags, kErrHeapFull);
+        atomicOr(&m.ctr->error_flags.v, kErrHeapFull);
         stat_add(m, S_FAILED, 1ull);
     }
     m.bkey[id] = key;
@@ -389,7 +389,7 @@ __device__ inline bool claim_keys(const DevMap& m, bool has_key, unsigned long l
             if (r == INS_NEW) {
                 is_new = true;
             } else if (r == INS_FULL) {
-                atomicOr(&m.ctr->error_flags, kErrTableFull);
+                atomicOr(&m.ctr->error_flags.v, kErrTableFull);
                 stat_add(m, S_FAILED, 1ull);
             }
         }
