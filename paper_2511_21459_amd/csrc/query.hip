@@ -22,6 +22,15 @@ struct QueryResult {
     double grad[3];  // d sdf / d x (world)
 };
 
+// Block table row of `key` for a query corner: the home slot is read for all corners at once, and
+// only a corner whose home slot holds another key walks the probe sequence.
+__device__ inline uint32_t corner_info(const DevMap& m, unsigned long long key, unsigned long long home_key,
+                                       uint32_t home_slot_id) {
+    if (home_key == key) return m.hvals[home_slot_id];
+    if (home_key == kEmptyKey) return kInvalidId;
+    return find_block(m, key);
+}
+
 template <int ST>
 __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bool strict) {
     QueryResult q;
@@ -34,7 +43,8 @@ __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bo
         if (!(__builtin_fabs(fb) <= (double)kKeyLimit)) return q;
         b[k] = (int64_t)fb;
     }
-    const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
+    const unsigned long long hkey = pack_key(b[0], b[1], b[2]);
+    const uint32_t id = find_block(m, hkey);
     if (id == kInvalidId) return q;
     const uint32_t info = m.binfo[id];
     if (info & kNoBlockBit) return q;
@@ -48,35 +58,54 @@ __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bo
         i0[k] = (int64_t)fl;
         f[k] = g - fl;
     }
+    // the corners' blocks: along each axis the 2 lattice points lie in block lo or lo + 1
+    int64_t blo[3];
+    int cross[3];
+    for (int k = 0; k < 3; ++k) {
+        blo[k] = i0[k] >> shift;  // floor division by the block side 2^shift
+        cross[k] = (int)(((i0[k] + 1) >> shift) - blo[k]);
+    }
+    // rows of the (up to 8) distinct blocks, addressed by (dx, dy, dz) in {0, 1}^3; all home
+    // slots are read before any is examined
+    unsigned long long bkeys[8], hk[8];
+    uint32_t hs[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        const bool need = (dx <= cross[0]) && (dy <= cross[1]) && (dz <= cross[2]);
+        bkeys[c] = pack_key(blo[0] + dx, blo[1] + dy, blo[2] + dz);
+        hs[c] = home_slot(bkeys[c], m.hmask);
+        hk[c] = (!need || bkeys[c] == hkey) ? hkey : __hip_atomic_load(&m.hkeys[hs[c]], __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint32_t binfo8[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        const bool need = (dx <= cross[0]) && (dy <= cross[1]) && (dz <= cross[2]);
+        uint32_t cid = kInvalidId;
+        if (need) cid = bkeys[c] == hkey ? id : corner_info(m, bkeys[c], hk[c], hs[c]);
+        binfo8[c] = cid == kInvalidId ? kNoBlockBit : (cid == id ? info : m.binfo[cid]);
+    }
+    // the 8 corner voxels: heap positions first, then all weight and TSDF reads
     double cw[8], cd[8];
-    uint32_t valid_mask = 0;
-    double wsum = 0.0, num = 0.0;
-    bool any_pos = false;
-    // one-entry cache of the last neighbouring block looked up
-    unsigned long long ckey = kEmptyKey;
-    uint32_t cinfo = kNoBlockBit;
-    const unsigned long long hkey = pack_key(b[0], b[1], b[2]);
+    size_t at8[8];
+    int lv8[8];
+    uint32_t have = 0;
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int dl[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
         int64_t cell[3], cb[3];
+        int sel = 0;
         for (int k = 0; k < 3; ++k) {
             cell[k] = i0[k] + dl[k];
-            cb[k] = cell[k] >> shift;  // floor division by the block side 2^shift
+            cb[k] = cell[k] >> shift;
+            sel |= (int)(cb[k] - blo[k]) << k;
         }
         cw[c] = ((dl[0] ? f[0] : 1.0 - f[0]) * (dl[1] ? f[1] : 1.0 - f[1])) * (dl[2] ? f[2] : 1.0 - f[2]);
-        cd[c] = 0.0;
-        const unsigned long long key = pack_key(cb[0], cb[1], cb[2]);
-        uint32_t binf;
-        if (key == hkey) {
-            binf = info;
-        } else {
-            if (key != ckey) {
-                ckey = key;
-                const uint32_t id2 = find_block(m, key);
-                cinfo = id2 == kInvalidId ? kNoBlockBit : m.binfo[id2];
-            }
-            binf = cinfo;
-        }
+        const uint32_t binf = binfo8[sel];
+        at8[c] = 0;
+        lv8[c] = 0;
         if (binf & kNoBlockBit) continue;
         const int n2 = (int)((binf >> kLevelShift) & 3u);
         int idx[3];
@@ -86,10 +115,25 @@ __device__ inline QueryResult query_point(const DevMap& m, const double x[3], bo
             idx[k] = (int)((p2 - 16 * cb[k]) >> (n2 + 1));
         }
         const int m2 = 8 >> n2;
-        const size_t at = (size_t)(binf & kSlotMask) * (size_t)(m2 * m2 * m2) + (size_t)morton3(idx[0], idx[1], idx[2]);
-        const uint32_t W = Store<ST>::getW(m, n2, at);
-        if (W == 0) continue;
-        cd[c] = (double)Store<ST>::getD(m, n2, at);
+        at8[c] = (size_t)(binf & kSlotMask) * (size_t)(m2 * m2 * m2) + (size_t)morton3(idx[0], idx[1], idx[2]);
+        lv8[c] = n2;
+        have |= 1u << c;
+    }
+    uint32_t W8[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        W8[c] = Store<ST>::getW(m, lv8[c], at8[c]);
+        cd[c] = (double)Store<ST>::getD(m, lv8[c], at8[c]);
+    }
+    uint32_t valid_mask = 0;
+    double wsum = 0.0, num = 0.0;
+    bool any_pos = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!(have & (1u << c)) || W8[c] == 0) {
+            cd[c] = 0.0;
+            continue;
+        }
         valid_mask |= 1u << c;
         wsum += cw[c];
         num += cw[c] * cd[c];
@@ -182,12 +226,21 @@ __global__ __launch_bounds__(256) void k_query_backward(const DevMap* __restrict
     }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partials, int nparts, double* out) {
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += partials[(size_t)b * 6 + threadIdx.x];
-        out[threadIdx.x] = s;
+// Final pose-gradient sum over the workgroup partials, in a fixed order (one workgroup of 256):
+// strided per-thread sums, then a tree in LDS.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int nparts, double* out) {
+    __shared__ double red[6][256];
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += 256)
+        for (int k = 0; k < 6; ++k) s[k] += partials[(size_t)b * 6 + k];
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 static bool make_params(const double* T, int32_t strict, QueryParams& qp) {
@@ -246,7 +299,7 @@ extern "C" mrh_status mrh_query_sdf_backward(mrh_map* map, const float* pts_dev,
         }
     });
     launch(map, K_REDUCE, [&] {
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, map->stream, map->partials, grid, map->pose_out);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, map->stream, map->partials, grid, map->pose_out);
     });
     mrh_status st = check_hip(map, hipGetLastError(), "query_sdf_backward");
     if (st != MRH_OK) return st;
