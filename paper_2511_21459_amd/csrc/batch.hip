@@ -18,7 +18,7 @@
 
 namespace mrh {
 
-mrh_status ensure_lidar(mrh_map* map);
+mrh_status ensure_lidar(mrh_map* map, int64_t n);
 bool depth_size_ok(int32_t width, int32_t height);
 mrh_status attach_tiles(mrh_map* map, int32_t width, int32_t height, DepthFrame& f);
 
@@ -121,7 +121,7 @@ struct mrh_batch {
     BatchEntry* h_ents[2] = {nullptr, nullptr};
     hipEvent_t copied[2] = {nullptr, nullptr};
     int buf = 0;
-    std::vector<char> lidar_seen;  // map accumulators present when d_maps was last uploaded
+    std::vector<uint32_t> dm_seen;  // each map's descriptor version when d_maps was last uploaded
     int32_t update_wgs = 1024, cull_wgs = 32, use_graph = 1;
     hipGraphExec_t exec = nullptr;
     std::vector<int64_t> graph_sig;  // launch geometry the graph was captured with
@@ -177,7 +177,7 @@ mrh_status mrh_batch_create(mrh_map* const* maps, int32_t n_maps, mrh_batch** ou
     b->n = n_maps;
     b->storage = maps[0]->cfg.storage;
     b->stream = maps[0]->stream;
-    b->lidar_seen.assign(n_maps, 0);
+    b->dm_seen.assign(n_maps, ~0u);
     bool ok = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc((void**)&b->d_maps, sizeof(DevMap) * n_maps) == hipSuccess &&
               hipMalloc((void**)&b->d_ents, sizeof(BatchEntry) * n_maps) == hipSuccess;
@@ -238,17 +238,17 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         const mrh_frame& f = frames[i];
         if (f.kind != MRH_FRAME_NONE && f.kind != MRH_FRAME_DEPTH && f.kind != MRH_FRAME_POINTS)
             return batch_err(b, MRH_ERR_INVALID_ARG, "batch: unknown frame kind");
-        if (f.kind == MRH_FRAME_POINTS && f.n > 0 && !b->maps[i]->lidar_ready) {
-            const mrh_status st = ensure_lidar(b->maps[i]);
+        if (f.kind == MRH_FRAME_POINTS && f.n > 0) {
+            const mrh_status st = ensure_lidar(b->maps[i], f.n);
             if (st != MRH_OK) return st;
         }
-        if ((char)b->maps[i]->lidar_ready != b->lidar_seen[i]) refresh = true;
+        if (b->maps[i]->dm_version != b->dm_seen[i]) refresh = true;
     }
     if (refresh) {
         std::vector<DevMap> dm(n);
         for (int i = 0; i < n; ++i) {
             dm[i] = b->maps[i]->dm;
-            b->lidar_seen[i] = (char)b->maps[i]->lidar_ready;
+            b->dm_seen[i] = b->maps[i]->dm_version;
         }
         if (hipStreamSynchronize(b->stream) != hipSuccess ||
             hipMemcpy(b->d_maps, dm.data(), sizeof(DevMap) * n, hipMemcpyHostToDevice) != hipSuccess)

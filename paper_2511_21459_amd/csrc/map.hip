@@ -27,6 +27,7 @@ mrh_status check_hip(mrh_map* m, hipError_t e, const char* what) {
 // Kernels read the map descriptor through a pointer: a ~900-byte by-value argument would not fit
 // the scalar register file and would be spilled into vector lanes on every launch.
 mrh_status upload_descriptor(mrh_map* m) {
+    ++m->dm_version;
     mrh_status st = check_hip(m, hipMemcpyAsync(m->dmd, &m->dm, sizeof(DevMap), hipMemcpyHostToDevice, m->stream),
                               "descriptor upload");
     if (st == MRH_OK) st = check_hip(m, hipStreamSynchronize(m->stream), "descriptor upload");
@@ -136,6 +137,8 @@ static void free_all(mrh_map* m) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);
+    if (d.rkeys) (void)hipFree(d.rkeys);
+    if (d.rcount) (void)hipFree(d.rcount);
     if (m->tile_max) (void)hipFree(m->tile_max);
     for (int n = 0; n < 4; ++n)
         if (d.vis[n]) (void)hipFree(d.vis[n]);

@@ -89,6 +89,11 @@ struct DevMap {
     unsigned long long* acc_s1[4];
     unsigned long long* acc_s2[4];
     uint32_t* btouch;  // per block: touched by a ray this frame
+    // LiDAR: the block keys each ray's walk visits, in walk order (rcap_k per ray, written by the
+    // allocation launch), and their count per ray (may exceed rcap_k)
+    unsigned long long* rkeys;
+    uint32_t* rcount;
+    int32_t rcap_k;
     uint4* vis[4];     // per level: the blocks the update visits this frame, (id, info, key lo, key hi)
     double B, invB;
     double nu[4], inv_nu[4];
@@ -369,6 +374,8 @@ struct mrh_map {
     double* pose_out = nullptr;  // 6 doubles, final reduction
     int32_t partials_cap = 0;
     bool lidar_ready = false;    // accumulators allocated
+    int64_t rcap_n = 0;          // rays the per-ray block-key buffers hold
+    uint32_t dm_version = 0;     // bumped whenever the device copy of dm is rewritten
     float* tile_max = nullptr;   // per 16 x 16 pixel tile of the current depth frame: largest valid depth
     size_t tile_cap = 0;
     bool profiling = false;      // bracket every launch with events (mrh_profile_enable)

@@ -60,11 +60,18 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
     Walk w;
     if (in_range) w.init(a, e, m.invB);
     bool active = in_range;
+    uint32_t steps = 0;
+    unsigned long long* rk = m.rkeys + (size_t)(i < sp.n ? i : 0) * (size_t)m.rcap_k;
     while (__ballot(active)) {
         const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
         insert_keys(m, active, key);
-        if (active) active = w.next();
+        if (active) {
+            if (steps < (uint32_t)m.rcap_k) rk[steps] = key;
+            ++steps;
+            active = w.next();
+        }
     }
+    if (i < sp.n) m.rcount[i] = steps;
 }
 
 // Saturated (+tau) observations of voxels near the sensor origin are first counted in a
@@ -203,55 +210,94 @@ struct BoxWalk {
     }
 };
 
-// Traversal and accumulation of one ray (segment a..e, surface point p, direction nn).
+// The observations of one ray (segment a..e, surface point p, direction nn) inside the block
+// `key` that its walk visits: the block walk restricted to the block's own voxel lattice.
 template <int ST>
-__device__ inline void ray_walk(const DevMap& m, const ScanParams& sp, const double a[3], const double e[3],
-                                const double p[3], const double nn[3], unsigned long long* tab) {
-    Walk w;
-    w.init(a, e, m.invB);
-    do {
-        const int64_t b[3] = {w.c0, w.c1, w.c2};
-        const uint32_t id = find_block(m, pack_key(b[0], b[1], b[2]));
-        const uint32_t info = id == kInvalidId ? kNoBlockBit : m.binfo[id];
-        const int level = (int)((info >> kLevelShift) & 3u);
-        // first touch of the block in this scan: queue it for the update (active lanes only)
-        const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
-        if (__ballot(first)) queue_block(m, first ? level : -1, id, info, pack_key(b[0], b[1], b[2]));
-        if (info & kNoBlockBit) continue;
-        const bool fresh = (info & kNewBit) != 0;
-        const int side = 8 >> level;
-        const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
-        const double nu = m.nu[level];
-        BoxWalk bw;
-        bw.init(a, e, b, m.B, m.inv_nu[level], side);
-        for (int s = 0;; ++s) {
-            // observation of the voxel centre (Eq. 1)
-            const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
-            const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
-            const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
-            const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
-            const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
-            bool near = false;
-            if (d >= m.tau) {
-                const double r0 = x0 - sp.P.t[0], r1 = x1 - sp.P.t[1], r2 = x2 - sp.P.t[2];
-                const double il = m.inv_nu[level];
-                near = ((r0 * r0 + r1 * r1) + r2 * r2) * (il * il) < kSatNear2;
-            }
-            accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d, near, tab);
-            if (s == 3 * side || !bw.next()) break;
+__device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const double a[3], const double e[3],
+                                 const double p[3], const double nn[3], unsigned long long key,
+                                 unsigned long long* tab) {
+    int32_t bx, by, bz;
+    unpack_key(key, bx, by, bz);
+    const int64_t b[3] = {bx, by, bz};
+    const uint32_t id = find_block(m, key);
+    const uint32_t info = id == kInvalidId ? kNoBlockBit : m.binfo[id];
+    const int level = (int)((info >> kLevelShift) & 3u);
+    // first touch of the block in this scan: queue it for the update (active lanes only)
+    const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
+    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key);
+    if (info & kNoBlockBit) return;
+    const bool fresh = (info & kNewBit) != 0;
+    const int side = 8 >> level;
+    const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
+    const double nu = m.nu[level];
+    BoxWalk bw;
+    bw.init(a, e, b, m.B, m.inv_nu[level], side);
+    for (int s = 0;; ++s) {
+        // observation of the voxel centre (Eq. 1)
+        const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
+        const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
+        const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
+        const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
+        const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
+        bool near = false;
+        if (d >= m.tau) {
+            const double r0 = x0 - sp.P.t[0], r1 = x1 - sp.P.t[1], r2 = x2 - sp.P.t[2];
+            const double il = m.inv_nu[level];
+            near = ((r0 * r0 + r1 * r1) + r2 * r2) * (il * il) < kSatNear2;
         }
-    } while (w.next());
+        accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d, near, tab);
+        if (s == 3 * side || !bw.next()) break;
+    }
 }
 
 // Traversal and accumulation for points chunk * 256 + threadIdx (all threads of the workgroup;
-// tab is the workgroup's LDS table of kSatSlots entries).
+// tab is the workgroup's LDS table of kSatSlots entries).  A ray's block walk is a serial chain,
+// so the (ray, block) pairs that the allocation launch recorded are processed in parallel instead:
+// each wave takes its 64 rays' pairs 64 at a time, lane l the l-th pair of the batch.  The blocks
+// of a ray beyond the recorded rcap_k are walked afterwards by the ray's own lane.
 template <int ST>
 __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk, unsigned long long* tab) {
     sat_table_clear(tab);
-    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const int64_t r0 = (int64_t)chunk * blockDim.x + (threadIdx.x & ~63u);
+    const int64_t own = r0 + lane;
+    const uint32_t K = (uint32_t)m.rcap_k;
+    const uint32_t cnt = own < sp.n ? m.rcount[own] : 0u;
+    const uint32_t c = cnt < K ? cnt : K;
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    const uint32_t excl = incl - c;
     double a[3], e[3], p[3], nn[3];
-    if (i < sp.n && point_segment(m, sp, i, a, e, p, nn) && segment_in_range(a, e, m.invB))
-        ray_walk<ST>(m, sp, a, e, p, nn, tab);
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t q = base + (uint32_t)lane;
+        // owner: the largest lane j with excl_j <= q (excl is non-decreasing over the lanes)
+        int j = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t ej = (uint32_t)__shfl((int)excl, j + step);
+            if (ej <= q) j += step;
+        }
+        const uint32_t ej = (uint32_t)__shfl((int)excl, j);
+        if (q < total) {
+            const int64_t i = r0 + j;
+            point_segment(m, sp, i, a, e, p, nn);  // valid: the ray has recorded blocks
+            ray_block<ST>(m, sp, a, e, p, nn, m.rkeys[(size_t)i * K + (q - ej)], tab);
+        }
+    }
+    if (cnt > K) {
+        point_segment(m, sp, own, a, e, p, nn);
+        Walk w;
+        w.init(a, e, m.invB);
+        bool more = true;
+        for (uint32_t s = 0; s < K && more; ++s) more = w.next();
+        while (more) {
+            ray_block<ST>(m, sp, a, e, p, nn, pack_key(w.c0, w.c1, w.c2), tab);
+            more = w.next();
+        }
+    }
     sat_table_flush(m, tab);
 }
 

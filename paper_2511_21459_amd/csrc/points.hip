@@ -30,25 +30,49 @@ __global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__
     flush_task_stats(m, as);
 }
 
-mrh_status ensure_lidar(mrh_map* map) {
-    if (map->lidar_ready) return MRH_OK;
+// Blocks a ray's walk can visit: the guard of the block walk bounds it by 4 + the sum over the
+// axes of the cells the segment spans (carving: up to max_range + tau long; otherwise 2 tau).
+static int32_t ray_block_cap(const mrh_config& c) {
+    const double len = c.carve ? c.max_range + c.tau : 2.0 * c.tau;
+    const double cells = 1.7320508075688772 * len / (8.0 * c.voxel) + 8.0;
+    return cells < 1024.0 ? (int32_t)cells : 1024;
+}
+
+// LiDAR state of a map: accumulators (first scan) and per-ray block-key buffers for n rays.
+mrh_status ensure_lidar(mrh_map* map, int64_t n) {
     DevMap& d = map->dm;
     mrh_status st = MRH_OK;
+    bool changed = false;
     auto alloc = [&](void** p, size_t bytes, const char* what) {
         if (st != MRH_OK) return;
         st = check_hip(map, hipMalloc(p, bytes), what);
         if (st == MRH_OK) st = check_hip(map, hipMemsetAsync(*p, 0, bytes, map->stream), what);
+        changed = true;
     };
-    alloc((void**)&d.btouch, (size_t)d.max_blocks * 4, "touch flags");
-    for (int n = 0; n < map->cfg.levels; ++n) {
-        const size_t nv = (size_t)d.heap_cap[n] * (size_t)(side_of(n) * side_of(n) * side_of(n));
-        alloc((void**)&d.acc_sat[n], nv * 4, "scan accumulators");
-        alloc((void**)&d.acc_band[n], nv * 4, "scan accumulators");
-        alloc((void**)&d.acc_s1[n], nv * 8, "scan accumulators");
-        alloc((void**)&d.acc_s2[n], nv * 8, "scan accumulators");
+    if (!map->lidar_ready) {
+        alloc((void**)&d.btouch, (size_t)d.max_blocks * 4, "touch flags");
+        for (int l = 0; l < map->cfg.levels; ++l) {
+            const size_t nv = (size_t)d.heap_cap[l] * (size_t)(side_of(l) * side_of(l) * side_of(l));
+            alloc((void**)&d.acc_sat[l], nv * 4, "scan accumulators");
+            alloc((void**)&d.acc_band[l], nv * 4, "scan accumulators");
+            alloc((void**)&d.acc_s1[l], nv * 8, "scan accumulators");
+            alloc((void**)&d.acc_s2[l], nv * 8, "scan accumulators");
+        }
+        d.rcap_k = ray_block_cap(map->cfg);
+        if (st == MRH_OK) map->lidar_ready = true;
     }
-    if (st == MRH_OK) st = upload_descriptor(map);
-    if (st == MRH_OK) map->lidar_ready = true;
+    if (st == MRH_OK && n > map->rcap_n) {
+        st = check_hip(map, hipStreamSynchronize(map->stream), "ray buffers");
+        if (d.rkeys) (void)hipFree(d.rkeys);
+        if (d.rcount) (void)hipFree(d.rcount);
+        d.rkeys = nullptr;
+        d.rcount = nullptr;
+        map->rcap_n = 0;
+        alloc((void**)&d.rkeys, (size_t)n * (size_t)d.rcap_k * 8, "ray block keys");
+        alloc((void**)&d.rcount, (size_t)n * 4, "ray block counts");
+        if (st == MRH_OK) map->rcap_n = n;
+    }
+    if (st == MRH_OK && changed) st = upload_descriptor(map);
     return st;
 }
 
@@ -62,7 +86,7 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
     if (!pose_from(T_ws, sp.P)) return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose");
     sp.xyz = xyz_dev;
     sp.n = n;
-    mrh_status st = ensure_lidar(map);
+    mrh_status st = ensure_lidar(map, n);
     if (st != MRH_OK) return st;
     if (n > 0) {
         const unsigned grid = (unsigned)((n + 255) / 256);
