@@ -4,7 +4,8 @@
 //
 //   k_batch_alloc     workgroup ranges per map: depth maps get their pixel tiles then their cull
 //                     workgroups, LiDAR maps one workgroup per 256 points
-//   k_batch_rays      LiDAR maps: one workgroup per 256 points (traversal and accumulation)
+//   k_batch_rays      LiDAR maps: one workgroup per kRaysPerGroup rays (their recorded (ray, block)
+//                     pairs in parallel: traversal and accumulation)
 //   k_batch_update    the update tasks of every map (per-level queues), each wave taking a
 //                     contiguous range of the concatenated task space (mostly one map per wave)
 //   k_batch_finalize  one workgroup per map
@@ -284,9 +285,8 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
                 return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad point frame");
             e.sp.xyz = f.data_dev;
             e.sp.n = f.n;
-            const uint32_t chunks = (uint32_t)((f.n + 255) / 256);
-            alloc_wgs += chunks;
-            ray_wgs += chunks;
+            alloc_wgs += (uint32_t)((f.n + 255) / 256);
+            ray_wgs += (uint32_t)((f.n + kRaysPerGroup - 1) / kRaysPerGroup);
         }
         e.alloc_end = alloc_wgs;
         e.ray_end = ray_wgs;

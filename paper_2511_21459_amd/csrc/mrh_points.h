@@ -80,7 +80,7 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
 // flushed with one global atomic per distinct voxel once the workgroup's rays are done.  The counts
 // are integers, so the result equals adding them one at a time.  An entry is (key + 1) << 32 | count
 // with key = level << 30 | heap position; keys are never removed while rays run.
-constexpr int kSatBits = 12;
+constexpr int kSatBits = 9;
 constexpr int kSatSlots = 1 << kSatBits;
 constexpr double kSatNear2 = 1024.0;  // voxels within 32 voxel edges of the origin use the table
 
@@ -250,19 +250,23 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
     }
 }
 
-// Traversal and accumulation for points chunk * 256 + threadIdx (all threads of the workgroup;
-// tab is the workgroup's LDS table of kSatSlots entries).  A ray's block walk is a serial chain,
-// so the (ray, block) pairs that the allocation launch recorded are processed in parallel instead:
-// each wave takes its 64 rays' pairs 64 at a time, lane l the l-th pair of the batch.  The blocks
-// of a ray beyond the recorded rcap_k are walked afterwards by the ray's own lane.
+// Rays per wave of the ray launch, and per 256-thread workgroup.
+constexpr int kRaysPerWave = 2;
+constexpr int kRaysPerGroup = 4 * kRaysPerWave;
+
+// Traversal and accumulation for rays chunk * kRaysPerGroup .. (all threads of the workgroup; tab
+// is the workgroup's LDS table of kSatSlots entries).  A ray's block walk is a serial chain of
+// lookups, so the (ray, block) pairs that the allocation launch recorded are processed in parallel
+// instead: each wave takes its kRaysPerWave rays' pairs 64 at a time, lane l the l-th pair of the
+// batch.  The blocks of a ray beyond the recorded rcap_k are walked afterwards by the ray's lane.
 template <int ST>
 __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk, unsigned long long* tab) {
     sat_table_clear(tab);
     const int lane = lane_id();
-    const int64_t r0 = (int64_t)chunk * blockDim.x + (threadIdx.x & ~63u);
+    const int64_t r0 = (int64_t)chunk * kRaysPerGroup + (int64_t)(threadIdx.x >> 6) * kRaysPerWave;
     const int64_t own = r0 + lane;
     const uint32_t K = (uint32_t)m.rcap_k;
-    const uint32_t cnt = own < sp.n ? m.rcount[own] : 0u;
+    const uint32_t cnt = (lane < kRaysPerWave && own < sp.n) ? m.rcount[own] : 0u;
     const uint32_t c = cnt < K ? cnt : K;
     uint32_t incl = c;
     for (int o = 1; o < 64; o <<= 1) {

@@ -92,11 +92,12 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
         const unsigned grid = (unsigned)((n + 255) / 256);
         launch(map, K_ALLOC_POINTS,
                [&] { hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); });
+        const unsigned rgrid = (unsigned)((n + kRaysPerGroup - 1) / kRaysPerGroup);
         launch(map, K_RAYS, [&] {
             switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_rays<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); break;
-                default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp);
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_rays<MRH_STORE_F16>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp); break;
+                default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp);
             }
         });
         launch(map, K_APPLY_POINTS, [&] {
