@@ -34,12 +34,18 @@ struct BatchEntry {
     ScanParams sp;
 };
 
+// The entry whose workgroup range holds workgroup b (all lanes of the wave active; n <= 64):
+// lane i tests entry i, so the ranges are read in one round trip.
 __device__ inline int entry_of(const BatchEntry* __restrict__ e, int n, uint32_t b, bool rays) {
-    for (int i = 0; i < n; ++i) {
-        const uint32_t lo = rays ? e[i].ray_begin : e[i].alloc_begin, hi = rays ? e[i].ray_end : e[i].alloc_end;
-        if (b >= lo && b < hi) return i;
+    const int lane = lane_id();
+    bool hit = false;
+    if (lane < n) {
+        const uint32_t lo = rays ? e[lane].ray_begin : e[lane].alloc_begin;
+        const uint32_t hi = rays ? e[lane].ray_end : e[lane].alloc_end;
+        hit = b >= lo && b < hi;
     }
-    return -1;
+    const unsigned long long msk = __ballot(hit);
+    return msk ? __ffsll((long long)msk) - 1 : -1;
 }
 
 __global__ __launch_bounds__(256) void k_batch_alloc(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
@@ -71,10 +77,12 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
                                                       int n) {
     __shared__ TaskCounts cnt[kMaxBatch];
     __shared__ uint32_t pre[kMaxBatch + 1];
+    __shared__ unsigned long long wst[kMaxBatch][5];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         if (ents[i].kind == MRH_FRAME_NONE) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
         else cnt[i] = frame_task_counts(maps[i], ents[i].kind == MRH_FRAME_DEPTH);
     }
+    for (int k = threadIdx.x; k < 5 * n; k += blockDim.x) wst[k / 5][k % 5] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
         pre[0] = 0;
@@ -84,23 +92,42 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
     const uint32_t total = pre[n];
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t t0 = (uint32_t)(((unsigned long long)total * wave) / nwaves);
-    const uint32_t t1 = (uint32_t)(((unsigned long long)total * (wave + 1)) / nwaves);
+    // strided over the concatenated task space (neighbouring tasks cost alike, so striding spreads
+    // the expensive runs); a wave's statistics go to per-map LDS sums, flushed once per workgroup
     int cur = -1;
     TaskStats ts;
-    for (uint32_t t = t0; t < t1; ++t) {
-        int i = cur < 0 ? 0 : cur;
-        while (t >= pre[i + 1]) ++i;
-        if (i != cur) {
-            if (cur >= 0) flush_task_stats(maps[cur], ts);
-            ts = TaskStats();
-            cur = i;
+    auto flush = [&](int i) {
+        const unsigned long long lo = wave_sum(ts.lane_obs), lm = wave_sum(ts.lane_merges);
+        if (lane_id() == 0) {
+            atomicAdd(&wst[i][0], ts.obs + lo);
+            atomicAdd(&wst[i][1], ts.fresh);
+            atomicAdd(&wst[i][2], ts.merges[0]);
+            atomicAdd(&wst[i][3], ts.merges[1]);
+            atomicAdd(&wst[i][4], lm);
         }
-        const uint32_t local = t - pre[i];
-        if (ents[i].kind == MRH_FRAME_DEPTH) depth_update_task<ST>(maps[i], ents[i].df, local, cnt[i], ts);
-        else points_update_task<ST>(maps[i], local, cnt[i], ts);
+    };
+    for (uint32_t t = wave; t < total; t += nwaves) {
+        // the map of task t: the largest i with pre[i] <= t
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        if (lo != cur) {
+            if (cur >= 0) flush(cur);
+            ts = TaskStats();
+            cur = lo;
+        }
+        const uint32_t local = t - pre[lo];
+        if (ents[lo].kind == MRH_FRAME_DEPTH) depth_update_task<ST>(maps[lo], ents[lo].df, local, cnt[lo], ts);
+        else points_update_task<ST>(maps[lo], local, cnt[lo], ts);
     }
-    if (cur >= 0) flush_task_stats(maps[cur], ts);
+    if (cur >= 0) flush(cur);
+    __syncthreads();
+    const int sid[5] = {S_OBS, S_OBS_FRESH, S_MERGE0, S_MERGE1, S_MERGE2};
+    for (int k = threadIdx.x; k < 5 * n; k += blockDim.x)
+        if (wst[k / 5][k % 5]) stat_add(maps[k / 5], sid[k % 5], wst[k / 5][k % 5]);
 }
 
 __global__ void k_batch_finalize(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents, int n) {
