@@ -312,7 +312,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
                 return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad point frame");
             e.sp.xyz = f.data_dev;
             e.sp.n = f.n;
-            alloc_wgs += (uint32_t)((f.n + 255) / 256);
+            alloc_wgs += (uint32_t)((f.n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup);
             ray_wgs += (uint32_t)((f.n + kRaysPerGroup - 1) / kRaysPerGroup);
         }
         e.alloc_end = alloc_wgs;

@@ -1,10 +1,12 @@
 // LiDAR fusion work units (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3 and Eq. 5; Sec. 3.2.1),
 // shared by the single-map kernels (points.hip) and the batched kernels (batch.hip).
 //
-//   points_alloc_chunk  256 points: validity, segment [o, p + tau n] (carving) or the band
-//                       [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated insert
-//   points_ray_chunk    256 points: the same block walk; inside each block a walk over the block's
-//                       own voxel lattice; each crossed voxel gets clip((p - x) . n, -tau, tau).
+//   points_alloc_chunk  16 rays: validity, segment [o, p + tau n] (carving) or the band
+//                       [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated
+//                       insert, and the record of each ray's block keys in walk order
+//   points_ray_chunk    8 rays: their recorded (ray, block) pairs in parallel; inside each block a
+//                       walk over the block's own voxel lattice; each crossed voxel gets
+//                       clip((p - x) . n, -tau, tau).
 //                       Saturated observations (+tau) only bump an integer count; the others add to
 //                       fixed-point sums of (d - D) and (d - D)^2, D being the voxel's mean at the
 //                       start of the scan, so the accumulation is exact and order-independent.  A
@@ -44,12 +46,19 @@ __device__ inline bool point_segment(const DevMap& m, const ScanParams& sp, int6
     return true;
 }
 
-// Allocation for points chunk * 256 + threadIdx.
+// Rays per wave of the allocation launch (each ray's block walk is a serial chain of lookups, so
+// waves carry few rays and many waves are in flight), and per 256-thread workgroup.
+constexpr int kAllocRaysPerWave = 4;
+constexpr int kAllocRaysPerGroup = 4 * kAllocRaysPerWave;
+
+// Allocation for rays chunk * kAllocRaysPerGroup ..: the block walk of each ray, the wave-
+// deduplicated insert of the keys, and the record of each ray's keys in walk order.
 __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk) {
     const int lane = lane_id();
-    const int64_t i = (int64_t)chunk * blockDim.x + threadIdx.x;
+    const bool mine = lane < kAllocRaysPerWave;
+    const int64_t i = (int64_t)chunk * kAllocRaysPerGroup + (int64_t)(threadIdx.x >> 6) * kAllocRaysPerWave + lane;
     double a[3], e[3], p[3], nn[3];
-    const bool ok = i < sp.n && point_segment(m, sp, i, a, e, p, nn);
+    const bool ok = mine && i < sp.n && point_segment(m, sp, i, a, e, p, nn);
     const unsigned long long vmask = __ballot(ok);
     const bool in_range = ok && segment_in_range(a, e, m.invB);
     const unsigned long long dmask = __ballot(ok && !in_range);
@@ -71,7 +80,7 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
             active = w.next();
         }
     }
-    if (i < sp.n) m.rcount[i] = steps;
+    if (mine && i < sp.n) m.rcount[i] = steps;
 }
 
 // Saturated (+tau) observations of voxels near the sensor origin are first counted in a

@@ -89,9 +89,9 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
     mrh_status st = ensure_lidar(map, n);
     if (st != MRH_OK) return st;
     if (n > 0) {
-        const unsigned grid = (unsigned)((n + 255) / 256);
+        const unsigned agrid = (unsigned)((n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup);
         launch(map, K_ALLOC_POINTS,
-               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(grid), dim3(256), 0, map->stream, map->dmd, sp); });
+               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(agrid), dim3(256), 0, map->stream, map->dmd, sp); });
         const unsigned rgrid = (unsigned)((n + kRaysPerGroup - 1) / kRaysPerGroup);
         launch(map, K_RAYS, [&] {
             switch (map->cfg.storage) {
