@@ -395,6 +395,6 @@ hipEvent_t take_event(mrh_map* m) {
 
 // launched by the integrate entry points after each frame
 void launch_finalize(mrh_map* m) {
-    launch(m, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, m->stream, m->dmd); });
+    launch(m, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(512), 0, m->stream, m->dmd); });
 }
 }  // namespace mrh

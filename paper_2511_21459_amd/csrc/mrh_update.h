@@ -265,16 +265,24 @@ __device__ inline void queue_block(const DevMap& m, int level, uint32_t id, uint
     }
 }
 
-// End of a frame for one map, by one workgroup: take this frame's level-0 pops off the stack,
-// return the slots freed by merges to their levels' stacks, publish the frame's statistics (the
-// new-block count is the growth of n_blocks), empty the update queues, note the block count.
-// Every counter is read once by thread 0 and shared through LDS, and written once by thread 0.
+// End of a frame for one map, by one workgroup of at least kStripes * 16 threads: take this frame's
+// level-0 pops off the stack, return the slots freed by merges to their levels' stacks, publish the
+// frame's statistics (the new-block count is the growth of n_blocks), empty the update queues,
+// note the block count.  Every counter and statistic is read in one round of independent loads,
+// shared through LDS, and written once.
 __device__ inline void finalize_map(const DevMap& m) {
     DevCounters* c = m.ctr;
     __shared__ int32_t s_top[4];
     __shared__ uint32_t s_pend[4];
     __shared__ unsigned long long s_new;
-    if (threadIdx.x == 0) {
+    __shared__ unsigned long long s_part[kStripes][16];
+    const int tid = threadIdx.x;
+    if (tid < kStripes * 16) {
+        const int k = tid >> 4, st = tid & 15;
+        s_part[k][st] = c->frame[k][st];
+        c->frame[k][st] = 0;
+    }
+    if (tid == 0) {
         for (int n = 0; n < 4; ++n) {
             s_top[n] = c->top[n].v;
             s_pend[n] = n < m.levels ? c->pending[n].v : 0u;
@@ -286,17 +294,14 @@ __device__ inline void finalize_map(const DevMap& m) {
     }
     __syncthreads();
     for (int n = 0; n < m.levels; ++n)
-        for (uint32_t i = threadIdx.x; i < s_pend[n]; i += blockDim.x) m.stack[n][s_top[n] + i] = m.pend[n][i];
-    if (threadIdx.x < S_COUNT) {
-        unsigned long long v = threadIdx.x == S_NEW ? s_new : 0ull;
-        for (int k = 0; k < kStripes; ++k) {
-            v += c->frame[k][threadIdx.x];
-            c->frame[k][threadIdx.x] = 0;
-        }
-        c->last[threadIdx.x] = v;
-        c->total[threadIdx.x] += v;
+        for (uint32_t i = tid; i < s_pend[n]; i += blockDim.x) m.stack[n][s_top[n] + i] = m.pend[n][i];
+    if (tid < S_COUNT) {
+        unsigned long long v = tid == S_NEW ? s_new : 0ull;
+        for (int k = 0; k < kStripes; ++k) v += s_part[k][tid];
+        c->last[tid] = v;
+        c->total[tid] += v;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         for (int n = 0; n < 4; ++n) {
             c->top[n].v = s_top[n] + (int32_t)s_pend[n];
             c->pending[n].v = 0;
