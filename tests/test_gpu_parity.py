@@ -143,6 +143,35 @@ def test_street_band_only(mrh, orc):
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)))
 
 
+def _long_ray_scan(seed):
+    """Carving rays hundreds of metres long (more blocks than the per-ray block record holds) mixed
+    with short ones."""
+    rng = np.random.default_rng(seed)
+    far = np.array([[600.0, 0.0, 0.0], [-450.0, 380.0, -20.0], [0.3, 700.0, 5.0], [500.0, -500.0, 40.0]])
+    near = rng.normal(size=(60, 3)) * 5.0 + np.array([10.0, 0.0, 0.0])
+    return np.concatenate([far, near, far * 0.999]).astype(np.float32)
+
+
+def test_lidar_long_rays(mrh, orc):
+    """Blocks past a ray's recorded capacity are walked by the ray's own lane."""
+    announce("lidar carving rays up to 900 m (block record overflow)")
+    cfg = dict(voxel=0.05, levels=2, tau=0.15, var_thr=0.025 ** 2, min_obs=2, min_range=1.0, max_range=1000.0,
+               carve=True, max_blocks=1 << 17, hash_slots=1 << 18)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for k in range(2):
+        T = np.eye(4)
+        T[:3, 3] = [0.1 + 0.37 * k, 0.2, 1.5]
+        pts = _long_ray_scan(k)
+        g.integrate_points(_dev(pts), T)
+        last, _ = g.sync()
+        st = o.integrate_points(pts, T)
+        assert last["observations"] == st["observations"], k
+        assert last["new_blocks"] == st["new_blocks"], k
+    assert o.num_blocks > 4 * 1100
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"]))
+
+
 def _query_points(n, seed=0):
     rng = np.random.default_rng(seed)
     return np.stack([rng.uniform(-0.45, 0.45, n), rng.uniform(-0.35, 0.35, n),
