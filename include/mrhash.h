@@ -71,7 +71,7 @@ typedef struct mrh_config {
 } mrh_config;
 
 typedef struct mrh_stats {
-    int64_t frames;         /* frames integrated (totals) or 1 (last frame) */
+    int64_t frames;         /* frames integrated (totals) or since the previous mrh_sync (last) */
     int64_t valid_points;   /* valid pixels or points */
     int64_t dropped_points; /* valid points whose traversal left the 21-bit key range */
     int64_t new_blocks;     /* blocks inserted */
@@ -142,9 +142,10 @@ mrh_status mrh_integrate_depth_sequence(mrh_map* map, const float* depth_dev, in
 mrh_status mrh_integrate_points_sequence(mrh_map* map, const float* xyz_dev, int32_t n_frames, int64_t n,
                                          const double* T_ws);
 
-/* Wait for the map's stream, then report.  last / totals may be NULL.  Returns the first latched
- * capacity error (MRH_ERR_TABLE_FULL, MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT) or MRH_OK, and
- * clears the latch. */
+/* Wait for the map's stream, then report.  last: the statistics of the frames integrated since
+ * the previous mrh_sync (the last frame when called after every frame); totals: since the map's
+ * creation or reset.  last / totals may be NULL.  Returns the first latched capacity error
+ * (MRH_ERR_TABLE_FULL, MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT) or MRH_OK, and clears the latch. */
 mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals);
 
 /* Trilinear SDF query (Sec. 3.4).  For each point p_i (device float32[n][3]) the world point is

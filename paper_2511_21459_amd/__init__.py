@@ -134,7 +134,8 @@ class Map:
                     "mrh_integrate_points_sequence")
 
     def sync(self):
-        """Wait for the map's stream; return (last-frame stats, totals); raise a latched error."""
+        """Wait for the map's stream; return (stats of the frames since the previous sync, totals);
+        raise a latched error."""
         last, tot = MrhStats(), MrhStats()
         self._check(_lib.load().mrh_sync(self._h, ctypes.byref(last), ctypes.byref(tot)), "mrh_sync")
         return last.as_dict(), tot.as_dict()

@@ -1,14 +1,15 @@
-// Batched fusion of many independent maps: one frame per map per call, four launches in total,
+// Batched fusion of many independent maps: one frame per map per call, three launches in total,
 // each covering every map through device-side tables (the per-map work is exactly that of the
-// single-map path), captured once into a HIP graph and replayed while the frame sizes stay fixed.
+// single-map path, frame hand-offs included), captured once into a HIP graph and replayed while
+// the frame sizes stay fixed.
 //
 //   k_batch_alloc     workgroup ranges per map: depth maps get their pixel tiles then their cull
-//                     workgroups, LiDAR maps one workgroup per 256 points
+//                     workgroups, LiDAR maps one workgroup per kAllocRaysPerGroup rays; a map's
+//                     last workgroup also runs its allocation-side hand-off
 //   k_batch_rays      LiDAR maps: one workgroup per kRaysPerGroup rays (their recorded (ray, block)
 //                     pairs in parallel: traversal and accumulation)
-//   k_batch_update    the update tasks of every map (per-level queues), each wave taking a
-//                     contiguous range of the concatenated task space (mostly one map per wave)
-//   k_batch_finalize  one workgroup per map
+//   k_batch_update    the update tasks of every map (per-level queues), strided over the
+//                     concatenated task space; workgroup i also runs map i's update-side hand-off
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -36,6 +37,10 @@ struct BatchEntry {
 
 // The entry whose workgroup range holds workgroup b (all lanes of the wave active; n <= 64):
 // lane i tests entry i, so the ranges are read in one round trip.
+__host__ __device__ inline int32_t entry_parity(const BatchEntry& e) {
+    return e.kind == MRH_FRAME_DEPTH ? e.df.parity : e.sp.parity;
+}
+
 __device__ inline int entry_of(const BatchEntry* __restrict__ e, int n, uint32_t b, bool rays) {
     const int lane = lane_id();
     bool hit = false;
@@ -55,6 +60,7 @@ __global__ __launch_bounds__(256) void k_batch_alloc(const DevMap* __restrict__ 
     const BatchEntry& e = ents[i];
     const DevMap& m = maps[i];
     const uint32_t local = blockIdx.x - e.alloc_begin;
+    if (local == e.alloc_end - e.alloc_begin - 1) alloc_duties(m, e.kind == MRH_FRAME_DEPTH ? e.df.parity : e.sp.parity);
     if (e.kind == MRH_FRAME_DEPTH) {
         if (local < e.tiles) depth_alloc_tile(m, e.df, local, e.tiles_x);
         else depth_cull(m, e.df, local - e.tiles, e.alloc_end - e.alloc_begin - e.tiles);
@@ -78,9 +84,11 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
     __shared__ TaskCounts cnt[kMaxBatch];
     __shared__ uint32_t pre[kMaxBatch + 1];
     __shared__ unsigned long long wst[kMaxBatch][5];
+    if ((int)blockIdx.x < n && ents[blockIdx.x].kind != MRH_FRAME_NONE)
+        update_duties(maps[blockIdx.x], entry_parity(ents[blockIdx.x]));
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         if (ents[i].kind == MRH_FRAME_NONE) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
-        else cnt[i] = frame_task_counts(maps[i], ents[i].kind == MRH_FRAME_DEPTH);
+        else cnt[i] = frame_task_counts(maps[i], ents[i].kind == MRH_FRAME_DEPTH, entry_parity(ents[i]));
     }
     for (int k = threadIdx.x; k < 5 * n; k += blockDim.x) wst[k / 5][k % 5] = 0ull;
     __syncthreads();
@@ -121,7 +129,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
         }
         const uint32_t local = t - pre[lo];
         if (ents[lo].kind == MRH_FRAME_DEPTH) depth_update_task<ST>(maps[lo], ents[lo].df, local, cnt[lo], ts);
-        else points_update_task<ST>(maps[lo], local, cnt[lo], ts);
+        else points_update_task<ST>(maps[lo], local, cnt[lo], ts, ents[lo].sp.parity);
     }
     if (cur >= 0) flush(cur);
     __syncthreads();
@@ -130,9 +138,6 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
         if (wst[k / 5][k % 5]) stat_add(maps[k / 5], sid[k % 5], wst[k / 5][k % 5]);
 }
 
-__global__ void k_batch_finalize(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents, int n) {
-    if ((int)blockIdx.x < n && ents[blockIdx.x].kind != MRH_FRAME_NONE) finalize_map(maps[blockIdx.x]);
-}
 
 }  // namespace mrh
 
@@ -178,13 +183,13 @@ static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32
             default: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_F32>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
         }
     }
-    const dim3 ug((unsigned)b->update_wgs);
+    // at least one workgroup per map: workgroup i carries map i's update-side hand-off
+    const dim3 ug((unsigned)(b->update_wgs > n ? b->update_wgs : n));
     switch (b->storage) {
         case MRH_STORE_F16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
         case MRH_STORE_BF16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_BF16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
         default: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F32>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n);
     }
-    hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)n), dim3(1024), 0, s, b->d_maps, b->d_ents, n);
 }
 
 }  // namespace mrh
@@ -304,6 +309,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
                 return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad depth frame");
             if (attach_tiles(b->maps[i], f.width, f.height, e.df) != MRH_OK)
                 return batch_err(b, MRH_ERR_OOM, "batch: tile buffer");
+            e.df.parity = (int32_t)(b->maps[i]->frames & 1u);
             e.tiles_x = (uint32_t)(f.width + 15) / 16;
             e.tiles = e.tiles_x * (uint32_t)((f.height + 15) / 16);
             alloc_wgs += e.tiles + (uint32_t)b->cull_wgs;
@@ -312,7 +318,9 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
                 return batch_err(b, MRH_ERR_INVALID_ARG, "batch: bad point frame");
             e.sp.xyz = f.data_dev;
             e.sp.n = f.n;
-            alloc_wgs += (uint32_t)((f.n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup);
+            e.sp.parity = (int32_t)(b->maps[i]->frames & 1u);
+            // at least one workgroup: it carries the map's allocation-side hand-off
+            alloc_wgs += f.n > 0 ? (uint32_t)((f.n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup) : 1u;
             ray_wgs += (uint32_t)((f.n + kRaysPerGroup - 1) / kRaysPerGroup);
         }
         e.alloc_end = alloc_wgs;
@@ -325,9 +333,16 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         hipEventRecord(b->copied[k], b->stream) != hipSuccess)
         return batch_err(b, MRH_ERR_HIP, "batch: descriptor upload");
 
+    // every map with a frame advances one frame (its parity flips) once the step is enqueued
+    auto advance = [&] {
+        for (int i = 0; i < n; ++i)
+            if (frames[i].kind != MRH_FRAME_NONE) b->maps[i]->frames += 1;
+    };
     if (!b->use_graph) {
         launch(m0, K_BATCH_GRAPH, [&] { enqueue_step(b, b->stream, alloc_wgs, ray_wgs); });
-        return check_hip(m0, hipGetLastError(), "batch_integrate");
+        const mrh_status st = check_hip(m0, hipGetLastError(), "batch_integrate");
+        if (st == MRH_OK) advance();
+        return st;
     }
     if (!b->exec || b->graph_sig != sig) {
         drop_graph(b);
@@ -346,7 +361,9 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         b->graph_sig = sig;
     }
     launch(m0, K_BATCH_GRAPH, [&] { (void)hipGraphLaunch(b->exec, b->stream); });
-    return check_hip(m0, hipGetLastError(), "batch_integrate");
+    const mrh_status st = check_hip(m0, hipGetLastError(), "batch_integrate");
+    if (st == MRH_OK) advance();
+    return st;
 }
 
 mrh_status mrh_batch_autotune(mrh_batch* b, const mrh_frame* frames, int32_t reps, int32_t best[3]) {

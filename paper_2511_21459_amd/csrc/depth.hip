@@ -1,7 +1,8 @@
 // RGB-D fusion of one map (Sec. 3.1 "Cameras", Eq. 2; Eq. 3, Eq. 5; Sec. 3.2.1).
 //
-// One frame is three launches on the map's stream: k_alloc_depth (pixel tiles, then cull
-// workgroups), k_integrate_depth (update tasks over the per-level queues), k_finalize.
+// One frame is two launches on the map's stream: k_alloc_depth (pixel tiles, then cull
+// workgroups; the last one also runs the allocation-side frame hand-off) and k_integrate_depth
+// (update tasks over the per-level queues; workgroup 0 also runs the update-side hand-off).
 #include <algorithm>
 #include <cmath>
 
@@ -9,7 +10,6 @@
 
 namespace mrh {
 
-void launch_finalize(mrh_map* m);
 
 // Frame sizes the kernels accept: pixel indices are 32-bit and pixel coordinates exact in FP32.
 bool depth_size_ok(int32_t width, int32_t height) {
@@ -82,6 +82,7 @@ bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, 
 // Workgroups [0, tiles): pixel tiles; [tiles, gridDim): cull.
 __global__ __launch_bounds__(256) void k_alloc_depth(const DevMap* __restrict__ pm, DepthFrame f, uint32_t tiles_x, uint32_t tiles) {
     const DevMap& m = *pm;
+    if (blockIdx.x == gridDim.x - 1) alloc_duties(m, f.parity);
     if (blockIdx.x >= tiles) depth_cull(m, f, blockIdx.x - tiles, gridDim.x - tiles);
     else depth_alloc_tile(m, f, blockIdx.x, tiles_x);
 }
@@ -91,7 +92,8 @@ __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restric
     const DevMap& m = *pm;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const TaskCounts n = frame_task_counts(m, true);
+    if (blockIdx.x == 0) update_duties(m, f.parity);
+    const TaskCounts n = frame_task_counts(m, true, f.parity);
     const uint32_t ntask = update_task_count(n);
     TaskStats ts;
     for (uint32_t t = wave; t < ntask; t += nwaves) depth_update_task<ST>(m, f, t, n, ts);
@@ -110,6 +112,8 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
         return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose or intrinsics, or zero focal length");
     const mrh_status ts = attach_tiles(map, width, height, f);
     if (ts != MRH_OK) return ts;
+    f.parity = (int32_t)(map->frames & 1u);
+    map->frames += 1;
     const uint32_t tiles_x = (uint32_t)(width + 15) / 16, tiles = tiles_x * (uint32_t)((height + 15) / 16);
     const uint32_t cull_groups = 128;
     launch(map, K_ALLOC_DEPTH, [&] {
@@ -124,7 +128,6 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
             default: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd, f);
         }
     });
-    launch_finalize(map);
     return check_hip(map, hipGetLastError(), "integrate_depth");
 }
 

@@ -58,24 +58,19 @@ __global__ void k_reset(const DevMap* __restrict__ pm, uint32_t n_hash) {
         DevCounters* c = m.ctr;
         c->n_blocks = 0;
         c->pops0 = 0;
-        c->nb_start = 0;
         c->error_flags.v = 0;
+        for (int p = 0; p < 2; ++p) {
+            c->n_prev[p] = 0;
+            c->pending0[p].v = 0;
+            for (int n = 0; n < 4; ++n) c->vis_n[p][n].v = 0;
+        }
         for (int n = 0; n < 4; ++n) {
             c->top[n].v = n < m.levels ? m.heap_cap[n] : 0;
             c->pending[n].v = 0;
-            c->vis_n[n].v = 0;
         }
-        c->n_prev = 0;
-        for (int s = 0; s < 16; ++s) {
-            c->last[s] = c->total[s] = 0;
-            for (int k = 0; k < kStripes; ++k) c->frame[k][s] = 0;
-        }
-        c->frames = 0;
     }
+    if (tid < 16 * kStripes) m.ctr->frame[tid >> 4][tid & 15] = 0;
 }
-
-// End of a frame (one workgroup).
-__global__ void k_finalize(const DevMap* __restrict__ pm) { finalize_map(*pm); }
 
 // Copy blocks out: keys, levels and (optionally) voxels converted from Morton to x-fastest order.
 template <int ST>
@@ -137,6 +132,8 @@ static void free_all(mrh_map* m) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);
+    for (int p = 0; p < 2; ++p)
+        if (d.pend0[p]) (void)hipFree(d.pend0[p]);
     if (d.rkeys) (void)hipFree(d.rkeys);
     if (d.rcount) (void)hipFree(d.rcount);
     if (m->tile_max) (void)hipFree(m->tile_max);
@@ -217,7 +214,9 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
         d.heap_cap[n] = (int32_t)cap;
         const size_t nv = (size_t)cap * (size_t)(side_of(n) * side_of(n) * side_of(n));
         alloc((void**)&d.stack[n], (size_t)cap * 4, "free stack");
-        alloc((void**)&d.pend[n], (size_t)cap * 4, "pending frees");
+        if (n >= 1) alloc((void**)&d.pend[n], (size_t)cap * 4, "pending frees");
+        if (n == 0)
+            for (int p = 0; p < 2; ++p) alloc((void**)&d.pend0[p], (size_t)cap * 4, "pending frees");
         const size_t pb = (size_t)plane_bytes(c.storage);
         alloc((void**)&d.D[n], nv * pb, "TSDF heap");
         alloc((void**)&d.W[n], nv * pb, "weight heap");
@@ -259,6 +258,8 @@ void mrh_map_destroy(mrh_map* map) {
 
 mrh_status mrh_map_reset(mrh_map* map) {
     if (!map) return MRH_ERR_INVALID_ARG;
+    map->frames = map->frames_at_sync = 0;
+    for (int s = 0; s < 16; ++s) map->stats_at_sync[s] = 0;
     const uint32_t n_hash = map->dm.hmask + 1;
     launch(map, K_RESET, [&] { hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, map->stream, map->dmd, n_hash); });
     return check_hip(map, hipGetLastError(), "reset");
@@ -286,8 +287,17 @@ mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals) {
     if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "sync");
     if (st != MRH_OK) return st;
     const uint32_t nb = h.n_blocks < map->dm.max_blocks ? h.n_blocks : map->dm.max_blocks;
-    if (last) fill_stats(h.last, h.frames ? 1 : 0, nb, h.error_flags.v, last);
-    if (totals) fill_stats(h.total, h.frames, nb, h.error_flags.v, totals);
+    unsigned long long tot[16], since[16];
+    for (int s = 0; s < 16; ++s) {
+        tot[s] = 0;
+        for (int k = 0; k < kStripes; ++k) tot[s] += h.frame[k][s];
+        since[s] = tot[s] - map->stats_at_sync[s];
+        map->stats_at_sync[s] = tot[s];
+    }
+    const uint32_t frames_since = map->frames - map->frames_at_sync;
+    map->frames_at_sync = map->frames;
+    if (last) fill_stats(since, frames_since, nb, h.error_flags.v, last);
+    if (totals) fill_stats(tot, map->frames, nb, h.error_flags.v, totals);
     if (h.error_flags.v) {
         const uint32_t zero = 0;
         st = check_hip(map, hipMemcpyAsync(&map->ctr->error_flags.v, &zero, 4, hipMemcpyHostToDevice, map->stream),
@@ -393,8 +403,4 @@ hipEvent_t take_event(mrh_map* m) {
     return e;
 }
 
-// launched by the integrate entry points after each frame
-void launch_finalize(mrh_map* m) {
-    launch(m, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(512), 0, m->stream, m->dmd); });
-}
 }  // namespace mrh

@@ -16,6 +16,7 @@
 namespace mrh {
 
 struct DepthFrame {
+    int32_t parity;  // the frame's parity (selects the double-buffered per-frame counts)
     Pose P;
     double fx, fy, cx, cy, ifx, ify;
     int32_t width, height;
@@ -167,7 +168,7 @@ __device__ inline bool block_visible(const DevMap& m, const DepthFrame& f, int64
 // Conservative frustum cull of the blocks that existed when the frame started, one thread per
 // block: workgroup g of ng covers ids g * 256 + threadIdx, stepping by ng * 256.
 __device__ inline void depth_cull(const DevMap& m, const DepthFrame& f, uint32_t g, uint32_t ng) {
-    const uint32_t n = m.ctr->n_prev;
+    const uint32_t n = m.ctr->n_prev[f.parity];
     for (uint32_t base = g * blockDim.x; base < n; base += ng * blockDim.x) {
         const uint32_t id = base + threadIdx.x;
         int level = -1;
@@ -182,7 +183,7 @@ __device__ inline void depth_cull(const DevMap& m, const DepthFrame& f, uint32_t
                 if ((info & kNewBit) || block_visible(m, f, bx, by, bz)) level = (int)((info >> kLevelShift) & 3u);
             }
         }
-        queue_block_wg(m, level, id, info, key);
+        queue_block_wg(m, level, id, info, key, f.parity);
     }
 }
 
@@ -364,7 +365,7 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         dcnt += var_count(m, W[q]) - cb;
     }
     ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt,
-                                                        bvs, bvc);
+                                                        bvs, bvc, f.parity);
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
@@ -401,7 +402,8 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt, bvs, bvc);
+    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt, bvs, bvc,
+                                                          f.parity);
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.

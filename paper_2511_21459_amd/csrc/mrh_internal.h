@@ -46,20 +46,23 @@ struct alignas(128) Line {
     T v;
 };
 
+// A frame runs as an allocation launch and an update launch (LiDAR: allocation, rays, update);
+// there is no separate end-of-frame launch.  The hand-offs between frames cross kernel boundaries
+// only: per-frame counts are double-buffered by frame parity p (the host alternates it), each
+// launch reads the buffer of its own frame and clears or fills the other one; slots freed at
+// level n >= 1 are returned to their stacks by the next allocation launch (which never pops those
+// levels), level-0 slots by one workgroup of the next update launch (which never pops level 0).
 struct alignas(128) DevCounters {
     // allocation word: one 64-bit atomic adds k to both halves for k new blocks
     uint32_t n_blocks;   // block ids handed out (keys inserted), low half
     uint32_t pops0;      // level-0 slots taken by this frame's new blocks, high half
-    uint32_t n_prev;     // min(n_blocks, max_blocks) when the frame started: ids >= n_prev are new
-    uint32_t nb_start;   // n_blocks when the frame started
+    uint32_t n_prev[2];  // per parity: min(n_blocks, max_blocks) when the frame started (ids >= are new)
     Line<uint32_t> error_flags;
     Line<int32_t> top[4];
-    Line<uint32_t> pending[4];
-    Line<uint32_t> vis_n[4];   // blocks queued for the update this frame, per level
-    unsigned long long frame[kStripes][16];
-    unsigned long long last[16];
-    unsigned long long total[16];
-    unsigned long long frames;
+    Line<uint32_t> pending[4];   // slots freed at level n >= 1 this frame (entry 0 unused)
+    Line<uint32_t> pending0[2];  // slots freed at level 0, per parity
+    Line<uint32_t> vis_n[2][4];  // per parity: blocks queued for the update, per level
+    unsigned long long frame[kStripes][16];  // statistics since the reset, in stripes
 };
 
 // Everything a kernel needs to find the map; passed by value as a kernel argument.
@@ -76,7 +79,8 @@ struct DevMap {
     int32_t levels;
     DevCounters* ctr;
     uint32_t* stack[4];
-    uint32_t* pend[4];
+    uint32_t* pend[4];      // level n >= 1 frees (entry 0 unused)
+    uint32_t* pend0[2];     // level-0 frees, per parity
     int32_t heap_cap[4];
     void* D[4];   // per level, plane of the storage format (see mrh_store.h)
     void* W[4];
@@ -375,6 +379,9 @@ struct mrh_map {
     int32_t partials_cap = 0;
     bool lidar_ready = false;    // accumulators allocated
     int64_t rcap_n = 0;          // rays the per-ray block-key buffers hold
+    uint32_t frames = 0;         // frames enqueued since the last reset (parity of the next = frames & 1)
+    uint32_t frames_at_sync = 0;
+    unsigned long long stats_at_sync[16] = {0};
     uint32_t dm_version = 0;     // bumped whenever the device copy of dm is rewritten
     float* tile_max = nullptr;   // per 16 x 16 pixel tile of the current depth frame: largest valid depth
     size_t tile_cap = 0;

@@ -25,6 +25,7 @@ constexpr double kS1Scale = 16777216.0;         // 2^24 per metre
 constexpr double kS2Scale = 281474976710656.0;  // 2^48 per square metre
 
 struct ScanParams {
+    int32_t parity;  // the frame's parity (selects the double-buffered per-frame counts)
     Pose P;
     const float* xyz;  // device points, sensor frame, [n][3]
     int64_t n;
@@ -233,7 +234,7 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
     const int level = (int)((info >> kLevelShift) & 3u);
     // first touch of the block in this scan: queue it for the update (active lanes only)
     const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
-    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key);
+    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key, sp.parity);
     if (info & kNoBlockBit) return;
     const bool fresh = (info & kNewBit) != 0;
     const int side = 8 >> level;
@@ -346,7 +347,7 @@ __device__ inline void take_accumulators(const DevMap& m, int level, size_t at, 
 }
 
 template <int ST>
-__device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as) {
+__device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as, int par) {
     const int lane = lane_id();
     const uint32_t id = e.x, info = e.y;
     const double bvs = m.bvsum[id];
@@ -418,12 +419,12 @@ __device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as)
         }
     }
     as.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
-                                                        bvs, bvc);
+                                                        bvs, bvc, par);
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
-__device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& as) {
+__device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& as, int par) {
     const int lane = lane_id();
     const uint32_t id = e.x, info = e.y;
     const double bvs = m.bvsum[id];
@@ -449,7 +450,7 @@ __device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& a
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc);
+    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc, par);
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
@@ -491,11 +492,11 @@ __device__ inline void apply_packed(const DevMap& m, const uint4* list, uint32_t
 
 // One update task t of a scan whose queues hold n0..n3 blocks per level.
 template <int ST>
-__device__ inline void points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, TaskStats& as) {
+__device__ inline void points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, TaskStats& as, int par) {
     const uint32_t* n = c.n;  // LiDAR frames queue their new blocks like the others (n_new = 0)
     const uint32_t g2 = (n[2] + 7) / 8;
-    if (t < n[0]) apply_fine<ST>(m, m.vis[0][t], as);
-    else if (t < n[0] + n[1]) apply_level1<ST>(m, m.vis[1][t - n[0]], as);
+    if (t < n[0]) apply_fine<ST>(m, m.vis[0][t], as, par);
+    else if (t < n[0] + n[1]) apply_level1<ST>(m, m.vis[1][t - n[0]], as, par);
     else if (t < n[0] + n[1] + g2) apply_packed<ST>(m, m.vis[2], n[2], t - n[0] - n[1], 2, as);
     else apply_packed<ST>(m, m.vis[3], n[3], t - n[0] - n[1] - g2, 3, as);
 }

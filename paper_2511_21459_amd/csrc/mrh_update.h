@@ -43,11 +43,17 @@ __device__ inline int64_t pop_slot(const DevMap& m, int level) {
     return (int64_t)m.stack[level][top - 1];
 }
 
-// Slots freed by a merge wait in a pending list until the frame's end (a stack that is popped
-// in the same launch is never pushed).
-__device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
-    const uint32_t p = atomicAdd(&m.ctr->pending[level].v, 1u);
-    m.pend[level][p] = slot;
+// Slots freed by a merge wait in a pending list until a later launch that does not pop their
+// level returns them (a stack that is popped in the same launch is never pushed).  par is the
+// frame's parity.
+__device__ inline void push_pending(const DevMap& m, int level, uint32_t slot, int par) {
+    if (level == 0) {
+        const uint32_t p = atomicAdd(&m.ctr->pending0[par].v, 1u);
+        m.pend0[par][p] = slot;
+    } else {
+        const uint32_t p = atomicAdd(&m.ctr->pending[level].v, 1u);
+        m.pend[level][p] = slot;
+    }
 }
 
 // End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
@@ -55,7 +61,8 @@ __device__ inline void push_pending(const DevMap& m, int level, uint32_t slot) {
 // written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
 template <int ST>
 __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
-                                   bool have, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc) {
+                                   bool have, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc,
+                                   int par) {
     const int lane = lane_id();
     const uint32_t slot = info & kSlotMask;
     const size_t base = (size_t)slot * 512 + (size_t)lane * 8;
@@ -99,7 +106,7 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
         m.bvsum[id] = csum;
         m.bvcnt[id] = (uint32_t)ccnt;
         m.binfo[id] = (uint32_t)cslot | (1u << kLevelShift);
-        push_pending(m, 0, slot);
+        push_pending(m, 0, slot, par);
     }
     return 1;
 }
@@ -108,7 +115,8 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
 // 8 consecutive lanes.  Returns 1 when the block merged.
 template <int ST>
 __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
-                                     float S2, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc) {
+                                     float S2, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc,
+                                     int par) {
     const int lane = lane_id();
     const int side = 8 >> level, nv = side * side * side;
     const uint32_t slot = info & kSlotMask;
@@ -150,7 +158,7 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
         m.bvsum[id] = csum;
         m.bvcnt[id] = (uint32_t)ccnt;
         m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
-        push_pending(m, level, slot);
+        push_pending(m, level, slot, par);
     }
     return 1;
 }
@@ -161,6 +169,7 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
 template <int ST>
 __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uint32_t info, int level, int seg, float D,
                                     uint32_t W, float S2, bool dirty, int nupd, double dsum, int dcnt) {
+    const int par = 0;  // levels >= 2 free into the single list of their level
     const int lane = lane_id();
     for (int o = 1; o < seg; o <<= 1) {
         dsum += __shfl_xor(dsum, o);
@@ -204,7 +213,7 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
         m.bvsum[id] = var_term(m, Wc, Sc);
         m.bvcnt[id] = (uint32_t)var_count(m, Wc);
         m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
-        push_pending(m, level, slot);
+        push_pending(m, level, slot, par);
         return 1;
     }
     return 0;
@@ -229,10 +238,10 @@ __device__ inline uint32_t update_task_count(const TaskCounts& c) {
 
 // Counts of the current frame; with_new: the blocks allocated this frame are update tasks of their
 // own (RGB-D); otherwise they are queued like every other block (LiDAR first touch).
-__device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new) {
+__device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new, int par) {
     TaskCounts c;
-    for (int l = 0; l < 4; ++l) c.n[l] = m.ctr->vis_n[l].v;
-    c.new_base = m.ctr->n_prev;
+    for (int l = 0; l < 4; ++l) c.n[l] = m.ctr->vis_n[par][l].v;
+    c.new_base = m.ctr->n_prev[par];
     const uint32_t nb = m.ctr->n_blocks < m.max_blocks ? m.ctr->n_blocks : m.max_blocks;
     c.n_new = with_new && nb > c.new_base ? nb - c.new_base : 0u;
     return c;
@@ -252,79 +261,81 @@ __device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
 
 // Queue block `id` for this frame's update on the list of its level (lanes with level < 0 queue
 // nothing).  Called by every lane of the wave; one atomic per level per wave.
-__device__ inline void queue_block(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key) {
+__device__ inline void queue_block(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key,
+                                   int par) {
     const int lane = lane_id();
     for (int lv = 0; lv < 4; ++lv) {
         const unsigned long long msk = __ballot(level == lv);
         if (!msk) continue;
         const int f0 = __ffsll((long long)msk) - 1;
         uint32_t vb = 0;
-        if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[lv].v, (uint32_t)__popcll(msk));
+        if (lane == f0) vb = atomicAdd(&m.ctr->vis_n[par][lv].v, (uint32_t)__popcll(msk));
         vb = (uint32_t)__shfl((int)vb, f0);
         if (level == lv) m.vis[lv][vb + rank_in_mask(msk)] = make_entry(id, info, key);
     }
 }
 
-// End of a frame for one map, by one workgroup of at least kStripes * 16 threads: take this frame's
-// level-0 pops off the stack, return the slots freed by merges to their levels' stacks, publish the
-// frame's statistics (the new-block count is the growth of n_blocks), empty the update queues,
-// note the block count.  Every counter and statistic is read in one round of independent loads,
-// shared through LDS, and written once.
-__device__ inline void finalize_map(const DevMap& m) {
+// Frame hand-off, part 1: run by one workgroup of a frame's allocation launch (frame parity par).
+// Clears the other parity's update-queue counts (the previous frame's, used by the next one) and
+// returns the slots freed at levels >= 1 by the previous frame's merges to their stacks; nothing
+// else in the allocation launch touches those counts or stacks.
+__device__ inline void alloc_duties(const DevMap& m, int par) {
     DevCounters* c = m.ctr;
     __shared__ int32_t s_top[4];
     __shared__ uint32_t s_pend[4];
-    __shared__ unsigned long long s_new;
-    __shared__ unsigned long long s_part[kStripes][16];
-    const int tid = threadIdx.x;
-    if (tid < kStripes * 16) {
-        const int k = tid >> 4, st = tid & 15;
-        s_part[k][st] = c->frame[k][st];
-        c->frame[k][st] = 0;
-    }
-    if (tid == 0) {
-        for (int n = 0; n < 4; ++n) {
-            s_top[n] = c->top[n].v;
-            s_pend[n] = n < m.levels ? c->pending[n].v : 0u;
-        }
-        const uint32_t avail = s_top[0] > 0 ? (uint32_t)s_top[0] : 0u;
-        const uint32_t pops = c->pops0;
-        s_top[0] -= (int32_t)(pops < avail ? pops : avail);
-        s_new = (unsigned long long)(c->n_blocks - c->nb_start);
+    if (threadIdx.x < 4) {
+        const int n = threadIdx.x;
+        c->vis_n[par ^ 1][n].v = 0;
+        s_top[n] = n >= 1 && n < m.levels ? c->top[n].v : 0;
+        s_pend[n] = n >= 1 && n < m.levels ? c->pending[n].v : 0u;
     }
     __syncthreads();
-    for (int n = 0; n < m.levels; ++n)
-        for (uint32_t i = tid; i < s_pend[n]; i += blockDim.x) m.stack[n][s_top[n] + i] = m.pend[n][i];
-    if (tid < S_COUNT) {
-        unsigned long long v = tid == S_NEW ? s_new : 0ull;
-        for (int k = 0; k < kStripes; ++k) v += s_part[k][tid];
-        c->last[tid] = v;
-        c->total[tid] += v;
+    for (int n = 1; n < m.levels; ++n)
+        for (uint32_t i = threadIdx.x; i < s_pend[n]; i += blockDim.x) m.stack[n][s_top[n] + i] = m.pend[n][i];
+    if (threadIdx.x >= 1 && threadIdx.x < 4 && (int)threadIdx.x < m.levels && s_pend[threadIdx.x]) {
+        c->top[threadIdx.x].v = s_top[threadIdx.x] + (int32_t)s_pend[threadIdx.x];
+        c->pending[threadIdx.x].v = 0;
     }
-    if (tid == 0) {
-        for (int n = 0; n < 4; ++n) {
-            c->top[n].v = s_top[n] + (int32_t)s_pend[n];
-            c->pending[n].v = 0;
-            c->vis_n[n].v = 0;
-        }
+}
+
+// Frame hand-off, part 2: run by one workgroup of a frame's update launch (frame parity par).
+// Takes the frame's level-0 pops off the stack, returns the level-0 slots freed by the previous
+// frame's merges, and records where the next frame's new block ids start.  Nothing else in the
+// update launch pops level 0 or reads the other parity.
+__device__ inline void update_duties(const DevMap& m, int par) {
+    DevCounters* c = m.ctr;
+    __shared__ int32_t s_t0;
+    __shared__ uint32_t s_p;
+    if (threadIdx.x == 0) {
+        const int32_t t0 = c->top[0].v;
+        const uint32_t avail = t0 > 0 ? (uint32_t)t0 : 0u;
+        const uint32_t pops = c->pops0;
+        s_t0 = t0 - (int32_t)(pops < avail ? pops : avail);
+        s_p = c->pending0[par ^ 1].v;
         c->pops0 = 0;
-        c->frames += 1;
-        c->n_prev = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
-        c->nb_start = c->n_blocks;
+        c->n_prev[par ^ 1] = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < s_p; i += blockDim.x) m.stack[0][s_t0 + i] = m.pend0[par ^ 1][i];
+    if (threadIdx.x == 0) {
+        c->top[0].v = s_t0 + (int32_t)s_p;
+        c->pending0[par ^ 1].v = 0;
     }
 }
 
 // Queue block `id` on the update list of `level` (level < 0 queues nothing).  Called by every
 // thread of the workgroup (a barrier inside): positions come from LDS counters and one global
 // atomic per level per workgroup, since same-address device atomics serialise chip-wide.
-__device__ inline void queue_block_wg(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key) {
+__device__ inline void queue_block_wg(const DevMap& m, int level, uint32_t id, uint32_t info, unsigned long long key,
+                                      int par) {
     __shared__ uint32_t lcnt[4], lbase[4];
     if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
     __syncthreads();
     uint32_t local = 0;
     if (level >= 0) local = atomicAdd(&lcnt[level], 1u);
     __syncthreads();
-    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[threadIdx.x].v, lcnt[threadIdx.x]);
+    if (threadIdx.x < 4 && lcnt[threadIdx.x])
+        lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[par][threadIdx.x].v, lcnt[threadIdx.x]);
     __syncthreads();
     if (level >= 0) m.vis[level][lbase[level] + local] = make_entry(id, info, key);
 }
@@ -358,6 +369,7 @@ __device__ inline void register_block(const DevMap& m, unsigned long long key, u
 
 // k new blocks: one atomic on the allocation word; returns the old word (ids and pops start there).
 __device__ inline unsigned long long take_new_blocks(const DevMap& m, uint32_t k) {
+    stat_add(m, S_NEW, (unsigned long long)k);
     return atomicAdd(reinterpret_cast<unsigned long long*>(&m.ctr->n_blocks),
                      (unsigned long long)k | ((unsigned long long)k << 32));
 }

@@ -1,16 +1,19 @@
 // LiDAR fusion of one map (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3, Eq. 5; Sec. 3.2.1).
 //
-// One scan is four launches on the map's stream: k_alloc_points, k_rays, k_apply_points (update
-// tasks over the per-level queues of touched blocks), k_finalize.
+// One scan is three launches on the map's stream: k_alloc_points (its last workgroup also runs the
+// allocation-side frame hand-off), k_rays and k_apply_points (update tasks over the per-level queues
+// of touched blocks; workgroup 0 also runs the update-side hand-off).
 #include <cmath>
 
 #include "mrh_points.h"
 
 namespace mrh {
 
-void launch_finalize(mrh_map* m);
 
-__global__ __launch_bounds__(256) void k_alloc_points(const DevMap* __restrict__ pm, ScanParams sp) { points_alloc_chunk(*pm, sp, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_alloc_points(const DevMap* __restrict__ pm, ScanParams sp) {
+    if (blockIdx.x == gridDim.x - 1) alloc_duties(*pm, sp.parity);
+    points_alloc_chunk(*pm, sp, blockIdx.x);
+}
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_rays(const DevMap* __restrict__ pm, ScanParams sp) {
@@ -19,14 +22,15 @@ __global__ __launch_bounds__(256) void k_rays(const DevMap* __restrict__ pm, Sca
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__ pm) {
+__global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__ pm, int par) {
     const DevMap& m = *pm;
+    if (blockIdx.x == 0) update_duties(m, par);
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const TaskCounts n = frame_task_counts(m, false);
+    const TaskCounts n = frame_task_counts(m, false, par);
     const uint32_t ntask = update_task_count(n);
     TaskStats as;
-    for (uint32_t t = wave; t < ntask; t += nwaves) points_update_task<ST>(m, t, n, as);
+    for (uint32_t t = wave; t < ntask; t += nwaves) points_update_task<ST>(m, t, n, as, par);
     flush_task_stats(m, as);
 }
 
@@ -88,10 +92,14 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
     sp.n = n;
     mrh_status st = ensure_lidar(map, n);
     if (st != MRH_OK) return st;
+    sp.parity = (int32_t)(map->frames & 1u);
+    map->frames += 1;
+    const int par = sp.parity;
+    // the allocation and update launches always run (they carry the frame hand-off)
+    const unsigned agrid = n > 0 ? (unsigned)((n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup) : 1u;
+    launch(map, K_ALLOC_POINTS,
+           [&] { hipLaunchKernelGGL(k_alloc_points, dim3(agrid), dim3(256), 0, map->stream, map->dmd, sp); });
     if (n > 0) {
-        const unsigned agrid = (unsigned)((n + kAllocRaysPerGroup - 1) / kAllocRaysPerGroup);
-        launch(map, K_ALLOC_POINTS,
-               [&] { hipLaunchKernelGGL(k_alloc_points, dim3(agrid), dim3(256), 0, map->stream, map->dmd, sp); });
         const unsigned rgrid = (unsigned)((n + kRaysPerGroup - 1) / kRaysPerGroup);
         launch(map, K_RAYS, [&] {
             switch (map->cfg.storage) {
@@ -100,16 +108,15 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
                 default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp);
             }
         });
-        launch(map, K_APPLY_POINTS, [&] {
-            const dim3 g(1024), b(256);
-            switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F16>, g, b, 0, map->stream, map->dmd); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_BF16>, g, b, 0, map->stream, map->dmd); break;
-                default: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd);
-            }
-        });
     }
-    launch_finalize(map);
+    launch(map, K_APPLY_POINTS, [&] {
+        const dim3 g(1024), b(256);
+        switch (map->cfg.storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F16>, g, b, 0, map->stream, map->dmd, par); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_apply_points<MRH_STORE_BF16>, g, b, 0, map->stream, map->dmd, par); break;
+            default: hipLaunchKernelGGL(k_apply_points<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd, par);
+        }
+    });
     return check_hip(map, hipGetLastError(), "integrate_points");
 }
 
