@@ -183,7 +183,7 @@ enum {
     MRH_KERNEL_RESET = 0,
     MRH_KERNEL_ALLOC_DEPTH = 1,     /* RGB-D allocation (back-projection, band walk, insert) */
     MRH_KERNEL_INTEGRATE_DEPTH = 2, /* RGB-D projective update, variance, merge */
-    MRH_KERNEL_FINALIZE = 3,        /* end of frame: freed slots, statistics */
+    MRH_KERNEL_FINALIZE = 3,        /* reserved: the frame hand-off runs inside the other launches; stays 0 */
     MRH_KERNEL_ALLOC_POINTS = 4,    /* LiDAR allocation */
     MRH_KERNEL_RAYS = 5,            /* LiDAR ray traversal and accumulation */
     MRH_KERNEL_APPLY_POINTS = 6,    /* LiDAR state update, variance, merge */
@@ -193,7 +193,7 @@ enum {
     MRH_KERNEL_BATCH_ALLOC = 10,    /* batched: allocation + cull of every map */
     MRH_KERNEL_BATCH_RAYS = 11,     /* batched: LiDAR traversal of every map */
     MRH_KERNEL_BATCH_UPDATE = 12,   /* batched: update tasks of every map */
-    MRH_KERNEL_BATCH_FINALIZE = 13, /* batched: end of frame of every map */
+    MRH_KERNEL_BATCH_FINALIZE = 13, /* reserved, as MRH_KERNEL_FINALIZE; stays 0 */
     MRH_KERNEL_BATCH_GRAPH = 14,    /* batched: one replay of the captured step */
     MRH_KERNEL_COUNT = 15
 };
