@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_alloc_depth(const DevMap* __restrict__ 
 template <int ST>
 __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restrict__ pm, DepthFrame f) {
     const DevMap& m = *pm;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     if (blockIdx.x == 0) update_duties(m, f.parity);
     const TaskCounts n = frame_task_counts(m, true, f.parity);

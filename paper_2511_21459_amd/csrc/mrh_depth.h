@@ -35,20 +35,50 @@ struct DepthFrame {
 bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, int32_t height, const double K[4],
                       const double T_ws[16], DepthFrame& f);
 
-// Observation for the voxel whose camera-frame centre is x (Eq. 2 with the gate at -tau and
-// truncation at +tau).  Returns false when the voxel is not updated.
-__device__ inline bool project_observe(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                       double x0, double x1, double x2, float& obs) {
-    if (!(x2 > 0.0)) return false;
+// Nearest pixel of the voxel centre x (camera frame) under the projection of Eq. 2: the FP64
+// evaluation u = fx (x0 (1 / x2)) + cx, pixel floor(u + 1/2), and likewise for v.  Returns the
+// row-major pixel index, or -1 when x is not in front of the camera or falls outside the image.
+__device__ inline int pixel_exact(const DepthFrame& f, double x0, double x1, double x2) {
+    if (!(x2 > 0.0)) return -1;
     const double iz = 1.0 / x2;
     const double uu = (f.fx * (x0 * iz)) + f.cx;
     const double vv = (f.fy * (x1 * iz)) + f.cy;
     const double fu = __builtin_floor(uu + 0.5), fv = __builtin_floor(vv + 0.5);
-    if (!(fu >= 0.0 && fu <= (double)(f.width - 1) && fv >= 0.0 && fv <= (double)(f.height - 1))) return false;
-    const double d = (double)depth[(int64_t)fv * f.width + (int64_t)fu];
+    if (!(fu >= 0.0 && fu <= (double)(f.width - 1) && fv >= 0.0 && fv <= (double)(f.height - 1))) return -1;
+    return (int)fv * f.width + (int)fu;
+}
+
+// The same decision from the FP32 evaluation, taken only when it lies farther from a pixel boundary
+// than its error can reach; returns -2 when it cannot decide.  Error budget of the FP32 u from FP64
+// x: the roundings of x0, x2, fx, cx, the product and the sum (2^-24 relative each) and the hardware
+// reciprocal (1 ulp) stay below 6e-7 (|u| + |cx|), under the margin 1e-6 (|u| + |cx| + 16).  `lam`
+// receives |x| / x2 in FP32 for the range form.
+__device__ inline int pixel_fast(const DepthFrame& f, double x0, double x1, double x2, float& lam) {
+    lam = 0.f;
+    if (!(x2 > 0.0)) return -1;
+    const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
+    if (!(xf2 > 1e-6f)) return -2;
+    const float izf = __builtin_amdgcn_rcpf(xf2);
+    lam = __builtin_amdgcn_sqrtf((xf0 * xf0 + xf1 * xf1) + xf2 * xf2) * izf;
+    const float uf = f.fxf * (xf0 * izf) + f.cxf;
+    const float vf = f.fyf * (xf1 * izf) + f.cyf;
+    const float su = uf + 0.5f, sv = vf + 0.5f;
+    const float fu = __builtin_floorf(su), fv = __builtin_floorf(sv);
+    const float du = __builtin_fminf(su - fu, fu + 1.0f - su), dv = __builtin_fminf(sv - fv, fv + 1.0f - sv);
+    const float eu = 1e-6f * (__builtin_fabsf(uf) + __builtin_fabsf(f.cxf) + 16.0f);
+    const float ev = 1e-6f * (__builtin_fabsf(vf) + __builtin_fabsf(f.cyf) + 16.0f);
+    if (!(du > eu && dv > ev)) return -2;
+    if (!(fu >= 0.0f && fu <= (float)(f.width - 1) && fv >= 0.0f && fv <= (float)(f.height - 1))) return -1;
+    return (int)fv * f.width + (int)fu;
+}
+
+// Observation of Eq. 2 (gate at -tau, truncation at +tau) for the voxel centre x from the depth d
+// of its pixel, in FP64: the canonical evaluation.  False when the voxel is not updated.
+__device__ inline bool observe_exact(const DevMap& m, double x0, double x1, double x2, double d, float& obs) {
     if (!(__builtin_isfinite(d) && d > 0.0 && d <= m.max_depth)) return false;
     double raw;
     if (m.form == MRH_FORM_RANGE) {
+        const double iz = 1.0 / x2;
         const double nx = __builtin_sqrt((x0 * x0 + x1 * x1) + x2 * x2);
         raw = nx * ((d * iz) - 1.0);
     } else {
@@ -59,30 +89,12 @@ __device__ inline bool project_observe(const DevMap& m, const DepthFrame& f, con
     return true;
 }
 
-// The same observation with the projection evaluated in FP32.  Returns 1 (update with obs), 0 (no
-// update) or 2 (undecided: the canonical FP64 expression above must decide).  Every discrete
-// decision (pixel index, the -tau gate) is taken from the FP32 value only when it lies farther from
-// its threshold than the FP32 evaluation error can reach, so the decisions always equal the
-// canonical ones.  Error budget of u = fx (x0 / x2) + cx from FP64 x: the roundings of x0, x2, fx,
-// cx, the product and the sum (2^-24 relative each) and the hardware reciprocal (1 ulp) stay below
-// 6e-7 (|u| + |cx|), under the margin 1e-6 (|u| + |cx| + 16).  The range-form value carries about
-// 8 ulps (squares, sums, square root, reciprocal), far inside the 1e-5 tau gate band.
-__device__ inline int observe_fast(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth, double x0,
-                                   double x1, double x2, float& obs) {
-    if (!(x2 > 0.0)) return 0;
-    const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
-    if (!(xf2 > 1e-6f)) return 2;
-    const float izf = __builtin_amdgcn_rcpf(xf2);
-    const float uf = f.fxf * (xf0 * izf) + f.cxf;
-    const float vf = f.fyf * (xf1 * izf) + f.cyf;
-    const float su = uf + 0.5f, sv = vf + 0.5f;
-    const float fu = __builtin_floorf(su), fv = __builtin_floorf(sv);
-    const float du = __builtin_fminf(su - fu, fu + 1.0f - su), dv = __builtin_fminf(sv - fv, fv + 1.0f - sv);
-    const float eu = 1e-6f * (__builtin_fabsf(uf) + __builtin_fabsf(f.cxf) + 16.0f);
-    const float ev = 1e-6f * (__builtin_fabsf(vf) + __builtin_fabsf(f.cyf) + 16.0f);
-    if (!(du > eu && dv > ev)) return 2;
-    if (!(fu >= 0.0f && fu <= (float)(f.width - 1) && fv >= 0.0f && fv <= (float)(f.height - 1))) return 0;
-    const float d = depth[(int)fv * f.width + (int)fu];
+// The same observation with the range form's scale |x| / x2 in FP32 (`lam` from pixel_fast).
+// Returns 1 (update with obs), 0 (no update) or 2 (undecided: observe_exact must decide).  The
+// validity test is the canonical one (max_depth_f is the largest float not above max_depth) and
+// the z-difference form is evaluated exactly; the range-form value carries about 8 ulps (squares,
+// sums, square root, reciprocal), so its -tau gate is taken only outside a 1e-5 tau band.
+__device__ inline int observe_fast(const DevMap& m, double x2, float lam, float d, float& obs) {
     if (!(__builtin_isfinite(d) && d > 0.0f && d <= m.max_depth_f)) return 0;
     const double ddiff = (double)d - x2;
     if (m.form != MRH_FORM_RANGE) {
@@ -90,8 +102,6 @@ __device__ inline int observe_fast(const DevMap& m, const DepthFrame& f, const f
         obs = (float)(ddiff < m.tau ? ddiff : m.tau);
         return 1;
     }
-    // range form: raw = ||x|| (d / x2 - 1) = (d - x2) ||x|| / x2
-    const float lam = __builtin_amdgcn_sqrtf((xf0 * xf0 + xf1 * xf1) + xf2 * xf2) * izf;
     const float raw = (float)ddiff * lam;
     if (__builtin_fabsf(raw + m.tau_f) <= 1e-5f * m.tau_f + 1e-6f * __builtin_fabsf(raw)) return 2;
     if (raw < -m.tau_f) return 0;
@@ -99,12 +109,20 @@ __device__ inline int observe_fast(const DevMap& m, const DepthFrame& f, const f
     return 1;
 }
 
-// One voxel: the FP32 evaluation, and the canonical one where that is undecided.
+// One voxel: pixel decision, depth lookup, observation.
 __device__ inline bool observe(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth, double x0,
                                double x1, double x2, float& obs) {
-    const int r = observe_fast(m, f, depth, x0, x1, x2, obs);
-    if (r == 2) return project_observe(m, f, depth, x0, x1, x2, obs);
-    return r == 1;
+    float lam;
+    int p = pixel_fast(f, x0, x1, x2, lam);
+    const bool exact = p == -2;
+    if (exact) p = pixel_exact(f, x0, x1, x2);
+    if (p < 0) return false;
+    const float d = depth[p];
+    if (!exact) {
+        const int r = observe_fast(m, x2, lam, d, obs);
+        if (r != 2) return r == 1;
+    }
+    return observe_exact(m, x0, x1, x2, (double)d, obs);
 }
 
 // Wave-uniform test (all lanes active): true when no voxel of block (bx, by, bz) can be updated by
@@ -285,8 +303,9 @@ __device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_
 // Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
 template <int ST>
 __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            const uint4 e, TaskStats& ts) {
+                                            const uint4 eq, TaskStats& ts) {
     const int lane = lane_id();
+    const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
     if (info & kNoBlockBit) return;
     int32_t bx, by, bz;
@@ -311,26 +330,55 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
             pz[s][r] = f.P.R[2][r] * dz;
         }
     }
-    float obs[8];
-    uint32_t upd = 0, slow = 0;
+    // pixels first (FP64 only where FP32 cannot decide), then all depth loads at once, then the
+    // observations; x recomputed by voxel_camera equals these sums bit for bit (same products, same
+    // order, no contraction)
+    int pix[8];
+    float lam[8];
+    uint32_t exact = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int a = q & 1, b = (q >> 1) & 1, c = (q >> 2) & 1;
         const double x0 = (px[a][0] + py[b][0]) + pz[c][0];
         const double x1 = (px[a][1] + py[b][1]) + pz[c][1];
         const double x2 = (px[a][2] + py[b][2]) + pz[c][2];
-        const int r = observe_fast(m, f, depth, x0, x1, x2, obs[q]);
+        pix[q] = pixel_fast(f, x0, x1, x2, lam[q]);
+        exact |= (pix[q] == -2 ? 1u : 0u) << q;
+    }
+    for (uint32_t amb = exact; amb;) {
+        const int q = __builtin_ctz(amb);
+        amb &= amb - 1;
+        double x0, x1, x2;
+        voxel_camera(m, f, bx, by, bz, 0, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2), x0, x1, x2);
+        const int p = pixel_exact(f, x0, x1, x2);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k == q) pix[k] = p;
+    }
+    float dq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dq[q] = pix[q] >= 0 ? depth[pix[q]] : -1.f;
+    float obs[8];
+    uint32_t upd = 0, slow = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        obs[q] = 0.f;
+        const double x2 = (px[q & 1][2] + py[(q >> 1) & 1][2]) + pz[q >> 2][2];
+        const int r = (exact >> q) & 1 ? (dq[q] > 0.f ? 2 : 0) : observe_fast(m, x2, lam[q], dq[q], obs[q]);
         upd |= (r == 1 ? 1u : 0u) << q;
         slow |= (r == 2 ? 1u : 0u) << q;
     }
-    // voxels the FP32 evaluation left undecided, one canonical evaluation per pass
+    // voxels the FP32 evaluation left undecided: the canonical evaluation from the same depth sample
     while (slow) {
         const int q = __builtin_ctz(slow);
         slow &= slow - 1;
         double x0, x1, x2;
         voxel_camera(m, f, bx, by, bz, 0, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2), x0, x1, x2);
-        float o = 0.f;
-        if (project_observe(m, f, depth, x0, x1, x2, o)) {
+        float o = 0.f, dsel = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k == q) dsel = dq[k];
+        if (observe_exact(m, x0, x1, x2, (double)dsel, o)) {
             upd |= 1u << q;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
@@ -371,8 +419,9 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
 __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                              const uint4 e, TaskStats& ts) {
+                                              const uint4 eq, TaskStats& ts) {
     const int lane = lane_id();
+    const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
     int32_t bx, by, bz;
     unpack_key(entry_key(e), bx, by, bz);

@@ -117,6 +117,11 @@ __device__ inline unsigned long long entry_key(const uint4& e) {
     return (unsigned long long)e.z | ((unsigned long long)e.w << 32);
 }
 
+// Values the caller knows to be equal on every active lane, moved to scalar registers (a wave waits
+// for a loaded value here, so loaded values that are needed late are better left alone).
+__device__ inline uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ inline uint4 uniform(const uint4& e) { return make_uint4(uniform(e.x), uniform(e.y), uniform(e.z), uniform(e.w)); }
+
 // world <- sensor rigid transform, FP64
 struct Pose {
     double R[3][3];
