@@ -1,5 +1,5 @@
-// Batched fusion of many independent maps: one frame per map per call, three launches in total,
-// each covering every map through device-side tables (the per-map work is exactly that of the
+// Batched fusion of many independent maps: one frame per map per call, at most four launches in
+// total, each covering every map (of its kind) through device-side tables (the per-map work is exactly that of the
 // single-map path, frame hand-offs included), captured once into a HIP graph and replayed while
 // the frame sizes stay fixed.
 //
@@ -8,11 +8,14 @@
 //                     last workgroup also runs its allocation-side hand-off
 //   k_batch_rays      LiDAR maps: one workgroup per kRaysPerGroup rays (their recorded (ray, block)
 //                     pairs in parallel: traversal and accumulation)
-//   k_batch_update    the update tasks of every map (per-level queues), strided over the
-//                     concatenated task space; workgroup i also runs map i's update-side hand-off
+//   k_batch_update    the update tasks of every map of one frame kind (RGB-D or LiDAR: one launch
+//                     per kind present, so that each gets the registers of its own path), strided
+//                     over the concatenated task space; workgroup i also runs the update-side
+//                     hand-off of map i when map i is of that kind
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mrh_depth.h"
@@ -78,17 +81,21 @@ __global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ m
     points_ray_chunk<ST>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
 }
 
-template <int ST>
+template <int ST, int KIND>
 __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
                                                       int n) {
+    // the entry table is written by the host before the launch: read through the constant address
+    // space, so that a frame's descriptor (pose, intrinsics) is loaded into scalar registers
+    typedef __attribute__((address_space(4))) const BatchEntry CEntry;
+    const CEntry* ce = (const CEntry*)ents;
     __shared__ TaskCounts cnt[kMaxBatch];
     __shared__ uint32_t pre[kMaxBatch + 1];
     __shared__ unsigned long long wst[kMaxBatch][5];
-    if ((int)blockIdx.x < n && ents[blockIdx.x].kind != MRH_FRAME_NONE)
+    if ((int)blockIdx.x < n && ents[blockIdx.x].kind == KIND)
         update_duties(maps[blockIdx.x], entry_parity(ents[blockIdx.x]));
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        if (ents[i].kind == MRH_FRAME_NONE) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
-        else cnt[i] = frame_task_counts(maps[i], ents[i].kind == MRH_FRAME_DEPTH, entry_parity(ents[i]));
+        if (ents[i].kind != KIND) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
+        else cnt[i] = frame_task_counts(maps[i], KIND == MRH_FRAME_DEPTH, entry_parity(ents[i]));
     }
     for (int k = threadIdx.x; k < 5 * n; k += blockDim.x) wst[k / 5][k % 5] = 0ull;
     __syncthreads();
@@ -98,20 +105,19 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
     }
     __syncthreads();
     const uint32_t total = pre[n];
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     // strided over the concatenated task space (neighbouring tasks cost alike, so striding spreads
     // the expensive runs); a wave's statistics go to per-map LDS sums, flushed once per workgroup
     int cur = -1;
     TaskStats ts;
     auto flush = [&](int i) {
-        const unsigned long long lo = wave_sum(ts.lane_obs), lm = wave_sum(ts.lane_merges);
         if (lane_id() == 0) {
-            atomicAdd(&wst[i][0], ts.obs + lo);
+            atomicAdd(&wst[i][0], ts.obs);
             atomicAdd(&wst[i][1], ts.fresh);
-            atomicAdd(&wst[i][2], ts.merges[0]);
-            atomicAdd(&wst[i][3], ts.merges[1]);
-            atomicAdd(&wst[i][4], lm);
+            atomicAdd(&wst[i][2], ts.merge0);
+            atomicAdd(&wst[i][3], ts.merge1);
+            atomicAdd(&wst[i][4], ts.merge2);
         }
     };
     for (uint32_t t = wave; t < total; t += nwaves) {
@@ -122,14 +128,23 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
             if (pre[mid] <= t) lo = mid;
             else hi = mid;
         }
+        lo = (int)uniform((uint32_t)lo);
         if (lo != cur) {
             if (cur >= 0) flush(cur);
             ts = TaskStats();
             cur = lo;
         }
         const uint32_t local = t - pre[lo];
-        if (ents[lo].kind == MRH_FRAME_DEPTH) depth_update_task<ST>(maps[lo], ents[lo].df, local, cnt[lo], ts);
-        else points_update_task<ST>(maps[lo], local, cnt[lo], ts, ents[lo].sp.parity);
+        TaskCounts c = cnt[lo];
+        for (int k = 0; k < 4; ++k) c.n[k] = uniform(c.n[k]);
+        c.new_base = uniform(c.new_base);
+        c.n_new = uniform(c.n_new);
+        if constexpr (KIND == MRH_FRAME_DEPTH) {
+            const DepthFrame fr = *(const DepthFrame*)&ce[lo].df;
+            ts.add(depth_update_task<ST>(maps[lo], fr, local, c));
+        } else {
+            ts.add_uniform(points_update_task<ST>(maps[lo], local, c, ((const BatchEntry*)&ce[lo])->sp.parity));
+        }
     }
     if (cur >= 0) flush(cur);
     __syncthreads();
@@ -172,8 +187,9 @@ static void drop_graph(mrh_batch* b) {
     b->graph_sig.clear();
 }
 
-// Enqueue the four batched launches on stream s for the geometry in h (host copy of the table).
-static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32_t ray_wgs) {
+// Enqueue the batched launches on stream s for the launch geometry of the current table.
+static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32_t ray_wgs, int depth_maps,
+                         int point_maps) {
     const int n = b->n;
     if (alloc_wgs) hipLaunchKernelGGL(k_batch_alloc, dim3(alloc_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
     if (ray_wgs) {
@@ -185,11 +201,16 @@ static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32
     }
     // at least one workgroup per map: workgroup i carries map i's update-side hand-off
     const dim3 ug((unsigned)(b->update_wgs > n ? b->update_wgs : n));
-    switch (b->storage) {
-        case MRH_STORE_F16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
-        case MRH_STORE_BF16: hipLaunchKernelGGL(k_batch_update<MRH_STORE_BF16>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
-        default: hipLaunchKernelGGL(k_batch_update<MRH_STORE_F32>, ug, dim3(256), 0, s, b->d_maps, b->d_ents, n);
-    }
+    auto update = [&](auto kind) {
+        constexpr int K = decltype(kind)::value;
+        switch (b->storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F16, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_BF16, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
+            default: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F32, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n);
+        }
+    };
+    if (depth_maps) update(std::integral_constant<int, MRH_FRAME_DEPTH>());
+    if (point_maps) update(std::integral_constant<int, MRH_FRAME_POINTS>());
 }
 
 }  // namespace mrh
@@ -297,6 +318,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
     sig.push_back(b->update_wgs);
     sig.push_back(b->cull_wgs);
     uint32_t alloc_wgs = 0, ray_wgs = 0;
+    int depth_maps = 0, point_maps = 0;
     for (int i = 0; i < n; ++i) {
         const mrh_frame& f = frames[i];
         BatchEntry& e = h[i];
@@ -325,6 +347,8 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         }
         e.alloc_end = alloc_wgs;
         e.ray_end = ray_wgs;
+        depth_maps += f.kind == MRH_FRAME_DEPTH ? 1 : 0;
+        point_maps += f.kind == MRH_FRAME_POINTS ? 1 : 0;
         sig.push_back(f.kind);
         sig.push_back((int64_t)e.alloc_end);
         sig.push_back((int64_t)e.ray_end);
@@ -339,7 +363,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
             if (frames[i].kind != MRH_FRAME_NONE) b->maps[i]->frames += 1;
     };
     if (!b->use_graph) {
-        launch(m0, K_BATCH_GRAPH, [&] { enqueue_step(b, b->stream, alloc_wgs, ray_wgs); });
+        launch(m0, K_BATCH_GRAPH, [&] { enqueue_step(b, b->stream, alloc_wgs, ray_wgs, depth_maps, point_maps); });
         const mrh_status st = check_hip(m0, hipGetLastError(), "batch_integrate");
         if (st == MRH_OK) advance();
         return st;
@@ -349,7 +373,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return batch_err(b, MRH_ERR_HIP, "batch: begin capture");
-        enqueue_step(b, b->capture_stream, alloc_wgs, ray_wgs);
+        enqueue_step(b, b->capture_stream, alloc_wgs, ray_wgs, depth_maps, point_maps);
         const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
         if (ce != hipSuccess || !g) return batch_err(b, MRH_ERR_HIP, "batch: end capture");
         const hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);

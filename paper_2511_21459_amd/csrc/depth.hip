@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restric
     const TaskCounts n = frame_task_counts(m, true, f.parity);
     const uint32_t ntask = update_task_count(n);
     TaskStats ts;
-    for (uint32_t t = wave; t < ntask; t += nwaves) depth_update_task<ST>(m, f, t, n, ts);
+    for (uint32_t t = wave; t < ntask; t += nwaves) ts.add(depth_update_task<ST>(m, f, t, n));
     flush_task_stats(m, ts);
 }
 

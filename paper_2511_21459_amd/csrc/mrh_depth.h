@@ -302,18 +302,18 @@ __device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_
 
 // Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
 template <int ST>
-__device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            const uint4 eq, TaskStats& ts) {
+__device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                            const uint4 eq) {
     const int lane = lane_id();
     const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
-    if (info & kNoBlockBit) return;
+    if (info & kNoBlockBit) return TaskOut{};
     int32_t bx, by, bz;
     unpack_key(entry_key(e), bx, by, bz);
     const bool fresh = (info & kNewBit) != 0;
     const double bvs = m.bvsum[id];
     const uint32_t bvc = m.bvcnt[id];
-    if (!fresh && block_hidden(m, f, bx, by, bz)) return;
+    if (!fresh && block_hidden(m, f, bx, by, bz)) return TaskOut{};
     int I, J, K;
     demorton3(lane, I, J, K);
     const double nu = m.nu[0];
@@ -386,9 +386,10 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         }
     }
     const int nupd = wave_sum((int)__popc(upd));
-    if (nupd == 0 && !fresh) return;
-    ts.obs += (unsigned long long)nupd;
-    if (fresh) ts.fresh += (unsigned long long)nupd;
+    if (nupd == 0 && !fresh) return TaskOut{};
+    TaskOut out;
+    out.obs = (uint32_t)nupd;
+    out.fresh = fresh ? (uint32_t)nupd : 0u;
 
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
     float D[8], S2[8];
@@ -412,14 +413,15 @@ __device__ inline void integrate_fine_block(const DevMap& m, const DepthFrame& f
         dsum += var_term(m, W[q], S2[q]) - before;
         dcnt += var_count(m, W[q]) - cb;
     }
-    ts.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt,
+    out.merge0 = (uint32_t)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, nupd, dsum, dcnt,
                                                         bvs, bvc, f.parity);
+    return out;
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
-__device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                              const uint4 eq, TaskStats& ts) {
+__device__ inline TaskOut integrate_level1_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                              const uint4 eq) {
     const int lane = lane_id();
     const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
@@ -427,7 +429,7 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
     unpack_key(entry_key(e), bx, by, bz);
     const double bvs = m.bvsum[id];
     const uint32_t bvc = m.bvcnt[id];
-    if (block_hidden(m, f, bx, by, bz)) return;
+    if (block_hidden(m, f, bx, by, bz)) return TaskOut{};
     int i, j, k;
     demorton3(lane, i, j, k);
     double x0, x1, x2;
@@ -435,8 +437,9 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
     float obs = 0.f;
     const bool upd = observe(m, f, depth, x0, x1, x2, obs);
     const int nupd = __popcll(__ballot(upd));
-    if (nupd == 0) return;
-    ts.obs += (unsigned long long)nupd;
+    if (nupd == 0) return TaskOut{};
+    TaskOut out;
+    out.obs = (uint32_t)nupd;
     const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
     float D, S2;
     uint32_t W;
@@ -451,15 +454,15 @@ __device__ inline void integrate_level1_block(const DevMap& m, const DepthFrame&
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    ts.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt, bvs, bvc,
+    out.merge1 = (uint32_t)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, nupd, dsum, dcnt, bvs, bvc,
                                                           f.parity);
+    return out;
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
 template <int ST>
-__device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                               const uint4* list, uint32_t count, uint32_t group, int level,
-                                               TaskStats& ts) {
+__device__ inline TaskOut integrate_packed_blocks(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                               const uint4* list, uint32_t count, uint32_t group, int level) {
     const int lane = lane_id();
     const int seg = level == 2 ? 8 : 1;
     const uint32_t bi = group * (uint32_t)(64 / seg) + (uint32_t)(lane / seg);
@@ -479,14 +482,13 @@ __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame
         voxel_camera(m, f, bx, by, bz, level, i, j, k, x0, x1, x2);
         upd = observe(m, f, depth, x0, x1, x2, obs);
     }
-    if (!__ballot(upd)) return;
+    if (!__ballot(upd)) return TaskOut{};
     float D = 0.f, S2 = 0.f;
     uint32_t W = 0;
     double dsum = 0.0;
     int dcnt = 0;
     if (upd) {
         Store<ST>::get(m, level, (size_t)(info & kSlotMask) * seg + (lane % seg), D, W, S2);
-        ts.lane_obs += 1;
         const double before = var_term(m, W, S2);
         const int cb = var_count(m, W);
         welford(obs, D, W, S2);
@@ -497,23 +499,26 @@ __device__ inline void integrate_packed_blocks(const DevMap& m, const DepthFrame
         // a segment whose block merges needs all of its voxels
         Store<ST>::get(m, level, (size_t)(info & kSlotMask) * seg + (lane % seg), D, W, S2);
     }
-    ts.lane_merges += (unsigned long long)finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum,
-                                                      dcnt);
+    TaskOut out;
+    out.obs = (uint32_t)wave_sum(upd ? 1 : 0);
+    out.merge2 = (uint32_t)wave_sum(finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum,
+                                                      dcnt));
+    return out;
 }
 
 // One update task t of the frame's task space (see TaskCounts).
 template <int ST>
-__device__ inline void depth_update_task(const DevMap& m, const DepthFrame& f, uint32_t t, const TaskCounts& c,
-                                         TaskStats& ts) {
-    const uint32_t n0 = c.n[0] + c.n_new, g2 = (c.n[2] + 7) / 8;
-    if (t < c.n[0]) integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t], ts);
-    else if (t < n0) {
+__device__ inline TaskOut depth_update_task(const DevMap& m, const DepthFrame& f, uint32_t t, const TaskCounts& c) {
+    const uint32_t n0 = c.n[0] + c.n_new;
+    const uint32_t g2 = (c.n[2] + 7) / 8;
+    if (t < c.n[0]) return integrate_fine_block<ST>(m, f, f.depth, m.vis[0][t]);
+    if (t < n0) {
         const uint32_t id = c.new_base + (t - c.n[0]);
-        integrate_fine_block<ST>(m, f, f.depth, make_entry(id, m.binfo[id], m.bkey[id]), ts);
+        return integrate_fine_block<ST>(m, f, f.depth, make_entry(id, m.binfo[id], m.bkey[id]));
     }
-    else if (t < n0 + c.n[1]) integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n0], ts);
-    else if (t < n0 + c.n[1] + g2) integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], c.n[2], t - n0 - c.n[1], 2, ts);
-    else integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], c.n[3], t - n0 - c.n[1] - g2, 3, ts);
+    if (t < n0 + c.n[1]) return integrate_level1_block<ST>(m, f, f.depth, m.vis[1][t - n0]);
+    if (t < n0 + c.n[1] + g2) return integrate_packed_blocks<ST>(m, f, f.depth, m.vis[2], c.n[2], t - n0 - c.n[1], 2);
+    return integrate_packed_blocks<ST>(m, f, f.depth, m.vis[3], c.n[3], t - n0 - c.n[1] - g2, 3);
 }
 
 }  // namespace mrh

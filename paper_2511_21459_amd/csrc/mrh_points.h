@@ -303,12 +303,19 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
     }
     if (cnt > K) {
         point_segment(m, sp, own, a, e, p, nn);
+        // the walk state waits in LDS while a block is traversed (registers would hold both)
+        __shared__ Walk wsave[256];
         Walk w;
         w.init(a, e, m.invB);
         bool more = true;
         for (uint32_t s = 0; s < K && more; ++s) more = w.next();
         while (more) {
-            ray_block<ST>(m, sp, a, e, p, nn, pack_key(w.c0, w.c1, w.c2), tab);
+            const unsigned long long key = pack_key(w.c0, w.c1, w.c2);
+            wsave[threadIdx.x] = w;
+            __asm__ volatile("" ::: "memory");
+            ray_block<ST>(m, sp, a, e, p, nn, key, tab);
+            __asm__ volatile("" ::: "memory");
+            w = wsave[threadIdx.x];
             more = w.next();
         }
     }
@@ -347,15 +354,15 @@ __device__ inline void take_accumulators(const DevMap& m, int level, size_t at, 
 }
 
 template <int ST>
-__device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as, int par) {
+__device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par) {
     const int lane = lane_id();
+    const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
     const double bvs = m.bvsum[id];
     const uint32_t bvc = m.bvcnt[id];
     const bool fresh = (info & kNewBit) != 0;
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
     uint32_t ns[8], nb[8];
-    unsigned long long s1[8], s2[8];
     {
         const uint4* a = reinterpret_cast<const uint4*>(m.acc_sat[0] + base);
         const uint4* b = reinterpret_cast<const uint4*>(m.acc_band[0] + base);
@@ -371,19 +378,10 @@ __device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as,
     }
     bool any_band = false;
     for (int q = 0; q < 8; ++q) any_band |= nb[q] != 0;
-    if (any_band) {
-        const ulonglong2* s1p = reinterpret_cast<const ulonglong2*>(m.acc_s1[0] + base);
-        const ulonglong2* s2p = reinterpret_cast<const ulonglong2*>(m.acc_s2[0] + base);
-        for (int h = 0; h < 4; ++h) {
-            const ulonglong2 u = s1p[h], v = s2p[h];
-            s1[2 * h] = u.x, s1[2 * h + 1] = u.y, s2[2 * h] = v.x, s2[2 * h + 1] = v.y;
-        }
-    } else {
-        for (int q = 0; q < 8; ++q) s1[q] = s2[q] = 0ull;
-    }
     const int wobs = wave_sum(nobs);
-    as.obs += (unsigned long long)wobs;
-    if (fresh) as.fresh += (unsigned long long)wobs;
+    TaskOut out;
+    out.obs = (uint32_t)wobs;
+    out.fresh = fresh ? (uint32_t)wobs : 0u;
     if (lane == 0) m.btouch[id] = 0u;
     float D[8], S2[8];
     uint32_t W[8];
@@ -398,14 +396,26 @@ __device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as,
     double dsum = 0.0;
     int dcnt = 0;
     if (upd) {
-        for (int q = 0; q < 8; ++q) {
+        const ulonglong2* s1p = reinterpret_cast<const ulonglong2*>(m.acc_s1[0] + base);
+        const ulonglong2* s2p = reinterpret_cast<const ulonglong2*>(m.acc_s2[0] + base);
+        for (int h = 0; h < 2; ++h) {
+        unsigned long long s1[4], s2[4];
+        if (any_band) {
+            const ulonglong2 u0 = s1p[2 * h], u1 = s1p[2 * h + 1], v0 = s2p[2 * h], v1 = s2p[2 * h + 1];
+            s1[0] = u0.x, s1[1] = u0.y, s1[2] = u1.x, s1[3] = u1.y, s2[0] = v0.x, s2[1] = v0.y, s2[2] = v1.x, s2[3] = v1.y;
+        } else {
+            for (int k = 0; k < 4; ++k) s1[k] = s2[k] = 0ull;
+        }
+        for (int qq = 0; qq < 4; ++qq) {
+            const int q = 4 * h + qq;
             if (!(upd & (1u << q))) continue;
             const double before = var_term(m, W[q], S2[q]);
             const int cb = var_count(m, W[q]);
-            apply_stats(m, ns[q], nb[q], s1[q], s2[q], D[q], W[q], S2[q]);
+            apply_stats(m, ns[q], nb[q], s1[qq], s2[qq], D[q], W[q], S2[q]);
             Store<ST>::round(m, D[q], W[q], S2[q]);
             dsum += var_term(m, W[q], S2[q]) - before;
             dcnt += var_count(m, W[q]) - cb;
+        }
         }
         // leave the accumulators at zero for the next scan
         uint4* a = reinterpret_cast<uint4*>(m.acc_sat[0] + base);
@@ -418,14 +428,16 @@ __device__ inline void apply_fine(const DevMap& m, const uint4 e, TaskStats& as,
             for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
         }
     }
-    as.merges[0] += (unsigned long long)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
+    out.merge0 = (uint32_t)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
                                                         bvs, bvc, par);
+    return out;
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
 template <int ST>
-__device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& as, int par) {
+__device__ inline TaskOut apply_level1(const DevMap& m, const uint4 eq, int par) {
     const int lane = lane_id();
+    const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
     const double bvs = m.bvsum[id];
     const uint32_t bvc = m.bvcnt[id];
@@ -436,7 +448,8 @@ __device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& a
     if (lane == 0) m.btouch[id] = 0u;
     const bool upd = ns + nb > 0;
     const int wobs = wave_sum((int)(ns + nb));
-    as.obs += (unsigned long long)wobs;
+    TaskOut out;
+    out.obs = (uint32_t)wobs;
     float D, S2;
     uint32_t W;
     Store<ST>::get(m, 1, at, D, W, S2);
@@ -450,13 +463,13 @@ __device__ inline void apply_level1(const DevMap& m, const uint4 e, TaskStats& a
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    as.merges[1] += (unsigned long long)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc, par);
+    out.merge1 = (uint32_t)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc, par);
+    return out;
 }
 
 // 64 / seg blocks of `level` (2: seg = 8 voxels, 3: seg = 1 voxel) per wave.
 template <int ST>
-__device__ inline void apply_packed(const DevMap& m, const uint4* list, uint32_t count, uint32_t group, int level,
-                                    TaskStats& as) {
+__device__ inline TaskOut apply_packed(const DevMap& m, const uint4* list, uint32_t count, uint32_t group, int level) {
     const int lane = lane_id();
     const int seg = level == 2 ? 8 : 1;
     const uint32_t bi = group * (uint32_t)(64 / seg) + (uint32_t)(lane / seg);
@@ -475,7 +488,6 @@ __device__ inline void apply_packed(const DevMap& m, const uint4* list, uint32_t
         Store<ST>::get(m, level, at, D, W, S2);
     }
     const bool upd = ns + nb > 0;
-    as.lane_obs += (unsigned long long)(ns + nb);
     double dsum = 0.0;
     int dcnt = 0;
     if (upd) {
@@ -486,19 +498,21 @@ __device__ inline void apply_packed(const DevMap& m, const uint4* list, uint32_t
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    as.lane_merges += (unsigned long long)finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0,
-                                                            dsum, dcnt);
+    TaskOut out;
+    out.obs = (uint32_t)wave_sum((int)(ns + nb));
+    out.merge2 = (uint32_t)wave_sum(finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum, dcnt));
+    return out;
 }
 
 // One update task t of a scan whose queues hold n0..n3 blocks per level.
 template <int ST>
-__device__ inline void points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, TaskStats& as, int par) {
+__device__ inline TaskOut points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, int par) {
     const uint32_t* n = c.n;  // LiDAR frames queue their new blocks like the others (n_new = 0)
     const uint32_t g2 = (n[2] + 7) / 8;
-    if (t < n[0]) apply_fine<ST>(m, m.vis[0][t], as, par);
-    else if (t < n[0] + n[1]) apply_level1<ST>(m, m.vis[1][t - n[0]], as, par);
-    else if (t < n[0] + n[1] + g2) apply_packed<ST>(m, m.vis[2], n[2], t - n[0] - n[1], 2, as);
-    else apply_packed<ST>(m, m.vis[3], n[3], t - n[0] - n[1] - g2, 3, as);
+    if (t < n[0]) return apply_fine<ST>(m, m.vis[0][t], par);
+    if (t < n[0] + n[1]) return apply_level1<ST>(m, m.vis[1][t - n[0]], par);
+    if (t < n[0] + n[1] + g2) return apply_packed<ST>(m, m.vis[2], n[2], t - n[0] - n[1], 2);
+    return apply_packed<ST>(m, m.vis[3], n[3], t - n[0] - n[1] - g2, 3);
 }
 
 }  // namespace mrh

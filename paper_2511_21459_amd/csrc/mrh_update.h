@@ -219,10 +219,32 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
     return 0;
 }
 
-// Statistics gathered by one wave over its tasks: obs / fresh / merges[0..1] are wave-uniform,
-// lane_obs / lane_merges (packed blocks) are per lane.
+// What one update task adds to its wave's statistics (wave-uniform).  Task routines return it and
+// the caller adds every field: updates of different fields in different branches would otherwise
+// be merged into one dynamically addressed update, which forces the sums into scratch memory.
+struct TaskOut {
+    uint32_t obs = 0, fresh = 0, merge0 = 0, merge1 = 0, merge2 = 0;
+};
+
+// Statistics gathered by one wave over its tasks.
 struct TaskStats {
-    unsigned long long obs = 0, fresh = 0, merges[2] = {0, 0}, lane_obs = 0, lane_merges = 0;
+    unsigned long long obs = 0, fresh = 0, merge0 = 0, merge1 = 0, merge2 = 0;
+    __device__ inline void add(const TaskOut& o) {
+        obs += o.obs;
+        fresh += o.fresh;
+        merge0 += o.merge0;
+        merge1 += o.merge1;
+        merge2 += o.merge2;
+    }
+    // the same with the (wave-uniform) counts summed in scalar registers: for kernels that are
+    // short of vector registers but not of scalar ones
+    __device__ inline void add_uniform(const TaskOut& o) {
+        obs += uniform(o.obs);
+        fresh += uniform(o.fresh);
+        merge0 += uniform(o.merge0);
+        merge1 += uniform(o.merge1);
+        merge2 += uniform(o.merge2);
+    }
 };
 
 // A frame's update task space: [queued level-0 blocks | blocks allocated this frame (ids
@@ -247,15 +269,14 @@ __device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new, i
     return c;
 }
 
-// flush one wave's statistics (lane 0 adds wave-uniform and lane-summed parts)
+// flush one wave's statistics (lane 0)
 __device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
-    const unsigned long long lane_obs = wave_sum(ts.lane_obs), lane_merges = wave_sum(ts.lane_merges);
     if (lane_id() == 0) {
-        stat_add(m, S_OBS, ts.obs + lane_obs);
+        stat_add(m, S_OBS, ts.obs);
         stat_add(m, S_OBS_FRESH, ts.fresh);
-        stat_add(m, S_MERGE0, ts.merges[0]);
-        stat_add(m, S_MERGE1, ts.merges[1]);
-        stat_add(m, S_MERGE2, lane_merges);
+        stat_add(m, S_MERGE0, ts.merge0);
+        stat_add(m, S_MERGE1, ts.merge1);
+        stat_add(m, S_MERGE2, ts.merge2);
     }
 }
 

@@ -25,12 +25,12 @@ template <int ST>
 __global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__ pm, int par) {
     const DevMap& m = *pm;
     if (blockIdx.x == 0) update_duties(m, par);
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const TaskCounts n = frame_task_counts(m, false, par);
     const uint32_t ntask = update_task_count(n);
     TaskStats as;
-    for (uint32_t t = wave; t < ntask; t += nwaves) points_update_task<ST>(m, t, n, as, par);
+    for (uint32_t t = wave; t < ntask; t += nwaves) as.add_uniform(points_update_task<ST>(m, t, n, par));
     flush_task_stats(m, as);
 }
 
