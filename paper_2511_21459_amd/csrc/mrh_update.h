@@ -408,28 +408,31 @@ __device__ inline void register_new(const DevMap& m, bool is_new, unsigned long 
 }
 
 // Wave-cooperative claim of one key per lane (has_key): keys found by a read-only probe need
-// nothing; the missing ones are deduplicated across the wave and one leader per distinct key does
-// the CAS insert.  Returns true on the lane that inserted a new key (its hash slot in *slot).
+// nothing; the missing ones are deduplicated across the wave (register-only ballots) and then one
+// leader per distinct key does the CAS insert, all leaders at once, so that a wave with several
+// new keys waits for one insert, not one after another.  Returns true on the lane that inserted a
+// new key (its hash slot in *slot).
 __device__ inline bool claim_keys(const DevMap& m, bool has_key, unsigned long long key, uint32_t* slot) {
     const int lane = lane_id();
     uint32_t stop = kInvalidId;
     bool need = false;
     if (has_key) need = probe_find(m, key, &stop) == kInvalidId;
-    bool is_new = false;
+    bool leader = false;
     unsigned long long pending = __ballot(need);
     while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const unsigned long long lkey = shfl_u64(key, leader);
-        const bool same = need && key == lkey;
-        pending &= ~__ballot(same);
-        if (lane == leader) {
-            const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, slot);
-            if (r == INS_NEW) {
-                is_new = true;
-            } else if (r == INS_FULL) {
-                atomicOr(&m.ctr->error_flags.v, kErrTableFull);
-                stat_add(m, S_FAILED, 1ull);
-            }
+        const int first = __ffsll((long long)pending) - 1;
+        const unsigned long long lkey = shfl_u64(key, first);
+        pending &= ~__ballot(need && key == lkey);
+        leader |= lane == first;
+    }
+    bool is_new = false;
+    if (leader) {
+        const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, slot);
+        if (r == INS_NEW) {
+            is_new = true;
+        } else if (r == INS_FULL) {
+            atomicOr(&m.ctr->error_flags.v, kErrTableFull);
+            stat_add(m, S_FAILED, 1ull);
         }
     }
     return is_new;
