@@ -105,3 +105,21 @@ def test_batch_autotune_resets_maps(mrh):
     for i, c in enumerate(cfgs):
         maps[i].sync()
         _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames]))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_steps_of_one_frame_kind(mrh, graph):
+    """Steps whose frames are all RGB-D, then all LiDAR, then mixed: each step launches only the
+    update kernels of the kinds present (and a new graph when the kinds change)."""
+    announce(f"batch steps of one frame kind, graph={graph}")
+    cfgs, frames = _streams()
+    kinds = [("depth",), ("points",), ("depth", "points")]
+    steps = [[fr if fr is not None and fr[0] in kinds[k] else None for fr in frames[k]] for k in range(3)]
+    maps = [mrh.Map(**c) for c in cfgs]
+    b = mrh.Batch(maps)
+    b.set_launch(256, 16, graph)
+    for fr in steps:
+        b.integrate(fr)
+    for i, c in enumerate(cfgs):
+        maps[i].sync()
+        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in steps]))
