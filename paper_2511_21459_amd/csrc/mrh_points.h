@@ -53,11 +53,19 @@ constexpr int kAllocRaysPerWave = 4;
 constexpr int kAllocRaysPerGroup = 4 * kAllocRaysPerWave;
 
 // Allocation for rays chunk * kAllocRaysPerGroup ..: the block walk of each ray, the wave-
-// deduplicated insert of the keys, and the record of each ray's keys in walk order.
+// deduplicated insert of the keys, and the record of each ray's keys in walk order.  A ray's walk
+// is a chain of lookups, so it advances kAllocRound blocks at a time: the ray's lane runs that many
+// DDA steps (arithmetic only) and leaves the keys in LDS, and then every lane of the wave claims one
+// key (ray = lane / kAllocRound, step = lane % kAllocRound): one round of probes and inserts for the
+// 64 keys instead of one per step.
+constexpr int kAllocRound = 64 / kAllocRaysPerWave;
+
 __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk) {
-    const int lane = lane_id();
+    __shared__ unsigned long long skeys[4][64];  // per wave: kAllocRaysPerWave rays x kAllocRound keys
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
     const bool mine = lane < kAllocRaysPerWave;
-    const int64_t i = (int64_t)chunk * kAllocRaysPerGroup + (int64_t)(threadIdx.x >> 6) * kAllocRaysPerWave + lane;
+    const int64_t r0 = (int64_t)chunk * kAllocRaysPerGroup + (int64_t)wv * kAllocRaysPerWave;
+    const int64_t i = r0 + lane;
     double a[3], e[3], p[3], nn[3];
     const bool ok = mine && i < sp.n && point_segment(m, sp, i, a, e, p, nn);
     const unsigned long long vmask = __ballot(ok);
@@ -71,15 +79,37 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
     if (in_range) w.init(a, e, m.invB);
     bool active = in_range;
     uint32_t steps = 0;
-    unsigned long long* rk = m.rkeys + (size_t)(i < sp.n ? i : 0) * (size_t)m.rcap_k;
+    // the ray and walk step whose key this lane claims in each round
+    const int ray = lane / kAllocRound, k = lane % kAllocRound;
+    const int64_t ri = r0 + ray;
+    unsigned long long* rk = m.rkeys + (size_t)(ri < sp.n ? ri : 0) * (size_t)m.rcap_k;
     while (__ballot(active)) {
-        const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
-        insert_keys(m, active, key);
-        if (active) {
-            if (steps < (uint32_t)m.rcap_k) rk[steps] = key;
-            ++steps;
-            active = w.next();
+        uint32_t cnt = 0;
+        if (mine) {
+            for (int s = 0; s < kAllocRound; ++s) {
+                unsigned long long key = 0ull;
+                if (active) {
+                    key = pack_key(w.c0, w.c1, w.c2);
+                    ++cnt;
+                    active = w.next();
+                }
+                skeys[wv][lane * kAllocRound + s] = key;
+            }
         }
+        // LDS operations of one wave complete in order; the fences keep the compiler from moving
+        // the read above the other lanes' writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const unsigned long long key = skeys[wv][lane];
+        const uint32_t rcnt = (uint32_t)__shfl((int)cnt, ray), rsteps = (uint32_t)__shfl((int)steps, ray);
+        const bool has = (uint32_t)k < rcnt;
+        insert_keys(m, has, key);
+        if (has && rsteps + (uint32_t)k < (uint32_t)m.rcap_k) rk[rsteps + (uint32_t)k] = key;
+        steps += cnt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (mine && i < sp.n) m.rcount[i] = steps;
 }
