@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
+    ap.add_argument("--only", choices=["street", "batched"],
+                    help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -412,6 +414,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only == "street":
+        print(json.dumps({"street": run_street(args, torch, np, mrh, configs)["out"]}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": run_batched(args, torch, np, mrh, configs)}), flush=True)
+        return
     room = run_room(args, torch, np, mrh, configs, room_sequence)
     census, wall, prof = room["census"], room["wall"], room["prof"]
     valid_points = sum(f["valid_points"] for f in census)
