@@ -56,6 +56,46 @@ __device__ inline void push_pending(const DevMap& m, int level, uint32_t slot, i
     }
 }
 
+// Wave-level forms of the two above for the lanes in `want` / `push` (one atomic for the wave, since
+// same-address device atomics serialise chip-wide).  The popped slots are those the same number of
+// single pops would return (stack[top-1], stack[top-2], ..); lanes beyond the free count get -1 and
+// the heap-full flag is raised.  Callable with some lanes inactive.
+__device__ inline int64_t pop_slots_wave(const DevMap& m, int level, bool want) {
+    const unsigned long long mask = __ballot(want);
+    if (!mask) return -1;
+    const int n = __popcll(mask), first = __ffsll((long long)mask) - 1;
+    int32_t top = 0;
+    if (lane_id() == first) {
+        top = atomicSub(&m.ctr->top[level].v, n);
+        const int32_t avail = top <= 0 ? 0 : (top < n ? top : n);
+        if (avail < n) {
+            atomicAdd(&m.ctr->top[level].v, n - avail);
+            atomicOr(&m.ctr->error_flags.v, kErrHeapFull);
+        }
+    }
+    top = __shfl(top, first);
+    const int avail = top <= 0 ? 0 : (top < n ? top : n);
+    const int r = rank_in_mask(mask);
+    if (!want || r >= avail) return -1;
+    return (int64_t)m.stack[level][top - 1 - r];
+}
+
+__device__ inline void push_pending_wave(const DevMap& m, int level, bool push, uint32_t slot, int par) {
+    const unsigned long long mask = __ballot(push);
+    if (!mask) return;
+    const int first = __ffsll((long long)mask) - 1;
+    uint32_t p = 0;
+    if (lane_id() == first) {
+        p = level == 0 ? atomicAdd(&m.ctr->pending0[par].v, (uint32_t)__popcll(mask))
+                       : atomicAdd(&m.ctr->pending[level].v, (uint32_t)__popcll(mask));
+    }
+    p = (uint32_t)__shfl((int)p, first) + (uint32_t)rank_in_mask(mask);
+    if (push) {
+        if (level == 0) m.pend0[par][p] = slot;
+        else m.pend[level][p] = slot;
+    }
+}
+
 // End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
 // sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
 // written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
@@ -185,7 +225,7 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
     }
     bool merge = live && nupd > 0 && level < m.levels - 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
     int64_t cslot = -1;
-    if (merge && leader) cslot = pop_slot(m, level + 1);
+    cslot = pop_slots_wave(m, level + 1, merge && leader);
     if (seg > 1) cslot = (int64_t)__shfl((long long)cslot, lane - (lane % seg));
     merge = merge && cslot >= 0;
     const uint32_t slot = info & kSlotMask;
@@ -213,7 +253,7 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
         m.bvsum[id] = var_term(m, Wc, Sc);
         m.bvcnt[id] = (uint32_t)var_count(m, Wc);
         m.binfo[id] = (uint32_t)cslot | ((uint32_t)(level + 1) << kLevelShift);
-        push_pending(m, level, slot, par);
+        push_pending_wave(m, level, true, slot, par);
         return 1;
     }
     return 0;
