@@ -220,8 +220,8 @@ class Map:
 
 
 class Batch:
-    """Many maps fused together: one frame per map per ``integrate`` call, four launches in total,
-    replayed from a captured HIP graph while the frame sizes stay the same."""
+    """Many maps fused together: one frame per map per ``integrate`` call, at most four launches in
+    total, replayed from a captured HIP graph while the frame kinds and sizes stay the same."""
 
     def __init__(self, maps):
         self.maps = list(maps)
