@@ -130,6 +130,23 @@ def test_street_sequence_multires(mrh, orc):
     assert merges > 50
 
 
+def test_street_full_size_first_scans(mrh, orc):
+    """LiDAR at the full street configuration (64 rings x 2048 azimuths, 2^21 blocks, 2^22 slots,
+    the launch shapes the benchmark times), first 2 scans: per-scan counts and the whole map."""
+    announce("street 64x2048 x2 scans full config")
+    pts, poses, _ = street_sequence(rings=64, azimuths=2048, scans=[0, 1])
+    g = mrh.Map(**configs.STREET)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.STREET))
+    for k in range(pts.shape[0]):
+        g.integrate_points(_dev(pts[k]), poses[k])
+        last, _ = g.sync()
+        st = o.integrate_points(pts[k], poses[k])
+        assert last["valid_points"] == st["valid_points"]
+        assert last["new_blocks"] == st["new_blocks"]
+        assert last["observations"] == st["observations"]
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)))
+
+
 def test_street_band_only(mrh, orc):
     announce("street 8x256 band-only (no carving)")
     pts, poses, _ = street_sequence(n_scans=200, rings=8, azimuths=256, scans=[10, 11])
