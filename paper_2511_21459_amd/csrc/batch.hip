@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
             const DepthFrame fr = *(const DepthFrame*)&ce[lo].df;
             ts.add(depth_update_task<ST>(maps[lo], fr, local, c));
         } else {
-            ts.add_uniform(points_update_task<ST>(maps[lo], local, c, ((const BatchEntry*)&ce[lo])->sp.parity));
+            ts.add_uniform(points_update_task<ST, false>(maps[lo], local, c, ((const BatchEntry*)&ce[lo])->sp.parity, nullptr));
         }
     }
     if (cur >= 0) flush(cur);

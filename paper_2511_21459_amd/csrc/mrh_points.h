@@ -383,8 +383,8 @@ __device__ inline void take_accumulators(const DevMap& m, int level, size_t at, 
     }
 }
 
-template <int ST>
-__device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par) {
+template <int ST, bool DEFER>
+__device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par, DeferList* dl) {
     const int lane = lane_id();
     const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
@@ -458,14 +458,14 @@ __device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par) {
             for (int h = 0; h < 4; ++h) s1p[h] = s2p[h] = make_ulonglong2(0ull, 0ull);
         }
     }
-    out.merge0 = (uint32_t)finish_fine<ST>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
-                                                        bvs, bvc, par);
+    out.merge0 = (uint32_t)finish_fine<ST, DEFER>(m, id, info, D, W, S2, have, upd != 0 || fresh, wobs, dsum, dcnt,
+                                                        bvs, bvc, par, dl);
     return out;
 }
 
 // Level-1 block: lane l owns the voxel at Morton position l.
-template <int ST>
-__device__ inline TaskOut apply_level1(const DevMap& m, const uint4 eq, int par) {
+template <int ST, bool DEFER>
+__device__ inline TaskOut apply_level1(const DevMap& m, const uint4 eq, int par, DeferList* dl) {
     const int lane = lane_id();
     const uint4 e = uniform(eq);  // one block per wave
     const uint32_t id = e.x, info = e.y;
@@ -493,7 +493,7 @@ __device__ inline TaskOut apply_level1(const DevMap& m, const uint4 eq, int par)
         dsum = var_term(m, W, S2) - before;
         dcnt = var_count(m, W) - cb;
     }
-    out.merge1 = (uint32_t)finish_coarse<ST>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc, par);
+    out.merge1 = (uint32_t)finish_coarse<ST, DEFER>(m, id, info, 1, D, W, S2, upd, wobs, dsum, dcnt, bvs, bvc, par, dl);
     return out;
 }
 
@@ -535,12 +535,15 @@ __device__ inline TaskOut apply_packed(const DevMap& m, const uint4* list, uint3
 }
 
 // One update task t of a scan whose queues hold n0..n3 blocks per level.
-template <int ST>
-__device__ inline TaskOut points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, int par) {
+// DEFER: merges of level-0 / level-1 blocks are recorded in *dl and done in batches (run_deferred);
+// the single-map update does this (a scan's merges all hit one map's stack tops and pending
+// counts), the batched update does not (its merges are spread over the maps' counters).
+template <int ST, bool DEFER>
+__device__ inline TaskOut points_update_task(const DevMap& m, uint32_t t, const TaskCounts& c, int par, DeferList* dl) {
     const uint32_t* n = c.n;  // LiDAR frames queue their new blocks like the others (n_new = 0)
     const uint32_t g2 = (n[2] + 7) / 8;
-    if (t < n[0]) return apply_fine<ST>(m, m.vis[0][t], par);
-    if (t < n[0] + n[1]) return apply_level1<ST>(m, m.vis[1][t - n[0]], par);
+    if (t < n[0]) return apply_fine<ST, DEFER>(m, m.vis[0][t], par, dl);
+    if (t < n[0] + n[1]) return apply_level1<ST, DEFER>(m, m.vis[1][t - n[0]], par, dl);
     if (t < n[0] + n[1] + g2) return apply_packed<ST>(m, m.vis[2], n[2], t - n[0] - n[1], 2);
     return apply_packed<ST>(m, m.vis[3], n[3], t - n[0] - n[1] - g2, 3);
 }

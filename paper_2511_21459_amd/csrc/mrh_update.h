@@ -96,38 +96,12 @@ __device__ inline void push_pending_wave(const DevMap& m, int level, bool push, 
     }
 }
 
-// End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
-// sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
-// written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
+// Merge of a level-0 block into level-1 slot cslot (Sec. 3.2.1, R10): lane l pools its 2x2x2 group
+// (the 8 children of coarse voxel l) and lane 0 rewrites the block's table row.  Every lane calls.
 template <int ST>
-__device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
-                                   bool have, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc,
-                                   int par) {
+__device__ inline void merge_fine_into(const DevMap& m, uint32_t id, uint32_t cslot, const float D[8],
+                                       const uint32_t W[8], const float S2[8]) {
     const int lane = lane_id();
-    const uint32_t slot = info & kSlotMask;
-    const size_t base = (size_t)slot * 512 + (size_t)lane * 8;
-    dsum = wave_sum(dsum);
-    dcnt = wave_sum(dcnt);
-    const double vsum = bvs + dsum;
-    const uint32_t vcnt = bvc + (uint32_t)dcnt;
-    bool merge = nupd > 0 && m.levels > 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
-    int64_t cslot = -1;
-    if (merge) {
-        if (lane == 0) cslot = pop_slot(m, 1);
-        cslot = (int64_t)__shfl((long long)cslot, 0);
-        merge = cslot >= 0;
-    }
-    if (!merge) {
-        if (dirty) Store<ST>::put8(m, base, D, W, S2);
-        if (lane == 0) {
-            m.bvsum[id] = vsum;
-            m.bvcnt[id] = vcnt;
-            if (info & kNewBit) m.binfo[id] = info & ~kNewBit;
-        }
-        return 0;
-    }
-    if (!have) Store<ST>::get8(m, base, D, W, S2);
-    // pool the 8 children: total weight, weighted mean TSDF, summed S2
     uint32_t Wc = 0;
     float sd = 0.f, s2 = 0.f;
     for (int q = 0; q < 8; ++q) {
@@ -145,18 +119,191 @@ __device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, f
     if (lane == 0) {
         m.bvsum[id] = csum;
         m.bvcnt[id] = (uint32_t)ccnt;
-        m.binfo[id] = (uint32_t)cslot | (1u << kLevelShift);
-        push_pending(m, 0, slot, par);
+        m.binfo[id] = cslot | (1u << kLevelShift);
     }
+}
+
+// Merge of a level-1 block (lane = Morton position) into level-2 slot cslot: the 8 children of a
+// coarse voxel are 8 consecutive lanes.  Every lane calls.
+template <int ST>
+__device__ inline void merge_level1_into(const DevMap& m, uint32_t id, uint32_t cslot, float D, uint32_t W, float S2) {
+    const int lane = lane_id();
+    uint32_t Wc = W;
+    float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
+    for (int o = 1; o < 8; o <<= 1) {
+        Wc += (uint32_t)__shfl_xor((int)Wc, o);
+        sd += __shfl_xor(sd, o);
+        s2 += __shfl_xor(s2, o);
+    }
+    const bool writer = (lane & 7) == 0;
+    float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
+    float Sc = Wc > 0 ? s2 : 0.f;
+    Store<ST>::round(m, Dc, Wc, Sc);
+    if (writer) Store<ST>::put(m, 2, (size_t)cslot * 8 + (size_t)(lane >> 3), Dc, Wc, Sc);
+    const double csum = wave_sum(writer ? var_term(m, Wc, Sc) : 0.0);
+    const int ccnt = wave_sum(writer ? var_count(m, Wc) : 0);
+    if (lane == 0) {
+        m.bvsum[id] = csum;
+        m.bvcnt[id] = (uint32_t)ccnt;
+        m.binfo[id] = cslot | (2u << kLevelShift);
+    }
+}
+
+// Merges recorded during a wave's tasks and performed after them (the LiDAR update, where a scan
+// merges tens of thousands of blocks): a merge candidate's update is stored as if it did not merge
+// (state and table row), its id goes to the wave's LDS list, and run_deferred() later pops the
+// coarse slots of all recorded merges with one atomic per level, pools each block from memory and
+// pushes the freed slots with one atomic per level (pops and pushes are same-address atomics that
+// serialise chip-wide).  A merge whose pop finds the heap empty leaves the block as stored and
+// raises the heap-full flag, as an immediate merge would.  Merging later in the same launch is
+// equivalent: no other task of the launch touches the block.
+constexpr int kDefer = 16;
+
+struct DeferList {
+    uint32_t* e;  // this wave's LDS words: ids[kDefer], infos[kDefer], freed level-0 / level-1 slots
+    uint32_t n;   // recorded merges (wave-uniform)
+
+    __device__ static inline void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __device__ inline void add(uint32_t id, uint32_t info) {
+        if (lane_id() == 0) {
+            e[n] = id;
+            e[kDefer + n] = info;
+        }
+        n += 1;
+    }
+    __device__ inline bool full() const { return n >= (uint32_t)kDefer; }
+};
+
+// count pops from stack[level] by lane 0 with the semantics of count single pops: returns the old
+// top; *avail receives how many succeeded (the rest is returned, heap-full flagged)
+__device__ inline int32_t pop_batch(const DevMap& m, int level, uint32_t count, uint32_t* avail) {
+    int32_t top = 0, got = 0;
+    if (count && lane_id() == 0) {
+        top = atomicSub(&m.ctr->top[level].v, (int32_t)count);
+        got = top <= 0 ? 0 : (top < (int32_t)count ? top : (int32_t)count);
+        if (got < (int32_t)count) {
+            atomicAdd(&m.ctr->top[level].v, (int32_t)count - got);
+            atomicOr(&m.ctr->error_flags.v, kErrHeapFull);
+        }
+    }
+    *avail = uniform((uint32_t)__shfl(got, 0));
+    return (int32_t)uniform((uint32_t)__shfl(top, 0));
+}
+
+// cnt freed slots (LDS list) onto the pending list of `level` with one atomic
+__device__ inline void push_batch(const DevMap& m, int level, const uint32_t* list, uint32_t cnt, int par) {
+    if (!cnt) return;
+    const int lane = lane_id();
+    uint32_t p = 0;
+    if (lane == 0) p = level == 0 ? atomicAdd(&m.ctr->pending0[par].v, cnt) : atomicAdd(&m.ctr->pending[level].v, cnt);
+    p = (uint32_t)__shfl((int)p, 0);
+    for (uint32_t i = (uint32_t)lane; i < cnt; i += 64) {
+        if (level == 0) m.pend0[par][p + i] = list[i];
+        else m.pend[level][p + i] = list[i];
+    }
+}
+
+// Perform the recorded merges; adds the merges done to m0 / m1 (levels 0 / 1).
+template <int ST>
+__device__ inline void run_deferred(const DevMap& m, DeferList& dl, int par, unsigned long long& m0,
+                                    unsigned long long& m1) {
+    if (dl.n == 0) return;
+    DeferList::sync();
+    uint32_t n0 = 0, n1 = 0;
+    for (uint32_t i = 0; i < dl.n; ++i) {
+        if (((uniform(dl.e[kDefer + i]) >> kLevelShift) & 3u) == 0u) ++n0;
+        else ++n1;
+    }
+    uint32_t a0 = 0, a1 = 0;
+    const int32_t t1 = pop_batch(m, 1, n0, &a0), t2 = pop_batch(m, 2, n1, &a1);
+    uint32_t* fl0 = dl.e + 2 * kDefer;
+    uint32_t* fl1 = dl.e + 3 * kDefer;
+    uint32_t r0 = 0, r1 = 0, f0 = 0, f1 = 0;
+    const int lane = lane_id();
+    for (uint32_t i = 0; i < dl.n; ++i) {
+        const uint32_t id = uniform(dl.e[i]), info = uniform(dl.e[kDefer + i]);
+        const uint32_t slot = info & kSlotMask;
+        if (((info >> kLevelShift) & 3u) == 0u) {
+            const uint32_t r = r0++;
+            if (r >= a0) continue;
+            const uint32_t cslot = uniform(m.stack[1][t1 - 1 - (int32_t)r]);
+            float D[8], S2[8];
+            uint32_t W[8];
+            Store<ST>::get8(m, (size_t)slot * 512 + (size_t)lane * 8, D, W, S2);
+            merge_fine_into<ST>(m, id, cslot, D, W, S2);
+            if (lane == 0) fl0[f0] = slot;
+            ++f0;
+        } else {
+            const uint32_t r = r1++;
+            if (r >= a1) continue;
+            const uint32_t cslot = uniform(m.stack[2][t2 - 1 - (int32_t)r]);
+            float D, S2;
+            uint32_t W;
+            Store<ST>::get(m, 1, (size_t)slot * 64 + (size_t)lane, D, W, S2);
+            merge_level1_into<ST>(m, id, cslot, D, W, S2);
+            if (lane == 0) fl1[f1] = slot;
+            ++f1;
+        }
+    }
+    DeferList::sync();
+    push_batch(m, 0, fl0, f0, par);
+    push_batch(m, 1, fl1, f1, par);
+    DeferList::sync();
+    m0 += f0;
+    m1 += f1;
+    dl.n = 0;
+}
+
+// End of a level-0 block's update.  dsum / dcnt are this lane's change of the block's variance
+// sum and count, nupd the wave's number of updated voxels, dirty whether this lane's group must be
+// written back, have whether D/W/S2 hold the lane's current group.  Returns 1 when the block merged.
+template <int ST, bool DEFER = false>
+__device__ inline int finish_fine(const DevMap& m, uint32_t id, uint32_t info, float D[8], uint32_t W[8], float S2[8],
+                                   bool have, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc,
+                                   int par, DeferList* dl = nullptr) {
+    const int lane = lane_id();
+    const uint32_t slot = info & kSlotMask;
+    const size_t base = (size_t)slot * 512 + (size_t)lane * 8;
+    dsum = wave_sum(dsum);
+    dcnt = wave_sum(dcnt);
+    const double vsum = bvs + dsum;
+    const uint32_t vcnt = bvc + (uint32_t)dcnt;
+    bool merge = nupd > 0 && m.levels > 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
+    if (DEFER && merge) {
+        dl->add(id, info);
+        merge = false;
+    }
+    int64_t cslot = -1;
+    if (merge) {
+        if (lane == 0) cslot = pop_slot(m, 1);
+        cslot = (int64_t)__shfl((long long)cslot, 0);
+        merge = cslot >= 0;
+    }
+    if (!merge) {
+        if (dirty) Store<ST>::put8(m, base, D, W, S2);
+        if (lane == 0) {
+            m.bvsum[id] = vsum;
+            m.bvcnt[id] = vcnt;
+            if (info & kNewBit) m.binfo[id] = info & ~kNewBit;
+        }
+        return 0;
+    }
+    if (!have) Store<ST>::get8(m, base, D, W, S2);
+    merge_fine_into<ST>(m, id, (uint32_t)cslot, D, W, S2);
+    if (lane == 0) push_pending(m, 0, slot, par);
     return 1;
 }
 
 // End of a level-1 block's update (lane = Morton position).  The 8 children of a coarse voxel are
 // 8 consecutive lanes.  Returns 1 when the block merged.
-template <int ST>
+template <int ST, bool DEFER = false>
 __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info, int level, float D, uint32_t W,
                                      float S2, bool dirty, int nupd, double dsum, int dcnt, double bvs, uint32_t bvc,
-                                     int par) {
+                                     int par, DeferList* dl = nullptr) {
     const int lane = lane_id();
     const int side = 8 >> level, nv = side * side * side;
     const uint32_t slot = info & kSlotMask;
@@ -166,6 +313,10 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
     const double vsum = bvs + dsum;
     const uint32_t vcnt = bvc + (uint32_t)dcnt;
     bool merge = nupd > 0 && level < m.levels - 1 && vcnt > 0 && vsum / (double)vcnt < m.var_thr;
+    if (DEFER && merge) {  // level 1 only: run_deferred pools level-1 blocks
+        dl->add(id, info);
+        merge = false;
+    }
     int64_t cslot = -1;
     if (merge) {
         if (lane == 0) cslot = pop_slot(m, level + 1);

@@ -29,8 +29,18 @@ __global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const TaskCounts n = frame_task_counts(m, false, par);
     const uint32_t ntask = update_task_count(n);
+    // merges of level-0 / level-1 blocks are recorded and done in batches (see run_deferred)
+    __shared__ uint32_t dbuf[4][4 * kDefer];
+    DeferList dl{dbuf[uniform(threadIdx.x >> 6)], 0u};
+    unsigned long long m0 = 0, m1 = 0;
     TaskStats as;
-    for (uint32_t t = wave; t < ntask; t += nwaves) as.add_uniform(points_update_task<ST>(m, t, n, par));
+    for (uint32_t t = wave; t < ntask; t += nwaves) {
+        as.add_uniform(points_update_task<ST, true>(m, t, n, par, &dl));
+        if (dl.full()) run_deferred<ST>(m, dl, par, m0, m1);
+    }
+    run_deferred<ST>(m, dl, par, m0, m1);
+    as.merge0 += m0;
+    as.merge1 += m1;
     flush_task_stats(m, as);
 }
 
