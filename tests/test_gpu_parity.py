@@ -96,6 +96,27 @@ def test_occluded_blocks(mrh, orc, form):
     print(rep)
 
 
+@pytest.mark.parametrize("size", [(203, 157), (17, 1)])
+def test_room_ragged_frame_sizes(mrh, orc, size):
+    """Frames whose width and height are not multiples of the 16x16 pixel tile (a partial last
+    tile row and column, half-pixel principal point), 4 frames of the orbit."""
+    w, h = size
+    announce(f"room ragged {w}x{h} x4 frames, 4 levels")
+    depths, cam, poses, _ = room_sequence(width=w, height=h, f=0.82 * w, frames=[0, 9, 18, 27])
+    cfg = dict(configs.ROOM, max_blocks=1 << 16, hash_slots=1 << 17)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for k in range(len(depths)):
+        g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
+        last, _ = g.sync()
+        st = o.integrate_depth(depths[k], cam.K, poses[k])
+        assert last["valid_points"] == st["valid_points"], k
+        assert last["new_blocks"] == st["new_blocks"], k
+        assert last["observations"] == st["observations"], k
+    assert o.num_blocks > 0
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"]))
+
+
 def test_room_full_size_first_frames(mrh, orc):
     """640x480 at the full configuration, first 3 frames."""
     announce("room 640x480 x3 frames full config")
