@@ -16,14 +16,8 @@
 
 namespace mrh {
 
-// float -> bfloat16, round to nearest even (quiet NaN kept)
-__host__ __device__ inline uint16_t f32_to_bf16(float x) {
-    uint32_t u;
-    __builtin_memcpy(&u, &x, 4);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even: the hardware conversion of gfx950 (v_cvt_pk_bf16_f32)
+__device__ inline uint16_t f32_to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
 __host__ __device__ inline float bf16_to_f32(uint16_t b) {
     const uint32_t u = (uint32_t)b << 16;
@@ -103,8 +97,12 @@ struct Store16 {
     __device__ static inline float decS2(const DevMap& m, uint16_t v, uint32_t W) {
         return f16_to_f32(v) * (float)W * m.tau2_f;
     }
+    // S2 / (W tau^2) through the hardware reciprocal: the product of W and tau^2 (1/2 ulp), the
+    // reciprocal (1 ulp) and the final product (1/2 ulp) keep the FP32 quotient within 2^-22 relative
+    // of the exact one, against the 2^-11 relative half-ulp of the FP16 value it is rounded to
+    // (an IEEE divide costs about ten instructions and this is done for every stored voxel).
     __device__ static inline uint16_t encS2(const DevMap& m, float S2, uint32_t W) {
-        return f32_to_f16(W > 0 ? S2 / ((float)W * m.tau2_f) : 0.f);
+        return f32_to_f16(W > 0 ? S2 * __builtin_amdgcn_rcpf((float)W * m.tau2_f) : 0.f);
     }
     // the values a store followed by a load gives back
     __device__ static inline void round(const DevMap& m, float& D, uint32_t& W, float& S2) {
