@@ -14,6 +14,8 @@ Also reported on the same JSON line:
     launches, fused by the batched FP16 graph path against plain FP32 per-map calls;
   * `query`: 1M trilinear queries near the room's surfaces, forward and adjoint;
   * `street`: 20 full-size LiDAR scans (64 x 2048) with carving, throughput and per-kernel times;
+  * `sweep`: the room sequence at merge thresholds 0 / 10 / 5 / 1 mm: blocks per level, state
+    memory and query error against the scene's exact signed distance;
   * `cpu_baseline`: the FP64 oracle on the headline workload (one thread), and the FP32 / FP16 /
     BF16 GPU maps' accuracy against the oracle's map (max / RMS |dD|, zero-crossing sign flips).
 """
@@ -382,6 +384,48 @@ def run_query(room, torch, np, mrh):
             "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1)}
 
 
+# merge thresholds of the sweep (m): a block merges once its mean voxel variance is below sigma^2;
+# 0 never merges, so every block stays at the finest level
+SWEEP_SIGMAS = (0.0, 0.01, 0.005, 0.001)
+
+
+def run_sweep(room, torch, np, mrh, configs, n_points=200_000):
+    """Merge-threshold sweep on the room sequence (the paper's threshold experiments, Sec. 3.2.1):
+    blocks per level, state memory, and the query error at points near the surfaces against the
+    scene's exact signed distance (points with |sdf| < tau / 2, where truncation does not apply)."""
+    from workloads import surface_query_points
+
+    scene, tau = room["scene"], configs.ROOM["tau"]
+    pts_np = surface_query_points(scene, n_points, sigma=0.01, seed=7)
+    truth = scene.sdf(pts_np.astype(np.float64))
+    pts = torch.from_numpy(pts_np).cuda()
+    dev = torch.from_numpy(room["depths"]).cuda()
+    rows = []
+    for sig in SWEEP_SIGMAS:
+        m = mrh.Map(**dict(configs.ROOM, var_thr=sig * sig))
+        m.integrate_depth_sequence(dev, room["cam"].K, room["poses"])
+        m.sync()
+        lv = m.extract(voxels=False)["levels"].cpu().numpy()
+        nb = [int((lv == n).sum()) for n in range(4)]
+        voxels = sum(nb[n] * (8 >> n) ** 3 for n in range(4))
+        sdf, valid, _ = m.query(pts)
+        sdf = sdf.cpu().numpy().astype(np.float64)
+        valid = valid.cpu().numpy().astype(bool)
+        near = np.abs(truth) < tau / 2
+        err = (sdf - truth)[valid & near]
+        rows.append({"sigma_thr_m": sig, "blocks_per_level": nb, "fine_block_frac": round(nb[0] / max(1, sum(nb)), 4),
+                     "voxels": voxels, "state_mb_f32": round(voxels * 12 / 1e6, 2),
+                     "query_valid_frac": round(float(valid[near].mean()), 4),
+                     "rms_err_m": round(float(np.sqrt(np.mean(err ** 2))), 5),
+                     "mean_abs_err_m": round(float(np.mean(np.abs(err))), 5)})
+        m.close()
+    base = rows[0]["voxels"]
+    for r in rows:
+        r["memory_vs_finest"] = round(r["voxels"] / base, 4)
+    return {"workload": f"room RGB-D orbit, {len(room['depths'])} frames, FP32; {n_points} query points offset "
+                        "N(0, 1 cm) from the surfaces", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,7 +439,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
-    ap.add_argument("--only", choices=["street", "batched"],
+    ap.add_argument("--only", choices=["street", "batched", "sweep"],
                     help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -419,6 +463,11 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched": run_batched(args, torch, np, mrh, configs)}), flush=True)
+        return
+    if args.only == "sweep":
+        depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
+        room = dict(depths=depths, cam=cam, poses=np.ascontiguousarray(poses), scene=scene)
+        print(json.dumps({"sweep": run_sweep(room, torch, np, mrh, configs)}), flush=True)
         return
     room = run_room(args, torch, np, mrh, configs, room_sequence)
     census, wall, prof = room["census"], room["wall"], room["prof"]
@@ -459,6 +508,7 @@ def main():
     if not args.no_extras:
         result["batched"] = run_batched(args, torch, np, mrh, configs)
         result["query"] = run_query(room, torch, np, mrh)
+        result["sweep"] = run_sweep(room, torch, np, mrh, configs)
         street = run_street(args, torch, np, mrh, configs)
         result["street"] = street["out"]
 

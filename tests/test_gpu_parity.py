@@ -79,6 +79,31 @@ def _occlusion_frames():
     return K, [(far, T), (half, T), (near, T), (holes, T), (step, T), (far, T2), (near, T2)]
 
 
+@pytest.mark.parametrize("sigma", [0.01, 0.001])
+def test_room_merge_thresholds(mrh, orc, sigma):
+    """The 4-level room orbit at the other thresholds of the merge sweep (sigma_thr = 10 mm merges
+    more blocks than the default 5 mm, 1 mm about a sixth as many): 320x240, 12 frames spread over
+    the orbit."""
+    announce(f"room 320x240 x12 frames, 4 levels, sigma_thr={sigma}")
+    frames = list(range(0, 100, 8))[:12]
+    depths, cam, poses, _ = room_sequence(width=320, height=240, f=262.5, frames=frames)
+    cfg = dict(configs.ROOM, var_thr=sigma * sigma, max_blocks=1 << 17, hash_slots=1 << 18)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    merges = [0, 0, 0, 0]
+    for k in range(len(frames)):
+        g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
+        last, _ = g.sync()
+        st = o.integrate_depth(depths[k], cam.K, poses[k])
+        assert last["valid_points"] == st["valid_points"]
+        assert last["new_blocks"] == st["new_blocks"]
+        merges = [a + b for a, b in zip(merges, st["merges"])]
+    rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"])
+    print(rep, "merges", merges)
+    if sigma >= 0.01:
+        assert merges[0] > 1000 and merges[1] > 100
+
+
 @pytest.mark.parametrize("form", ["range", "zdiff"])
 def test_occluded_blocks(mrh, orc, form):
     announce(f"occlusion planes 160x120 x7 frames form={form}")

@@ -158,6 +158,22 @@ class RoomScene:
             t = np.minimum(t, _hit_box_outside(o, w, lo, hi))
         return t
 
+    def sdf(self, p):
+        """Signed distance of world points p [..., 3] to the room's surfaces, positive in free space:
+        the minimum of the distance to the walls (from inside the room) and the signed distances of
+        the spheres and cuboids.  Exact in free space; inside an obstacle it is the depth below the
+        nearest face of that obstacle."""
+        p = np.asarray(p, dtype=np.float64)
+        size = np.array(self.size)
+        d = np.minimum(p, size - p).min(axis=-1)
+        for c, rad in self.spheres:
+            d = np.minimum(d, np.linalg.norm(p - c, axis=-1) - rad)
+        for lo, hi in self.boxes:
+            q = np.abs(p - 0.5 * (lo + hi)) - 0.5 * (hi - lo)
+            outside = np.linalg.norm(np.maximum(q, 0.0), axis=-1)
+            d = np.minimum(d, outside + np.minimum(q.max(axis=-1), 0.0))
+        return d
+
 
 def _orbit_clearance(centre, extent, orbit_c=(3.0, 3.0), orbit_r=1.5, z_mid=1.5, z_amp=0.2):
     rho = math.hypot(centre[0] - orbit_c[0], centre[1] - orbit_c[1])
@@ -338,9 +354,10 @@ def street_sequence(n_scans: int = 200, rings: int = 64, azimuths: int = 2048,
 # query points near the surfaces of a room
 # --------------------------------------------------------------------------------------------
 
-def surface_query_points(scene: RoomScene, n: int, sigma: float, seed: int = 100) -> np.ndarray:
+def surface_query_points(scene: RoomScene, n: int, sigma: float, seed: int = 100, with_offsets: bool = False):
     """float32[n, 3] world points sampled on the room's surfaces in proportion to their area and
-    offset by N(0, sigma^2) along the surface normal."""
+    offset by N(0, sigma^2) along the surface normal (towards free space); with ``with_offsets``
+    also the float64[n] offsets, in the same order."""
     rng = np.random.default_rng(seed)
     sx, sy, sz = scene.size
     faces = []  # (area, sampler)
@@ -361,6 +378,7 @@ def surface_query_points(scene: RoomScene, n: int, sigma: float, seed: int = 100
     area = np.array([a for a, _ in faces])
     counts = rng.multinomial(n, area / area.sum())
     out = []
+    offs = []
     for cnt, (_, spec) in zip(counts, faces):
         if cnt == 0:
             continue
@@ -385,6 +403,11 @@ def surface_query_points(scene: RoomScene, n: int, sigma: float, seed: int = 100
             p[:, others[1]] = rng.uniform(lo[others[1]], hi[others[1]], cnt)
             nv = np.zeros((cnt, 3))
             nv[:, axis] = nrm
-        out.append(p + nv * rng.normal(0.0, sigma, size=(cnt, 1)))
+        off = rng.normal(0.0, sigma, size=(cnt, 1))
+        out.append(p + nv * off)
+        offs.append(off[:, 0])
     pts = np.concatenate(out, axis=0)
-    return pts[rng.permutation(pts.shape[0])].astype(np.float32)
+    perm = rng.permutation(pts.shape[0])
+    if with_offsets:
+        return pts[perm].astype(np.float32), np.concatenate(offs)[perm]
+    return pts[perm].astype(np.float32)
