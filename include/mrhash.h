@@ -45,11 +45,13 @@ enum {
     MRH_FORM_ZDIFF = 1  /* depth minus the voxel's z (fronto-parallel distance) */
 };
 
-/* Storage precision of the voxel state (arithmetic is always FP32 in registers). */
+/* Storage precision of the voxel state (arithmetic is always FP32 in registers; the 16-bit formats
+ * round to nearest even on store).  The 16-bit formats keep the per-voxel variance S2 / W divided
+ * by tau^2 in place of S2; extraction returns S2 in m^2 for every format. */
 enum {
-    MRH_STORE_F32 = 0,  /* D: float metres, S2: float m^2           | W: uint32 */
-    MRH_STORE_F16 = 1,  /* D: half of D / tau, S2: half of S2/tau^2 | W: uint16 */
-    MRH_STORE_BF16 = 2  /* D: bfloat16 of D / tau, S2: half         | W: half  */
+    MRH_STORE_F32 = 0,  /* D: float metres, S2: float m^2                      | W: uint32 (12 B) */
+    MRH_STORE_F16 = 1,  /* D: half of D / tau, variance: half of S2/(W tau^2)  | W: uint16, saturating (6 B) */
+    MRH_STORE_BF16 = 2  /* D: bfloat16 of D / tau, variance: half, as for F16  | W: half (6 B) */
 };
 
 typedef struct mrh_config {
