@@ -320,6 +320,48 @@ def test_constant_field_merges_down_one_level_per_frame(orc):
     assert np.all(np.abs(ext.D) <= tau) and np.all(ext.S2 >= 0)
 
 
+@pytest.mark.parametrize("side", [-1, 1])
+def test_merge_threshold_at_closed_form_variance(orc, side):
+    """Eq. 6 and the merging criterion (Sec. 3.2.1) at a closed form.  Two noise-free planes delta
+    apart, each seen once by the same camera (z-difference form of Eq. 2), give every voxel that
+    lies inside the band on both frames W = 2, S2 = delta^2 / 2 (Eq. 5) and sigma^2 = S2 / W =
+    delta^2 / 4 (Eq. 6), so a block made only of such voxels has exactly that mean variance.  It
+    merges after the second frame when the threshold lies just above delta^2 / 4 (side +1) and
+    stays at the finest level just below it (side -1).  A variance taken as S2 / (W - 1), or a
+    comparison the other way round, fails one of the two."""
+    nu, tau, z0 = 0.02, 0.3, 2.0
+    d1, cam, T = plane_frame(z0, 32, 24, 24.0)
+    d2, _, _ = plane_frame(z0 + 0.02, 32, 24, 24.0)
+    delta = float(d2[0, 0]) - float(d1[0, 0])
+    var = delta * delta / 4.0
+    maps = {}
+    for name, thr in (("ref", 0.0), ("test", var * (1.0 + side * 1e-6))):
+        m = orc.OracleMap(nu, levels=2, tau=tau, var_thr=thr, max_depth=5.0, form="zdiff")
+        for d in (d1, d2):
+            m.integrate_depth(d, cam.K, T)
+        maps[name] = m.extract()
+    ref, ext = maps["ref"], maps["test"]
+    B = 8 * nu
+    zlo = ref.keys[:, 2] * B
+    # every voxel centre of the block within (d - z) in (-tau, tau) for both depths
+    inside = (zlo + 0.5 * nu > float(d2[0, 0]) - tau + 1e-9) & (zlo + B - 0.5 * nu < float(d1[0, 0]) + tau - 1e-9)
+    # blocks allocated by the first frame hold voxels seen twice (eligible); blocks first reached
+    # by the second frame hold single observations only and are not eligible
+    wmax = np.array([ref.W[ref.offsets[i]:ref.offsets[i + 1]].max() for i in range(len(ref.keys))])
+    eligible = inside & (wmax == 2)
+    assert eligible.sum() >= 8 and set(np.unique(ref.keys[eligible, 2]).tolist()) == {11, 12, 13}
+    for i in np.flatnonzero(eligible):
+        sl = slice(ref.offsets[i], ref.offsets[i + 1])
+        seen = ref.W[sl] > 0
+        assert np.all(ref.W[sl][seen] == 2)
+        np.testing.assert_allclose(ref.S2[sl][seen], delta * delta / 2.0, rtol=1e-9)
+    level = {tuple(k): int(lv) for k, lv in zip(ext.keys.tolist(), ext.levels)}
+    want = 1 if side > 0 else 0
+    got = [level[tuple(k)] for k in ref.keys[eligible].tolist()]
+    assert got == [want] * len(got), (side, np.bincount(got))
+    assert all(level[tuple(k)] == 0 for k in ref.keys[inside & (wmax < 2)].tolist())
+
+
 def test_free_space_merges_to_constant(orc):
     """LiDAR carving: voxels far in front of the returns see the truncated value +tau on every
     beam (Eq. 1), so blocks of free space have zero variance, merge down to the coarsest level and
