@@ -104,6 +104,35 @@ def test_room_merge_thresholds(mrh, orc, sigma):
         assert merges[0] > 1000 and merges[1] > 100
 
 
+@pytest.mark.parametrize("side", [-1, 1])
+def test_merge_threshold_closed_form(mrh, orc, side):
+    """Two noise-free planes 2 cm apart, seen once each (z-difference form): every voxel seen on
+    both frames inside the band has sigma^2 = delta^2 / 4, so the blocks made of such voxels (rows
+    z = 11..13 of 16 cm blocks) merge after the second frame with the threshold 1% above that value
+    and stay fine 1% below it; the GPU map's levels must equal the oracle's on every block."""
+    from workloads import plane_frame
+
+    announce(f"closed-form merge threshold, side {side}")
+    d1, cam, T = plane_frame(2.0, 32, 24, 24.0)
+    d2, _, _ = plane_frame(2.02, 32, 24, 24.0)
+    delta = float(d2[0, 0]) - float(d1[0, 0])
+    cfg = dict(voxel=0.02, levels=2, tau=0.3, var_thr=delta * delta / 4.0 * (1.0 + side * 1e-2), max_depth=5.0,
+               form="zdiff", max_blocks=1 << 14, hash_slots=1 << 15)
+    g = mrh.Map(**cfg)
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for d in (d1, d2):
+        g.integrate_depth(_dev(d), cam.K, T)
+        g.sync()
+        o.integrate_depth(d, cam.K, T)
+    ref = o.extract()
+    ex = excused_keys(o)
+    assert not any(k[2] in (11, 12, 13) for k in ex)
+    print(compare_maps(gpu_sorted(g), ref, excused=ex, tau=cfg["tau"]))
+    rows = np.isin(ref.keys[:, 2], [11, 12, 13])
+    merged = int((ref.levels[rows] == 1).sum())
+    assert (merged >= 8) if side > 0 else (merged == 0), merged
+
+
 @pytest.mark.parametrize("form", ["range", "zdiff"])
 def test_occluded_blocks(mrh, orc, form):
     announce(f"occlusion planes 160x120 x7 frames form={form}")
