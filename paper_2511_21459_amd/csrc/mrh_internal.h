@@ -183,11 +183,14 @@ __device__ inline uint32_t find_block(const DevMap& m, unsigned long long key) {
 enum InsertResult { INS_FOUND = 0, INS_NEW = 1, INS_FULL = 2 };
 
 // Lock-free linear-probing insert from slot `start` (the first EMPTY slot a read-only probe met).
-// Keys are only ever written by this CAS, so the returned old value decides every race.
+// Keys are only ever written by this CAS, so the returned old value decides every race.  The CAS
+// at `start` is issued without re-reading the slot (the probe saw it empty; the CAS's old value
+// says whether it still was), which saves a round trip on every new key.
 __device__ inline int probe_insert(const DevMap& m, unsigned long long key, uint32_t start, uint32_t* slot) {
     uint32_t h = start;
     for (int p = 0; p < m.max_probe; ++p) {
-        const unsigned long long k = __hip_atomic_load(&m.hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long k =
+            p == 0 ? kEmptyKey : __hip_atomic_load(&m.hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (k == key) return INS_FOUND;
         if (k == kEmptyKey) {
             const unsigned long long old = atomicCAS(&m.hkeys[h], kEmptyKey, key);
