@@ -172,16 +172,41 @@ def test_room_ragged_frame_sizes(mrh, orc, size):
 
 
 def test_room_full_size_first_frames(mrh, orc):
-    """640x480 at the full configuration, first 3 frames."""
+    """640x480 at the full configuration, first 3 frames; then the benchmark's query launch (1M
+    points near the surfaces, the same query pose) on that map, sampled outputs against the
+    oracle one by one."""
     announce("room 640x480 x3 frames full config")
-    depths, cam, poses, _ = room_sequence(frames=[0, 1, 2])
+    from workloads import surface_query_points
+
+    depths, cam, poses, scene = room_sequence(frames=[0, 1, 2])
     g = mrh.Map(**configs.ROOM)
     o = orc.OracleMap(**configs.oracle_kwargs(configs.ROOM))
     for k in range(3):
         g.integrate_depth(_dev(depths[k]), cam.K, poses[k])
         o.integrate_depth(depths[k], cam.K, poses[k])
     g.sync()
-    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=configs.ROOM["tau"]))
+    ex = excused_keys(o)
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=ex, tau=configs.ROOM["tau"]))
+    announce("room full config: 1M-point query, 10000 sampled against the oracle")
+    pts = surface_query_points(scene, 1_000_000, sigma=0.015, seed=100)
+    T = np.eye(4)
+    T[:3, 3] = [0.01, -0.01, 0.005]
+    sdf, valid, _ = g.query(_dev(pts), T=T)
+    idx = np.random.default_rng(5).choice(len(pts), 10000, replace=False)
+    osdf, ovalid, _ = o.query(pts[idx], T=T)
+    # a sample whose 3x3x3 block neighbourhood holds a block merged within rounding of the
+    # threshold may legitimately differ
+    B = 8 * configs.ROOM["voxel"]
+    pw = pts[idx].astype(np.float64) + T[:3, 3]
+    kb = np.floor(pw / B).astype(np.int64)
+    near = np.array([any((a + dx, b + dy, c + dz) in ex for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+                     for a, b, c in kb.tolist()], dtype=bool)
+    gv = valid.cpu().numpy()[idx]
+    ov = ovalid.astype(bool)
+    assert np.array_equal(gv[~near], ov[~near])
+    ok = gv & ov & ~near
+    assert ok.sum() > 1000
+    np.testing.assert_allclose(sdf.cpu().numpy()[idx][ok], osdf[ok], atol=1e-5, rtol=0)
 
 
 def test_street_sequence_multires(mrh, orc):
