@@ -174,7 +174,7 @@ def test_room_ragged_frame_sizes(mrh, orc, size):
 def test_room_full_size_first_frames(mrh, orc):
     """640x480 at the full configuration, first 3 frames; then the benchmark's query launch (1M
     points near the surfaces, the same query pose) on that map, sampled outputs against the
-    oracle one by one."""
+    oracle one by one, and its adjoint over all 1M points against the oracle's."""
     announce("room 640x480 x3 frames full config")
     from workloads import surface_query_points
 
@@ -207,6 +207,18 @@ def test_room_full_size_first_frames(mrh, orc):
     ok = gv & ov & ~near
     assert ok.sum() > 1000
     np.testing.assert_allclose(sdf.cpu().numpy()[idx][ok], osdf[ok], atol=1e-5, rtol=0)
+    announce("room full config: 1M-point query adjoint against the oracle's, every point")
+    # incoming gradient 1 as in the benchmark, 0 next to excused blocks so that both sides leave
+    # them out of the pose gradient too
+    kb = np.floor((pts.astype(np.float64) + T[:3, 3]) / B).astype(np.int64)
+    code = lambda k: ((k[..., 0] + (1 << 20)) << 42) | ((k[..., 1] + (1 << 20)) << 21) | (k[..., 2] + (1 << 20))
+    hood = np.array([(a + dx, b + dy, c + dz) for a, b, c in ex for dx in (-1, 0, 1) for dy in (-1, 0, 1)
+                     for dz in (-1, 0, 1)], dtype=np.int64).reshape(-1, 3)
+    gs = np.where(np.isin(code(kb), code(hood)), 0.0, 1.0).astype(np.float32)
+    gp, gpose = g.query_backward(_dev(pts), _dev(gs), T=T)
+    ogp, ogpose = o.query_backward(pts, gs.astype(np.float64), T=T)
+    np.testing.assert_allclose(gp.cpu().numpy(), ogp, atol=2e-3, rtol=1e-4)
+    np.testing.assert_allclose(gpose, ogpose, rtol=1e-4, atol=1e-6 * np.abs(ogpose).max())
 
 
 def test_street_sequence_multires(mrh, orc):
