@@ -123,3 +123,60 @@ def test_batch_steps_of_one_frame_kind(mrh, graph):
     for i, c in enumerate(cfgs):
         maps[i].sync()
         _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in steps]))
+
+
+def _device_sorted(m):
+    """Block codes, levels and voxel planes of a map on the device, blocks in key order (the voxels
+    of each block in their stored order)."""
+    e = m.extract()
+    k = e["keys"].to(torch.int64)
+    code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
+    order = torch.argsort(code)
+    offs = e["offsets"]
+    lens = (offs[1:] - offs[:-1])[order]
+    starts = offs[:-1][order]
+    first = torch.cumsum(lens, 0) - lens
+    idx = torch.repeat_interleave(starts - first, lens) + torch.arange(int(lens.sum()), device=lens.device)
+    return code[order], e["levels"][order], e["D"][idx], e["W"][idx], e["S2"][idx]
+
+
+def test_batch_full_size_streams(mrh):
+    """The benchmark's 16 streams (8 RGB-D 320x240 .. 640x480 rooms, 8 LiDAR 32x1024 .. 64x2048
+    streets, the same map configurations), two launches of the batched FP32 graph path: every map
+    equals the same frames fused map by map, bit for bit."""
+    from bench import LIDAR_STREAMS, RGBD_STREAMS
+
+    announce("batch of the 16 full-size benchmark streams, 2 launches, FP32 graph")
+    L = 2
+    streams = []
+    for i, (w, h) in enumerate(RGBD_STREAMS):
+        d, cam, P, _ = room_sequence(width=w, height=h, f=525.0 * w / 640.0, frames=range(L), scene_seed=100 + i,
+                                     noise_seed=200 + i)
+        streams.append(([("depth", _dev(d[k]), cam.K, P[k]) for k in range(L)],
+                        dict(configs.ROOM, max_blocks=1 << 17, hash_slots=1 << 18)))
+    for i, (r, a) in enumerate(LIDAR_STREAMS):
+        p, P, _ = street_sequence(rings=r, azimuths=a, scans=range(L), scene_seed=108 + i, noise_seed=208 + i)
+        nb = 1 << 20
+        streams.append(([("points", _dev(p[k]), P[k]) for k in range(L)],
+                        dict(configs.STREET, max_blocks=nb, hash_slots=2 * nb, heap_blocks=[nb // 2, nb // 2, nb // 2, nb])))
+    maps = [mrh.Map(**c) for _, c in streams]
+    b = mrh.Batch(maps)
+    b.set_launch(512, 16, True)
+    for k in range(L):
+        b.integrate([fr[k] for fr, _ in streams])
+    b.close()
+    for m, (frs, c) in zip(maps, streams):
+        m.sync()
+        s = mrh.Map(**c)
+        for fr in frs:
+            if fr[0] == "depth":
+                s.integrate_depth(fr[1], fr[2], fr[3])
+            else:
+                s.integrate_points(fr[1], fr[2])
+        s.sync()
+        got, want = _device_sorted(m), _device_sorted(s)
+        assert got[0].numel() > 1000
+        for a, w in zip(got, want):
+            assert torch.equal(a, w)
+        s.close()
+        m.close()
