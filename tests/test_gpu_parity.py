@@ -259,6 +259,26 @@ def test_street_full_size_first_scans(mrh, orc):
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)))
 
 
+@pytest.mark.timeout(300)
+def test_street_full_sequence(mrh, orc):
+    """The benchmark's whole LiDAR workload: the 20 scans of 64 x 2048 points at the full street
+    configuration, per-scan counts and the final map (about 394k blocks, 900k merges)."""
+    announce("street 64x2048 x20 scans full config (benchmark sequence)")
+    pts, poses, _ = street_sequence(rings=64, azimuths=2048, scans=range(20))
+    g = mrh.Map(**configs.STREET)
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.STREET))
+    merges = 0
+    for k in range(pts.shape[0]):
+        g.integrate_points(_dev(pts[k]), poses[k])
+        last, _ = g.sync()
+        st = o.integrate_points(pts[k], poses[k])
+        assert last["valid_points"] == st["valid_points"], k
+        assert last["new_blocks"] == st["new_blocks"], k
+        assert last["observations"] == st["observations"], k
+        merges += sum(st["merges"])
+    print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)), "merges", merges)
+
+
 def test_street_band_only(mrh, orc):
     announce("street 8x256 band-only (no carving)")
     pts, poses, _ = street_sequence(n_scans=200, rings=8, azimuths=256, scans=[10, 11])
