@@ -6,9 +6,10 @@
  * check and the CPU-baseline leg of the benchmark load it.  It shares no code, header, table or
  * helper with the HIP library; the two are written independently from the same definitions.
  *
- * Parity status of each entry point (what pins it against something other than itself) is
- * listed beside it.  "parity unpinned" marks a function whose result the paper fixes only up to
- * a reading we chose, with invariants as the only check.
+ * What pins each entry point against something other than itself is listed beside it; every
+ * function here has such a pin (none is "parity unpinned").  The merge rule's readings (which
+ * voxels enter the block mean, one level per frame, pooling) are fixed by the closed-form
+ * threshold case and the conservation checks, not by a worked example from the paper.
  */
 #ifndef MRH_ORACLE_H
 #define MRH_ORACLE_H
@@ -43,11 +44,18 @@ typedef struct orc_stats {
 void* orc_create(const orc_config* cfg);
 void orc_destroy(void* map);
 
-/* RGB-D projective fusion of one z-depth frame (Eq. 2, 3, 5).  depth is row-major H x W. */
+/* RGB-D projective fusion of one z-depth frame (Eq. 2, 3, 5).  depth is row-major H x W.
+ * Pinned by: closed-form Eq. 2 values on a plane seen head-on by an identity camera and by a
+ * yawed, pitched, rolled and translated one (both forms; the updated-voxel set and the allocated
+ * blocks too); the sphere's zero crossing; a two-pass mean and variance of each voxel's
+ * observation history (Eq. 3, 5, 6); the closed-form merge threshold of two planes. */
 int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t height,
                         const double K[4], const double T_ws[16]);
 
-/* LiDAR ray fusion of one scan of n sensor-frame points (Eq. 1, 3, 5). */
+/* LiDAR ray fusion of one scan of n sensor-frame points (Eq. 1, 3, 5).
+ * Pinned by: the exact voxel column of an axis-aligned beam holding clip(Zp - z); point-order
+ * independence; free space merging to the coarsest level at exactly +tau; exact cell sets of the
+ * traversals (below). */
 int orc_integrate_points(void* map, const float* xyz, int64_t n, const double T_ws[16]);
 
 void orc_last_stats(const void* map, orc_stats* out);
@@ -65,12 +73,16 @@ void orc_extract(const void* map, int32_t* keys, uint8_t* levels, int64_t* offse
 int64_t orc_near_threshold(const void* map, int32_t* keys, int64_t* frames, double* margins,
                            int64_t cap);
 
-/* Trilinear SDF query (Sec. 3.4): T may be NULL (identity).  strict = 1 requires all 8 corners. */
+/* Trilinear SDF query (Sec. 3.4): T may be NULL (identity).  strict = 1 requires all 8 corners.
+ * Pinned by: exact reproduction of a linear field on one level; the closed-form blend across a
+ * boundary between two levels (corner values at their containing voxels' centres); the query
+ * pose; axis finite differences of the returned gradient. */
 void orc_query(const void* map, const float* pts, int64_t n, const double* T, int32_t strict,
                double* sdf, uint8_t* valid, double* grad_world);
 
 /* Adjoint of orc_query: grad_pts = dL/dp (n x 3), grad_pose = dL/dxi for a left perturbation
- * xi = (rho, phi) of T (6 values). */
+ * xi = (rho, phi) of T (6 values).  Pinned by finite differences of the pose perturbation and the
+ * chain rule through R. */
 void orc_query_backward(const void* map, const float* pts, int64_t n, const double* T,
                         int32_t strict, const double* grad_sdf, double* grad_pts,
                         double grad_pose[6]);
@@ -80,7 +92,8 @@ void orc_query_backward(const void* map, const float* pts, int64_t n, const doub
  * it is here to write the stored hash vectors the library's hash is checked against. */
 uint32_t orc_eq4_hash(int32_t x, int32_t y, int32_t z, uint64_t n_hash);
 
-/* The traversals, exposed for brute-force pins.  Return the number of cells written (<= cap). */
+/* The traversals, exposed for brute-force pins.  Return the number of cells written (<= cap).
+ * Pinned by the exact (rational-arithmetic) set of cells each segment meets. */
 int64_t orc_block_dda(const double a[3], const double e[3], double inv_cell, int64_t* cells,
                       int64_t cap);
 int64_t orc_voxel_dda(const double a[3], const double e[3], const int32_t block[3], double block_edge,

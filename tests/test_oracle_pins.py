@@ -152,6 +152,77 @@ def test_plane_closed_form(orc, form):
     assert not np.any(upd & behind)
 
 
+def _rot(yaw, pitch, roll):
+    """Rotation matrix Rz(yaw) Ry(pitch) Rx(roll) (angles in degrees)."""
+    a, b, c = np.deg2rad([yaw, pitch, roll])
+    Rz = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]])
+    Ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(c), -np.sin(c)], [0, np.sin(c), np.cos(c)]])
+    return Rz @ Ry @ Rx
+
+
+@pytest.mark.parametrize("form", ["range", "zdiff"])
+def test_rotated_camera_plane_closed_form(orc, form):
+    """Eq. 2 under a yawed, pitched, rolled and translated camera.  The world plane that the camera
+    sees head-on (normal R e_z) has the same constant z-depth Z0 at every pixel whatever the pose,
+    so the depth image is known exactly and the fused map has a closed form in the voxel's sensor
+    coordinates x = R^T (c - t): D = clip(||x|| (Z0 / x_z - 1)) (range form) or clip(Z0 - x_z)
+    (z-difference form), W = 1, S2 = 0.  Which voxels are updated is also fixed: those that project
+    inside the image (pixel floor(u + 1/2), floor(v + 1/2)) and lie no more than tau behind the
+    plane.  Allocation is checked against the world points of the pixels (each pixel's block is
+    allocated) and against the plane (no allocated block lies farther than tau from it).  A pose
+    applied transposed, in either direction, fails these checks."""
+    nu, tau = 0.02, 0.06
+    B = 8 * nu
+    Z0 = float(np.float32(1.3))
+    depth, cam, _ = plane_frame(Z0, 64, 48, 50.0)
+    T = np.eye(4)
+    R = _rot(25.0, -15.0, 10.0)
+    T[:3, :3] = R
+    T[:3, 3] = [0.31, -0.23, 0.47]
+    t = T[:3, 3]
+    m = orc.OracleMap(nu, tau=tau, max_depth=5.0, form=form)
+    st = m.integrate_depth(depth, cam.K, T)
+    ext = m.extract()
+    assert st["valid_points"] == 64 * 48
+
+    # allocation: the block of every pixel's world point is present ...
+    keys = set(map(tuple, ext.keys.tolist()))
+    rays = cam.rays()
+    pw = (rays * Z0).reshape(-1, 3) @ R.T + t
+    for b in np.floor(pw / B).astype(np.int64).tolist():
+        assert tuple(b) in keys
+    # ... and every allocated block meets the slab of points within tau of the world plane
+    nw = R[:, 2]
+    cplane = Z0 + float(nw @ t)
+    corners = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], np.float64)
+    box = (ext.keys[:, None, :] + corners[None]) * B
+    s = box @ nw - cplane
+    assert np.all(s.min(axis=1) <= tau + 1e-9) and np.all(s.max(axis=1) >= -tau - 1e-9)
+
+    # values and the set of updated voxels
+    c = _centres(ext, nu, B)
+    x = (c - t) @ R
+    upd = ext.W > 0
+    assert upd.sum() == st["observations"] > 1000
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = cam.fx * (x[:, 0] / x[:, 2]) + cam.cx
+        v = cam.fy * (x[:, 1] / x[:, 2]) + cam.cy
+        if form == "range":
+            raw = np.linalg.norm(x, axis=1) * (Z0 / x[:, 2] - 1.0)
+        else:
+            raw = Z0 - x[:, 2]
+    front = x[:, 2] > 0
+    inside = front & (u >= -0.5 + 1e-6) & (u < cam.width - 0.5 - 1e-6) & (v >= -0.5 + 1e-6) & (v < cam.height - 0.5 - 1e-6)
+    outside = ~front | (u < -0.5 - 1e-6) | (u >= cam.width - 0.5 + 1e-6) | (v < -0.5 - 1e-6) | (v >= cam.height - 0.5 + 1e-6)
+    want = inside & (raw >= -tau + 1e-9)
+    wont = outside | (front & (raw < -tau - 1e-9))
+    assert want.sum() > 1000
+    assert np.all(upd[want]) and not np.any(upd[wont])
+    np.testing.assert_allclose(ext.D[upd], np.minimum(raw[upd], tau), rtol=0, atol=1e-12)
+    assert np.all(ext.W[upd] == 1) and np.all(ext.S2 == 0)
+
+
 def test_sphere_plane_truncation_and_zero_crossing(orc):
     """One noise-free frame of the sphere-and-plane scene: |D| <= tau, W = 1, S2 = 0 and the
     zero crossing on the optical axis sits on the sphere's front at z = 2.0 m."""
@@ -415,6 +486,86 @@ def test_trilinear_reproduces_linear_field(orc):
     z = pts[valid, 2].astype(np.float64)
     np.testing.assert_allclose(sdf[valid], Z0 - z, atol=1e-12)
     np.testing.assert_allclose(grad[valid], np.tile([0.0, 0.0, -1.0], (valid.sum(), 1)), atol=1e-9)
+
+
+def test_trilinear_across_levels_closed_form(orc):
+    """Multi-resolution interpolation (Sec. 3.4, renormalised trilinear reading): the point's own
+    block fixes the lattice, and each of the 8 lattice corners takes the TSDF of the voxel, at
+    whatever level, whose half-open cell holds it.  Pinned on a map with two levels side by side:
+    a noise-free fronto-parallel plane (z-difference form, so every observation is Z0 - z of the
+    voxel centre, a linear field) seen twice by camera A, then once by camera B shifted along x.
+    After A's two frames every observed voxel holds two equal observations (variance 0), so A's
+    blocks merge one level; pooling a linear field over 8 children of equal weight gives the field
+    at the coarse centre.  B's frame adds the coarse centre's own value to those blocks and
+    allocates fine blocks where A never looked.  So every corner value is Z0 minus the z of its
+    containing voxel's centre, and a query equals the trilinear blend of those values.  Only
+    corners whose voxel is known to hold exactly that value are used (a fine voxel observed at
+    least once; a coarse voxel whose 8 children were each seen twice by A, or that A never saw and
+    B saw once), and the test needs queries whose corners span both levels, which is where
+    indexing a corner's block on the wrong level's lattice fails."""
+    nu, tau = 0.02, 0.3
+    B = 8 * nu
+    Z0 = float(np.float32(1.5))
+    depth, cam, T0 = plane_frame(Z0, 96, 72, 60.0)
+    T1 = np.eye(4)
+    T1[0, 3] = 0.5
+    m = orc.OracleMap(nu, levels=2, tau=tau, max_depth=5.0, form="zdiff", var_thr=1e-8, min_obs=2)
+    for Tk in (T0, T0, T1):
+        m.integrate_depth(depth, cam.K, Tk)
+    ext = m.extract()
+    assert set(np.unique(ext.levels).tolist()) == {0, 1}
+    idx = {tuple(k): i for i, k in enumerate(ext.keys.tolist())}
+
+    rng = np.random.default_rng(21)
+    n = 20000
+    # half of the points near A's right-hand field edge, where B's fine blocks meet A's coarse ones
+    xs = np.concatenate([rng.uniform(-1.1, 1.6, n // 2), rng.uniform(0.8, 1.6, n - n // 2)])
+    pts = np.stack([xs, rng.uniform(-0.6, 0.6, n), rng.uniform(Z0 - 0.12, Z0 + 0.12, n)],
+                   axis=1).astype(np.float32)
+    sdf, valid, _ = m.query(pts, strict=True)
+
+    def corner_value(P):
+        """(value, known) of the voxel holding lattice point P under the half-open convention."""
+        cb = np.floor(P / B).astype(np.int64)
+        i = idx.get(tuple(cb.tolist()))
+        if i is None:
+            return None, False
+        lv = int(ext.levels[i])
+        mm, nu_l = 8 >> lv, nu * (1 << lv)
+        loc = np.floor((P - cb * B) / nu_l + 1e-9).astype(np.int64)
+        v = int(ext.offsets[i] + loc[0] + mm * (loc[1] + mm * loc[2]))
+        zc = cb[2] * B + (loc[2] + 0.5) * nu_l
+        w = int(ext.W[v])
+        known = (w >= 1) if lv == 0 else (w in (1, 16, 17))
+        return Z0 - zc, known
+
+    checked = mixed = 0
+    for p, s, ok in zip(pts.astype(np.float64), sdf, valid):
+        hb = idx.get(tuple(np.floor(p / B).astype(np.int64).tolist()))
+        if hb is None:
+            continue
+        lv = int(ext.levels[hb])
+        nu_l = nu * (1 << lv)
+        g = p / nu_l - 0.5
+        i0 = np.floor(g)
+        f = g - i0
+        want, lvls, usable = 0.0, set(), True
+        for c in range(8):
+            dl = np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1])
+            val, known = corner_value((i0 + dl + 0.5) * nu_l)
+            if not known:
+                usable = False
+                break
+            w = np.prod(np.where(dl == 1, f, 1.0 - f))
+            want += w * val
+            lvls.add(int(ext.levels[idx[tuple(np.floor((i0 + dl + 0.5) * nu_l / B).astype(np.int64).tolist())]]))
+        if not usable:
+            continue
+        assert ok
+        assert abs(s - want) < 1e-12, (p, s, want)
+        checked += 1
+        mixed += len(lvls) > 1
+    assert checked > 5000 and mixed > 300, (checked, mixed)
 
 
 def test_query_pose_is_applied(orc):
