@@ -35,6 +35,18 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "room_integrate_traffic.json")
 
 
+def cpu_model():
+    """The host CPU's model name (what lscpu prints), for the CPU-baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_hash():
     csrc = os.path.join(ROOT, "paper_2511_21459_amd", "csrc")
     h = hashlib.sha256()
@@ -98,23 +110,26 @@ def timed(fn, steps, torch):
 
 
 def map_arrays(m):
-    """(block codes, levels, offsets, D, W) of a GPU map as numpy, blocks in table order."""
+    """(block codes, levels, offsets, D, W, S2) of a GPU map as numpy, blocks in table order."""
     import numpy as np
 
     e = m.extract()
     k = e["keys"].cpu().numpy().astype(np.int64)
     code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
     return (code, e["levels"].cpu().numpy(), e["offsets"].cpu().numpy(), e["D"].cpu().numpy().astype(np.float64),
-            e["W"].cpu().numpy().view(np.uint32))
+            e["W"].cpu().numpy().view(np.uint32), e["S2"].cpu().numpy().astype(np.float64))
 
 
-def compare_arrays(ref, got, flips=False):
+def compare_arrays(ref, got, flips=False, tau=None):
     """max / RMS |dD| over voxels observed in both maps, in blocks present in both at the same level;
-    optionally the sign flips on the reference's zero crossing (voxels with a 6-neighbour of the
-    opposite reference sign inside the block, sign(0) = +, whose sign in `got` differs)."""
+    the count of voxels of those blocks whose weights differ; with tau, the count of observed voxels
+    whose |dS2| exceeds the FP32 accumulation bound 1e-5 |S2| + W (2 tau)^2 2^-20 (each of the W
+    updates adds a term of magnitude at most (2 tau)^2, rounded at FP32 precision); optionally the
+    sign flips on the reference's zero crossing (voxels with a 6-neighbour of the opposite reference
+    sign inside the block, sign(0) = +, whose sign in `got` differs)."""
     import numpy as np
 
-    (ca, la, oa, Da, Wa), (cb, lb, ob, Db, Wb) = ref, got
+    (ca, la, oa, Da, Wa, Sa), (cb, lb, ob, Db, Wb, Sb) = ref, got
     common, ia, ib = np.intersect1d(ca, cb, return_indices=True)
     same = la[ia] == lb[ib]
     ia, ib = ia[same], ib[same]
@@ -125,7 +140,13 @@ def compare_arrays(ref, got, flips=False):
     out = {"blocks_compared": int(len(ia)), "blocks_level_differs": int((~same).sum()),
            "blocks_only_in_one": int(len(ca) + len(cb) - 2 * len(common)),
            "max_abs_dD_m": float(d.max()) if d.size else 0.0,
-           "rms_dD_m": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
+           "rms_dD_m": float(np.sqrt(np.mean(d * d))) if d.size else 0.0,
+           "voxels_compared": int(len(sa)), "w_mismatch": int(np.count_nonzero(Wa[sa] != Wb[sb]))}
+    if tau is not None:
+        ds2 = np.abs(Sa[sa] - Sb[sb])[obs]
+        bound = 1e-5 * np.abs(Sa[sa][obs]) + Wa[sa][obs].astype(np.float64) * (2 * tau) ** 2 * 2.0 ** -20
+        out["s2_over_fp32_bound"] = int(np.count_nonzero(ds2 > bound))
+        out["max_abs_dS2_m2"] = float(ds2.max()) if ds2.size else 0.0
     if flips:
         nf = nc = 0
         for i, j in zip(ia, ib):
@@ -523,6 +544,7 @@ def main():
             pts += o.integrate_depth(room["depths"][k], room["cam"].K, room["poses"][k])["valid_points"]
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(pts / dt / 1e6, 4), "unit": "M points/s", "cores": 1,
+                                  "cpu_model": cpu_model(),
                                   "kind": "oracle",
                                   "sample": f"first {n} of the {args.frames} frames, FP64 oracle, one thread "
                                             f"({dt:.1f} s)"}
@@ -531,9 +553,10 @@ def main():
             ex = o.extract()
             k = ex.keys.astype(np.int64)
             code = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
-            ref = (code, ex.levels, ex.offsets, ex.D, ex.W)
+            ref = (code, ex.levels, ex.offsets, ex.D, ex.W, ex.S2)
             result["cpu_baseline"]["gpu_vs_oracle"] = {
-                st: compare_arrays(ref, arr, flips=True) for st, arr in room["arrays"].items()}
+                st: compare_arrays(ref, arr, flips=True, tau=configs.ROOM["tau"])
+                for st, arr in room["arrays"].items()}
         if not args.no_extras:
             ns = min(args.cpu_scans, street["n"])
             o = oracle.OracleMap(**configs.oracle_kwargs(configs.STREET))
@@ -543,7 +566,8 @@ def main():
                 pts += o.integrate_points(street["pts"][k], street["poses"][k])["valid_points"]
             dt = time.perf_counter() - t0
             result["street"]["cpu_baseline"] = {
-                "value": round(pts / dt / 1e6, 4), "unit": "M points/s", "cores": 1, "kind": "oracle",
+                "value": round(pts / dt / 1e6, 4), "unit": "M points/s", "cores": 1, "cpu_model": cpu_model(),
+                "kind": "oracle",
                 "sample": f"first {ns} of the {street['n']} scans, FP64 oracle, one thread ({dt:.1f} s)"}
     print(json.dumps(result), flush=True)
 

@@ -51,8 +51,12 @@ enum {
 enum {
     MRH_STORE_F32 = 0,  /* D: float metres, S2: float m^2                      | W: uint32 (12 B) */
     MRH_STORE_F16 = 1,  /* D: half of D / tau, variance: half of S2/(W tau^2)  | W: uint16, saturating (6 B) */
-    MRH_STORE_BF16 = 2  /* D: bfloat16 of D / tau, variance: half, as for F16  | W: half (6 B) */
+    MRH_STORE_BF16 = 2  /* D: bfloat16 of D / tau, variance: half, as for F16  | W: half, saturating (6 B) */
 };
+/* Weight ranges of the 16-bit formats: the uint16 weight is exact up to 65535 and saturates there;
+ * the half weight is exact up to 2048, rounds to the nearest half above it (so one more observation
+ * of a voxel with W >= 2048 may leave the stored W unchanged) and saturates at 65504.  A saturated
+ * weight keeps averaging new observations as if W stayed at the cap. */
 
 typedef struct mrh_config {
     double voxel;          /* finest voxel edge nu_0 (m); every block is 8 nu_0 wide (Sec. 3.2) */
@@ -229,9 +233,10 @@ typedef struct mrh_frame {
 
 typedef struct mrh_batch mrh_batch;
 
-/* Group n_maps maps (same device, same storage format) into a batch.  The batch enqueues on
- * maps[0]'s stream; the maps must not be used on other streams while a batched call runs.  The
- * batch keeps the map pointers (the maps must outlive it).  Errors: MRH_ERR_INVALID_ARG. */
+/* Group n_maps maps (same device, same storage format, same stream) into a batch.  The batch
+ * enqueues on that stream.  The batch keeps the map pointers (the maps must outlive it).
+ * Errors: MRH_ERR_INVALID_ARG (NULL or repeated maps, n_maps outside [1, 64], maps on different
+ * devices or streams or with different storage formats), MRH_ERR_HIP. */
 mrh_status mrh_batch_create(mrh_map* const* maps, int32_t n_maps, mrh_batch** out);
 void mrh_batch_destroy(mrh_batch* batch);
 

@@ -3,7 +3,7 @@
 //
 //   MRH_STORE_F32   D float (m)             W uint32          S2 float (m^2)          12 B / voxel
 //   MRH_STORE_F16   D half of D / tau       W uint16 (satur.) V half of S2 / (W tau^2)  6 B / voxel
-//   MRH_STORE_BF16  D bfloat16 of D / tau   W half            V half of S2 / (W tau^2)  6 B / voxel
+//   MRH_STORE_BF16  D bfloat16 of D / tau   W half (satur.)   V half of S2 / (W tau^2)  6 B / voxel
 //
 // The 16-bit formats keep the per-voxel variance sigma^2 = S2 / W normalised by tau^2 rather than
 // S2 itself: sigma^2 / tau^2 stays in [0, 4] whatever the weight, so it neither overflows half
@@ -91,8 +91,14 @@ struct Store16 {
     __device__ static inline uint32_t decW(uint16_t b) {
         return ST == MRH_STORE_F16 ? (uint32_t)b : (uint32_t)f16_to_f32(b);
     }
+    // u16 saturates at 65535; the half weight saturates at 65504, the largest finite half (a larger
+    // W would round to infinity, whose conversion back to an integer is undefined).  A half weight
+    // is exact up to 2048; above that it rounds to the nearest representable value (spacing 2 up
+    // to 4096, 4 up to 8192, ...), so a single +1 observation of a voxel with W >= 2048 can leave
+    // the stored weight unchanged while D and S2 still move.
     __device__ static inline uint16_t encW(uint32_t W) {
-        return ST == MRH_STORE_F16 ? (uint16_t)(W < 65535u ? W : 65535u) : f32_to_f16((float)W);
+        return ST == MRH_STORE_F16 ? (uint16_t)(W < 65535u ? W : 65535u)
+                                   : f32_to_f16((float)(W < 65504u ? W : 65504u));
     }
     __device__ static inline float decS2(const DevMap& m, uint16_t v, uint32_t W) {
         return f16_to_f32(v) * (float)W * m.tau2_f;

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity_util import announce, gpu_sorted
+from parity_util import announce, compare_maps, excused_keys, gpu_sorted
 from workloads import configs, room_sequence, sphere_plane_frame, street_sequence
 
 pytestmark = pytest.mark.gpu
@@ -22,8 +22,10 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _streams():
-    """Two RGB-D rooms of different sizes, one sphere-plane, two LiDAR streets of different sizes."""
+def _streams(host=False):
+    """Two RGB-D rooms of different sizes, one sphere-plane, two LiDAR streets of different sizes.
+    With host=True the frames hold the numpy arrays (for the oracle) instead of device tensors."""
+    dev = (lambda a: a) if host else _dev
     r1 = room_sequence(width=320, height=240, f=262.5, frames=[0, 3, 6], scene_seed=101, noise_seed=201)
     r2 = room_sequence(width=416, height=312, f=341.25, frames=[0, 3, 6], scene_seed=102, noise_seed=202)
     sp = sphere_plane_frame(seed=3)
@@ -34,11 +36,11 @@ def _streams():
     cfgs = [room_cfg, room_cfg, configs.SPHERE_PLANE, street_cfg, street_cfg]
     frames = []
     for k in range(3):
-        fr = [("depth", _dev(r1[0][k]), r1[1].K, r1[2][k]),
-              ("depth", _dev(r2[0][k]), r2[1].K, r2[2][k]),
-              ("depth", _dev(sp[0]), sp[1].K, sp[2]) if k != 1 else None,
-              ("points", _dev(s1[0][k]), s1[1][k]),
-              ("points", _dev(s2[0][k]), s2[1][k])]
+        fr = [("depth", dev(r1[0][k]), r1[1].K, r1[2][k]),
+              ("depth", dev(r2[0][k]), r2[1].K, r2[2][k]),
+              ("depth", dev(sp[0]), sp[1].K, sp[2]) if k != 1 else None,
+              ("points", dev(s1[0][k]), s1[1][k]),
+              ("points", dev(s2[0][k]), s2[1][k])]
         frames.append(fr)
     return cfgs, frames
 
@@ -76,6 +78,52 @@ def test_batch_equals_single_maps(mrh, graph):
     for i, c in enumerate(cfgs):
         maps[i].sync()
         _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames]))
+
+
+def _oracle_map(orc, cfg, frames_of_map):
+    o = orc.OracleMap(**configs.oracle_kwargs(cfg))
+    for fr in frames_of_map:
+        if fr is None:
+            continue
+        if fr[0] == "depth":
+            o.integrate_depth(fr[1], fr[2], fr[3])
+        else:
+            o.integrate_points(fr[1], fr[2])
+    return o
+
+
+def test_batch_maps_match_oracle(mrh, orc):
+    """Every map of a batched run (graph replay, 3 calls over 3 RGB-D and 2 LiDAR maps of uneven
+    sizes, one call without a sphere-plane frame) against the FP64 oracle fed the same frames: bit-exact
+    block keys, equal levels (merge decisions at the threshold excused), W exact, |dD| <= 1e-5 m."""
+    announce("batch of 5 maps against the oracle")
+    cfgs, frames = _streams()
+    _, host = _streams(host=True)
+    maps = [mrh.Map(**c) for c in cfgs]
+    b = mrh.Batch(maps)
+    b.set_launch(512, 16, True)
+    for fr in frames:
+        b.integrate(fr)
+    for i, c in enumerate(cfgs):
+        maps[i].sync()
+        o = _oracle_map(orc, c, [fr[i] for fr in host])
+        rep = compare_maps(gpu_sorted(maps[i]), o.extract(), tol_d=1e-5, excused=excused_keys(o), tau=c["tau"])
+        print(i, rep)
+        assert rep["compared_blocks"] > 0
+
+
+def test_batch_rejects_maps_on_different_streams(mrh):
+    announce("batch of maps bound to different streams")
+    a = mrh.Map(**configs.SPHERE_PLANE)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b = mrh.Map(**configs.SPHERE_PLANE)
+    with pytest.raises(mrh.MrhError) as ei:
+        mrh.Batch([a, b])
+    assert ei.value.code == -1
+    torch.cuda.synchronize()
+    a.close()
+    b.close()
 
 
 def test_batch_f16_equals_single_f16(mrh):
@@ -140,25 +188,51 @@ def _device_sorted(m):
     return code[order], e["levels"][order], e["D"][idx], e["W"][idx], e["S2"][idx]
 
 
-def test_batch_full_size_streams(mrh):
-    """The benchmark's 16 streams (8 RGB-D 320x240 .. 640x480 rooms, 8 LiDAR 32x1024 .. 64x2048
-    streets, the same map configurations), two launches of the batched FP32 graph path: every map
-    equals the same frames fused map by map, bit for bit."""
+def _full_size_streams(L, host=False):
     from bench import LIDAR_STREAMS, RGBD_STREAMS
 
-    announce("batch of the 16 full-size benchmark streams, 2 launches, FP32 graph")
-    L = 2
+    dev = (lambda a: a) if host else _dev
     streams = []
     for i, (w, h) in enumerate(RGBD_STREAMS):
         d, cam, P, _ = room_sequence(width=w, height=h, f=525.0 * w / 640.0, frames=range(L), scene_seed=100 + i,
                                      noise_seed=200 + i)
-        streams.append(([("depth", _dev(d[k]), cam.K, P[k]) for k in range(L)],
+        streams.append(([("depth", dev(d[k]), cam.K, P[k]) for k in range(L)],
                         dict(configs.ROOM, max_blocks=1 << 17, hash_slots=1 << 18)))
     for i, (r, a) in enumerate(LIDAR_STREAMS):
         p, P, _ = street_sequence(rings=r, azimuths=a, scans=range(L), scene_seed=108 + i, noise_seed=208 + i)
         nb = 1 << 20
-        streams.append(([("points", _dev(p[k]), P[k]) for k in range(L)],
+        streams.append(([("points", dev(p[k]), P[k]) for k in range(L)],
                         dict(configs.STREET, max_blocks=nb, hash_slots=2 * nb, heap_blocks=[nb // 2, nb // 2, nb // 2, nb])))
+    return streams
+
+
+def test_batch_full_size_step_matches_oracle(mrh, orc):
+    """One batched FP32 graph step of the benchmark's 16 full-size streams (8 RGB-D rooms 320x240 ..
+    640x480, 8 LiDAR streets 32x1024 .. 64x2048): every map against the FP64 oracle."""
+    announce("batch of the 16 full-size benchmark streams, 1 launch, against the oracle")
+    streams = _full_size_streams(1)
+    host = _full_size_streams(1, host=True)
+    maps = [mrh.Map(**c) for _, c in streams]
+    b = mrh.Batch(maps)
+    b.set_launch(512, 16, True)
+    b.integrate([fr[0] for fr, _ in streams])
+    b.close()
+    for i, (m, (frs, c)) in enumerate(zip(maps, host)):
+        m.sync()
+        o = _oracle_map(orc, c, frs)
+        rep = compare_maps(gpu_sorted(m), o.extract(), tol_d=1e-5, excused=excused_keys(o), tau=c["tau"])
+        print(i, rep)
+        assert rep["compared_blocks"] > 100
+        m.close()
+
+
+def test_batch_full_size_streams(mrh):
+    """The benchmark's 16 streams (8 RGB-D 320x240 .. 640x480 rooms, 8 LiDAR 32x1024 .. 64x2048
+    streets, the same map configurations), two launches of the batched FP32 graph path: every map
+    equals the same frames fused map by map, bit for bit."""
+    announce("batch of the 16 full-size benchmark streams, 2 launches, FP32 graph")
+    L = 2
+    streams = _full_size_streams(L)
     maps = [mrh.Map(**c) for _, c in streams]
     b = mrh.Batch(maps)
     b.set_launch(512, 16, True)

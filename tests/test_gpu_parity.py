@@ -437,7 +437,7 @@ def test_empty_and_invalid_inputs(mrh):
     assert g.counts() == (0, 0)
 
 
-def test_capacity_errors(mrh):
+def test_capacity_errors(mrh, orc):
     announce("table / heap / block capacity errors")
     depth, cam, T = sphere_plane_frame(seed=0)
     d = _dev(depth)
@@ -453,12 +453,21 @@ def test_capacity_errors(mrh):
     assert ei.value.code == -4  # heap full
     nb, nv = h.counts()
     assert nv == 100 * 512  # blocks without storage report no voxels
-    t = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=1 << 15, hash_slots=1 << 16, max_probe=1))
+    # a probe limit of one slot: any two of the frame's keys sharing an Eq. 4 home slot make the
+    # second insert fail; the host evaluation of the hash shows such a pair exists
+    slots = 4096
+    o = orc.OracleMap(**configs.oracle_kwargs(configs.SPHERE_PLANE))
+    o.integrate_depth(depth, cam.K, T)
+    homes = [mrh.block_hash(int(x), int(y), int(z), slots) for x, y, z in o.extract().keys.tolist()]
+    collide = len(homes) - len(set(homes))
+    assert collide > 0
+    t = mrh.Map(**dict(configs.SPHERE_PLANE, max_blocks=2048, hash_slots=slots, max_probe=1))
     t.integrate_depth(d, cam.K, T)
-    try:
+    with pytest.raises(mrh.MrhError) as ei:
         t.sync()
-    except mrh.MrhError as e:
-        assert e.code == -3
+    assert ei.value.code == -3  # table full
+    _, tot = t.sync()  # the latch was cleared by the failing sync; totals still count the losses
+    assert tot["failed_inserts"] >= collide
 
 
 def test_reset_reuses_map(mrh, orc):

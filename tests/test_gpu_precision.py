@@ -105,7 +105,8 @@ def test_room_sequence_precision(mrh, orc, storage):
     rep = _compare(gs, ref, ex, cfg["tau"])
     rep32 = _compare(gs, g32s, ex, cfg["tau"])
     flips, cross = _zero_cross_flips(rep["same"], ref.D, ref.W, gs.D, ref.offsets, gs.offsets, ref.levels)
-    level_diff = int(np.sum(gs.levels != ref.levels))
+    differ = [tuple(k) for k in ref.keys[gs.levels != ref.levels].tolist()]
+    level_diff = len(differ)
     print(storage, "vs oracle", {k: v for k, v in rep.items() if k != "same"}, "vs fp32 gpu",
           {k: v for k, v in rep32.items() if k != "same"}, "flipped", flips, "of", cross,
           "level mismatches", level_diff, "excused", len(ex))
@@ -115,4 +116,7 @@ def test_room_sequence_precision(mrh, orc, storage):
     assert rep["max_abs_dD"] <= tau * ULP[storage] * 8
     assert rep["rms_dD"] <= tau * ULP[storage]
     assert flips <= max(2, 0.02 * cross)
-    assert level_diff <= len(ex)
+    # every block at a different level is one whose merge decision the oracle took within the
+    # 16-bit excusal margin of the threshold
+    stray = [k for k in differ if k not in ex]
+    assert not stray, f"{len(stray)} blocks at different levels outside the excused set, e.g. {stray[:5]}"
