@@ -128,6 +128,19 @@ mrh_status mrh_map_reset(mrh_map* map);
 mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
                                const double K[4], const double T_ws[16]);
 
+/* mrh_integrate_depth for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same two kernels and the same
+ * result, but the per-tile depth summary (4 bytes per 16 x 16 pixels) lives in a fixed device
+ * array of the library instead of a per-map buffer that grows with the frame, and the launch
+ * profiler is bypassed.  The call itself allocates nothing (no hipMalloc, hipFree or event creation;
+ * the map's own memory comes from mrh_map_create).  Limit: frames of at most 65536 tiles (e.g.
+ * 4096 x 4096 pixels); larger frames return MRH_ERR_INVALID_ARG with the reason in mrh_last_error.
+ * The array is shared by every call on one GPU and keeps the last call's contents (each call
+ * rewrites the tiles it reads before reading them): calls that overlap on one GPU, on different
+ * streams, race and must not be issued.  Other arguments and errors as mrh_integrate_depth. */
+mrh_status mrh_integrate_depth_noalloc(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                                       const double K[4], const double T_ws[16]);
+
 /* Fuse one LiDAR scan (Sec. 3.1 "3D Point Cloud", Eq. 1, Eq. 3, Eq. 5; Sec. 3.2.1).
  *   xyz_dev: device float32[n][3] points in the sensor frame; non-finite points and points with
  *            range outside [min_range, max_range] are skipped.  n may be 0.

@@ -107,6 +107,18 @@ class Map:
         self._check(_lib.load().mrh_integrate_depth(self._h, p, depth.shape[1], depth.shape[0], Kp, Tp),
                     "mrh_integrate_depth")
 
+    def integrate_depth_noalloc(self, depth: torch.Tensor, K, T_ws):
+        """integrate_depth through the entry point that allocates no device memory (the per-tile
+        depth summary sits in the library's fixed per-GPU array; frames of at most 65536 16 x 16
+        tiles; calls overlapping on one GPU race)."""
+        if depth.dim() != 2:
+            raise ValueError("depth must be [H, W]")
+        p = _dev(depth, torch.float32, name="depth")
+        Ka, Kp = _host_doubles(K, 4)
+        Ta, Tp = _host_doubles(T_ws, 16)
+        self._check(_lib.load().mrh_integrate_depth_noalloc(self._h, p, depth.shape[1], depth.shape[0], Kp, Tp),
+                    "mrh_integrate_depth_noalloc")
+
     def integrate_points(self, xyz: torch.Tensor, T_ws):
         """Fuse one LiDAR scan: float32 [N, 3] sensor-frame points on the GPU."""
         p = _dev(xyz, torch.float32, (3,), name="xyz")

@@ -30,6 +30,7 @@ EXPORTS = [
     "mrh_query_sdf_backward", "mrh_extract_blocks", "mrh_last_error", "mrh_profile_enable",
     "mrh_profile_collect", "mrh_batch_create", "mrh_batch_destroy", "mrh_batch_integrate", "mrh_batch_set_launch",
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
+    "mrh_integrate_depth_noalloc",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
@@ -102,6 +103,8 @@ def load():
     L.mrh_map_reset.argtypes = [P]
     L.mrh_integrate_depth.restype = i32
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_integrate_depth_noalloc.restype = i32
+    L.mrh_integrate_depth_noalloc.argtypes = [P, P, i32, i32, P, P]
     L.mrh_integrate_points.restype = i32
     L.mrh_integrate_points.argtypes = [P, P, i64, P]
     L.mrh_integrate_depth_sequence.restype = i32

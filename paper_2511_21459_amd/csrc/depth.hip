@@ -5,6 +5,7 @@
 // (update tasks over the per-level queues; workgroup 0 also runs the update-side hand-off).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "mrh_depth.h"
 
@@ -129,6 +130,69 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
         }
     });
     return check_hip(map, hipGetLastError(), "integrate_depth");
+}
+
+// ---- the variant that allocates nothing ------------------------------------------------------
+// The per-tile depth summary lives in a fixed device array instead of the map's growable buffer.
+// Each GPU holds its own copy for the life of the process; its address is looked up once per
+// device (the array's name is not a device address in host code).
+namespace mrh {
+constexpr size_t kScratchTiles = 65536;  // 16 x 16 pixel tiles: frames of up to 4096 x 4096 pixels
+constexpr int kScratchDevices = 64;
+}  // namespace mrh
+
+static __device__ __align__(256) float scratch[mrh::kScratchTiles];
+
+static float* g_scratch_ptr[mrh::kScratchDevices];
+static std::once_flag g_scratch_once[mrh::kScratchDevices];
+static hipError_t g_scratch_err[mrh::kScratchDevices];
+
+// Device address of `scratch` on `device`, resolved with that device current (once per device).
+static hipError_t scratch_address(int device, float** out) {
+    if (device < 0 || device >= mrh::kScratchDevices) return hipErrorInvalidDevice;
+    std::call_once(g_scratch_once[device], [device] {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess) g_scratch_ptr[device] = static_cast<float*>(p);
+        if (prev != device) (void)hipSetDevice(prev);
+        g_scratch_err[device] = e;
+    });
+    *out = g_scratch_ptr[device];
+    return g_scratch_err[device];
+}
+
+extern "C" mrh_status mrh_integrate_depth_noalloc(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                                                  const double K[4], const double T_ws[16]) {
+    if (!map || !depth_dev || !K || !T_ws || !depth_size_ok(width, height)) return MRH_ERR_INVALID_ARG;
+    const size_t tiles_need = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
+    if (tiles_need > kScratchTiles)
+        return set_error(map, MRH_ERR_INVALID_ARG, "frame of %d x %d pixels has %zu tiles; the no-allocation entry point "
+                         "takes at most %zu (4096 x 4096 pixels)", width, height, tiles_need, kScratchTiles);
+    DepthFrame f;
+    if (!make_depth_frame(map->cfg, depth_dev, width, height, K, T_ws, f))
+        return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose or intrinsics, or zero focal length");
+    float* tiles_dev = nullptr;
+    const mrh_status sa = check_hip(map, scratch_address(map->device, &tiles_dev), "scratch address");
+    if (sa != MRH_OK) return sa;
+    f.tiles_x = (width + 15) / 16;
+    f.tiles_y = (height + 15) / 16;
+    f.tile_max = tiles_dev;
+    f.parity = (int32_t)(map->frames & 1u);
+    map->frames += 1;
+    const uint32_t tiles_x = (uint32_t)f.tiles_x, tiles = (uint32_t)tiles_need;
+    const uint32_t cull_groups = 128;
+    // launched directly: the launch profiler's events are created on demand, which allocates
+    hipLaunchKernelGGL(k_alloc_depth, dim3(tiles + cull_groups), dim3(256), 0, map->stream, map->dmd, f, tiles_x, tiles);
+    const dim3 g(1024), b(256);
+    switch (map->cfg.storage) {
+        case MRH_STORE_F16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F16>, g, b, 0, map->stream, map->dmd, f); break;
+        case MRH_STORE_BF16: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_BF16>, g, b, 0, map->stream, map->dmd, f); break;
+        default: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd, f);
+    }
+    return check_hip(map, hipGetLastError(), "integrate_depth_noalloc");
 }
 
 extern "C" mrh_status mrh_integrate_depth_sequence(mrh_map* map, const float* depth_dev, int32_t n_frames, int32_t width,
