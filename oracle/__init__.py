@@ -60,6 +60,10 @@ def lib():
         L.orc_voxel_dda.restype = ctypes.c_int64
         L.orc_voxel_dda.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P,
                                     ctypes.c_int64]
+        L.orc_mesh.restype = ctypes.c_int64
+        L.orc_mesh.argtypes = [P, ctypes.c_double, P, ctypes.c_int64, P, P, P, P, ctypes.c_int64]
+        L.orc_set_block.restype = ctypes.c_int
+        L.orc_set_block.argtypes = [P, P, ctypes.c_int32, P, P]
         _lib = L
     return _lib
 
@@ -166,6 +170,21 @@ class OracleMap:
                         _p(valid), _p(grad))
         return sdf, valid.astype(bool), grad
 
+    def mesh(self, collapse: float = 0.0, only_keys=None) -> Mesh:
+        """Multi-resolution Marching Cubes (Sec. 3.4) of the whole map or of the listed blocks."""
+        return _mesh(self._h, collapse, only_keys)
+
+    def set_block(self, key, level: int, D: np.ndarray, W: np.ndarray):
+        """Test hook: put a level-`level` block with the given voxels (x fastest) at `key`."""
+        k = np.ascontiguousarray(key, dtype=np.int32).reshape(3)
+        D = np.ascontiguousarray(D, dtype=np.float64).ravel()
+        W = np.ascontiguousarray(W, dtype=np.uint32).ravel()
+        m = 8 >> int(level)
+        if D.size != m ** 3 or W.size != m ** 3:
+            raise ValueError("block arrays must hold (8 >> level)^3 voxels")
+        if lib().orc_set_block(self._h, _p(k), int(level), _p(D), _p(W)) != 0:
+            raise ValueError("level outside the map's levels")
+
     def query_backward(self, pts: np.ndarray, grad_sdf: np.ndarray, T=None, strict=False):
         pts = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, 3)
         n = pts.shape[0]
@@ -176,6 +195,28 @@ class OracleMap:
         lib().orc_query_backward(self._h, _p(pts), n, None if Tp is None else _p(Tp), int(strict),
                                  _p(g), _p(gp), _p(gpose))
         return gp, gpose
+
+
+@dataclass
+class Mesh:
+    verts: np.ndarray   # float64[t, 3, 3] world metres, counter-clockwise seen from outside
+    blocks: np.ndarray  # int32[t, 3] block key of the triangle's cube
+    codes: np.ndarray   # uint32[t] level << 30 | voxel << 15 | v0 << 10 | v1 << 5 | v2
+    near: np.ndarray    # bool[t] a decision of the cube lay within rounding of its threshold
+
+
+def _mesh(h, collapse: float, only_keys=None) -> Mesh:
+    ok = None if only_keys is None else np.ascontiguousarray(only_keys, dtype=np.int32).reshape(-1, 3)
+    okp = None if ok is None else _p(ok)
+    nok = 0 if ok is None else ok.shape[0]
+    n = int(lib().orc_mesh(h, float(collapse), okp, nok, None, None, None, None, 0))
+    verts = np.zeros((n, 3, 3), np.float64)
+    blocks = np.zeros((n, 3), np.int32)
+    codes = np.zeros(n, np.uint32)
+    near = np.zeros(n, np.uint8)
+    if n:
+        lib().orc_mesh(h, float(collapse), okp, nok, _p(verts), _p(blocks), _p(codes), _p(near), n)
+    return Mesh(verts, blocks, codes, near.astype(bool))
 
 
 def eq4_hash(x: int, y: int, z: int, n_hash: int) -> int:

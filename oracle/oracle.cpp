@@ -387,6 +387,302 @@ QueryOut query_one(const Map& m, const double x[3], bool strict) {
     return q;
 }
 
+/*
+ * ---- Multi-resolution Marching Cubes (Sec. 3.4) ----------------------------------------------
+ *
+ * Positions are integers in units of half a finest voxel (nu_0 / 2): along one axis the centre of
+ * voxel i of a level-n block with coordinate b sits at 16 b + (2 i + 1) 2^n, and a block face at
+ * 16 b.  Every position the mesher evaluates is such an integer, so the cell indices and the
+ * trilinear weights below are exact.
+ *
+ * Cubes.  Each voxel (i, j, k) of a level-n block spans one cube from its own centre to the next
+ * lattice point along +x, +y and +z.  Inside the block that is the next voxel centre of the same
+ * level.  On the block's upper face along an axis the cube reaches the first voxel-centre plane of
+ * the face neighbour: when the neighbour is finer the coarse cube is truncated there, so that it
+ * ends where the finer block's own cubes begin (the transition rule of Sec. 3.4); when the
+ * neighbour is coarser the cube is stretched to its first centre plane, so that no gap opens
+ * between the two levels.  Without a face neighbour there is no cube.
+ *
+ * Corner values are the map's multi-resolution trilinear interpolant (the one of the query,
+ * Sec. 3.4) at the corner: the corner's own block fixes the lattice, the 8 surrounding lattice
+ * points take the TSDF of the voxel, at any level, containing them, absent or unobserved ones
+ * drop out and the weights are renormalised.  At a voxel centre this is the voxel's own D (valid
+ * iff W > 0).  A cube is meshed only when all 8 corner values are valid.
+ *
+ * Surface.  Corners with D < 0 are inside.  On each of the cube's 6 faces every edge whose two
+ * corners differ in sign carries a surface point; the points are joined in pairs by segments, one
+ * pair on a face with two such edges, two on a face with four (then each segment cuts off one
+ * outside corner, so the inside corners stay connected across the face).  Each segment is
+ * directed so that, with the face's outward normal N, N x (end - start) points to the outside
+ * corners.  The directed segments close into loops; each loop is fanned into triangles from its
+ * edge of lowest index, so every triangle's normal (right-hand rule) points to the outside.  A
+ * loop that passes through all four surface points of one face is fanned around the mean of its
+ * vertices instead (from a vertex, a triangle could lie flat on that face, on top of one of the
+ * neighbouring cube's); the k-th loop's centre has vertex id 20 + k.
+ *
+ * Vertex collapse.  An edge's surface point lies at t = v0 / (v0 - v1) from its lower corner.  When
+ * it is closer than collapse * nu_n (nu_n: the cube's voxel size) to a corner of the edge it is
+ * moved onto that corner; triangles with two vertices on one point are dropped.
+ *
+ * Numbering: corner c = x + 2 y + 4 z (x, y, z in {0, 1}); edge e lies along axis a = e / 4, its
+ * two other coordinates are bit 0 and bit 1 of e % 4 on the other axes in increasing order.
+ */
+struct MeshOut {
+    std::vector<double>* verts;
+    std::vector<int32_t>* blocks;
+    std::vector<uint32_t>* codes;
+    std::vector<uint8_t>* near;
+};
+
+int edge_axis(int e) { return e / 4; }
+
+/* the corners of edge e: low end c0, high end c1 */
+void edge_corners(int e, int& c0, int& c1) {
+    const int a = e / 4, r = e % 4;
+    int other[2], o = 0;
+    for (int k = 0; k < 3; ++k)
+        if (k != a) other[o++] = k;
+    c0 = ((r & 1) << other[0]) | (((r >> 1) & 1) << other[1]);
+    c1 = c0 | (1 << a);
+}
+
+/* Interpolant at an exact lattice position P (half-finest units); false when no corner counts. */
+bool lattice_value(const Map& m, const int64_t P[3], double& out) {
+    int64_t hb[3];
+    for (int k = 0; k < 3; ++k) hb[k] = floor_div(P[k], 16);
+    const Block* home = find(m, hb[0], hb[1], hb[2]);
+    if (!home) return false;
+    const int n = home->level;
+    const int64_t s = int64_t(2) << n, half = int64_t(1) << n;
+    int64_t i0[3];
+    double f[3];
+    for (int k = 0; k < 3; ++k) {
+        const int64_t q = P[k] - half; /* = (cell index + fraction) * s */
+        i0[k] = floor_div(q, s);
+        f[k] = (double)(q - i0[k] * s) / (double)s;
+    }
+    double wsum = 0.0, num = 0.0;
+    bool any = false;
+    for (int c = 0; c < 8; ++c) {
+        const int dl[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        const double w = (dl[0] ? f[0] : 1.0 - f[0]) * (dl[1] ? f[1] : 1.0 - f[1]) * (dl[2] ? f[2] : 1.0 - f[2]);
+        int64_t p2[3], cb[3];
+        for (int k = 0; k < 3; ++k) {
+            p2[k] = (i0[k] + dl[k]) * s + half;
+            cb[k] = floor_div(p2[k], 16);
+        }
+        const Block* blk = find(m, cb[0], cb[1], cb[2]);
+        if (!blk) continue;
+        const int n2 = blk->level, m2 = side(n2);
+        int idx[3];
+        for (int k = 0; k < 3; ++k) idx[k] = (int)((p2[k] - 16 * cb[k]) / (int64_t(2) << n2));
+        const int v = idx[0] + m2 * (idx[1] + m2 * idx[2]);
+        if (blk->W[v] == 0) continue;
+        wsum += w;
+        num += w * blk->D[v];
+        if (w > 0.0) any = true;
+    }
+    if (!any) return false;
+    out = num / wsum;
+    return true;
+}
+
+/* Mesh one block (key b); appends its triangles. */
+void mesh_block(const Map& m, const Key& b, const Block& blk, double collapse, MeshOut& o) {
+    const int n = blk.level, mside = side(n);
+    const int64_t half = int64_t(1) << n, s = int64_t(2) << n;
+    const double h = 0.5 * m.cfg.voxel; /* metres per lattice unit */
+    const double snap = collapse * m.nu[n];
+    int nb_level[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t q[3] = {b[0], b[1], b[2]};
+        q[a] += 1;
+        const Block* nb = find(m, q[0], q[1], q[2]);
+        nb_level[a] = nb ? nb->level : -1;
+    }
+    for (int k = 0; k < mside; ++k)
+        for (int j = 0; j < mside; ++j)
+            for (int i = 0; i < mside; ++i) {
+                const int idx[3] = {i, j, k};
+                int64_t lo[3], hi[3];
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = 16 * (int64_t)b[a] + (2 * idx[a] + 1) * half;
+                    if (idx[a] + 1 < mside) {
+                        hi[a] = lo[a] + s;
+                    } else if (nb_level[a] >= 0) {
+                        hi[a] = 16 * ((int64_t)b[a] + 1) + (int64_t(1) << nb_level[a]);
+                    } else {
+                        ok = false;
+                    }
+                }
+                if (!ok) continue;
+                double v[8];
+                int64_t P[8][3];
+                for (int c = 0; c < 8 && ok; ++c) {
+                    for (int a = 0; a < 3; ++a) P[c][a] = ((c >> a) & 1) ? hi[a] : lo[a];
+                    ok = lattice_value(m, P[c], v[c]);
+                }
+                if (!ok) continue;
+                bool near = false;
+                int inside = 0;
+                for (int c = 0; c < 8; ++c) {
+                    if (v[c] < 0.0) inside |= 1 << c;
+                    if (std::fabs(v[c]) < 1e-6) near = true;
+                }
+                if (inside == 0 || inside == 255) continue;
+                /* surface points of the crossing edges, with vertex collapse */
+                bool cross[12];
+                int vid[12];
+                double pos[12][3];
+                for (int e = 0; e < 12; ++e) {
+                    int c0, c1;
+                    edge_corners(e, c0, c1);
+                    cross[e] = ((inside >> c0) & 1) != ((inside >> c1) & 1);
+                    if (!cross[e]) continue;
+                    const int a = edge_axis(e);
+                    const double L = (double)(hi[a] - lo[a]) * h;
+                    const double t = v[c0] / (v[c0] - v[c1]);
+                    if (std::fabs(v[c0] - v[c1]) < 1e-3) near = true;
+                    const double d0 = t * L, d1 = (1.0 - t) * L;
+                    if (std::fabs(d0 - snap) < 1e-6 * m.nu[n] || std::fabs(d1 - snap) < 1e-6 * m.nu[n]) near = true;
+                    if (d0 < snap) {
+                        vid[e] = 12 + c0;
+                        for (int q = 0; q < 3; ++q) pos[e][q] = (double)P[c0][q] * h;
+                    } else if (d1 < snap) {
+                        vid[e] = 12 + c1;
+                        for (int q = 0; q < 3; ++q) pos[e][q] = (double)P[c1][q] * h;
+                    } else {
+                        vid[e] = e;
+                        for (int q = 0; q < 3; ++q)
+                            pos[e][q] = (double)P[c0][q] * h + t * ((double)P[c1][q] * h - (double)P[c0][q] * h);
+                    }
+                }
+                /* directed segments on the 6 faces */
+                int next[12];
+                for (int e = 0; e < 12; ++e) next[e] = -1;
+                for (int a = 0; a < 3; ++a)
+                    for (int sd = 0; sd < 2; ++sd) {
+                        /* the face's 4 edges: along the two other axes, with coordinate sd on axis a */
+                        int fe[4], nf = 0;
+                        for (int e = 0; e < 12; ++e) {
+                            if (edge_axis(e) == a) continue;
+                            int c0, c1;
+                            edge_corners(e, c0, c1);
+                            if (((c0 >> a) & 1) == sd) fe[nf++] = e;
+                        }
+                        int cut[4], nc = 0;
+                        for (int q = 0; q < 4; ++q)
+                            if (cross[fe[q]]) cut[nc++] = fe[q];
+                        if (nc == 0) continue;
+                        /* pairs of cut edges and, for each pair, an outside corner on its outside side */
+                        int pairs[2][2], outc[2], np = 0;
+                        if (nc == 2) {
+                            pairs[0][0] = cut[0], pairs[0][1] = cut[1];
+                            outc[0] = -1;
+                            for (int c = 0; c < 8; ++c)
+                                if (((c >> a) & 1) == sd && !((inside >> c) & 1)) outc[0] = c;
+                            np = 1;
+                        } else {
+                            /* each outside corner of the face is cut off with its two face edges */
+                            for (int c = 0; c < 8; ++c) {
+                                if (((c >> a) & 1) != sd || ((inside >> c) & 1)) continue;
+                                int q2 = 0;
+                                for (int q = 0; q < 4; ++q) {
+                                    int c0, c1;
+                                    edge_corners(cut[q], c0, c1);
+                                    if (c0 == c || c1 == c) pairs[np][q2++] = cut[q];
+                                }
+                                outc[np++] = c;
+                            }
+                        }
+                        const double N[3] = {a == 0 ? 2.0 * sd - 1.0 : 0.0, a == 1 ? 2.0 * sd - 1.0 : 0.0,
+                                             a == 2 ? 2.0 * sd - 1.0 : 0.0};
+                        for (int p = 0; p < np; ++p) {
+                            /* unit-cube midpoints of the two edges */
+                            double M[2][3];
+                            for (int q = 0; q < 2; ++q) {
+                                int c0, c1;
+                                edge_corners(pairs[p][q], c0, c1);
+                                for (int x = 0; x < 3; ++x) M[q][x] = 0.5 * (((c0 >> x) & 1) + ((c1 >> x) & 1));
+                            }
+                            const double d[3] = {M[1][0] - M[0][0], M[1][1] - M[0][1], M[1][2] - M[0][2]};
+                            const double cr[3] = {N[1] * d[2] - N[2] * d[1], N[2] * d[0] - N[0] * d[2],
+                                                  N[0] * d[1] - N[1] * d[0]};
+                            double dot = 0.0;
+                            for (int x = 0; x < 3; ++x)
+                                dot += cr[x] * ((double)((outc[p] >> x) & 1) - 0.5 * (M[0][x] + M[1][x]));
+                            if (dot > 0.0) next[pairs[p][0]] = pairs[p][1];
+                            else next[pairs[p][1]] = pairs[p][0];
+                        }
+                    }
+                /* loops, fanned from their lowest edge; a loop through all four surface points of
+                 * one face is fanned around the mean of its vertices instead (a fan from one of
+                 * those points would lay a triangle flat on the face, where the neighbouring cube
+                 * lays its own) */
+                bool seen[12] = {false};
+                const uint32_t vox = (uint32_t)(i + mside * (j + mside * k));
+                int nloops = 0;
+                for (int e = 0; e < 12; ++e) {
+                    if (!cross[e] || seen[e]) continue;
+                    int loop[12], nl = 0;
+                    for (int x = e; !seen[x]; x = next[x]) {
+                        seen[x] = true;
+                        loop[nl++] = x;
+                    }
+                    bool on_loop[12] = {false};
+                    for (int q = 0; q < nl; ++q) on_loop[loop[q]] = true;
+                    bool full_face = false;
+                    for (int a = 0; a < 3; ++a)
+                        for (int sd = 0; sd < 2; ++sd) {
+                            int cnt = 0;
+                            for (int x = 0; x < 12; ++x) {
+                                if (edge_axis(x) == a || !on_loop[x]) continue;
+                                int c0, c1;
+                                edge_corners(x, c0, c1);
+                                if (((c0 >> a) & 1) == sd) ++cnt;
+                            }
+                            if (cnt == 4) full_face = true;
+                        }
+                    const int centre_id = 20 + nloops++;
+                    double centre[3] = {0.0, 0.0, 0.0};
+                    if (full_face) {
+                        for (int q = 0; q < nl; ++q)
+                            for (int y = 0; y < 3; ++y) centre[y] += pos[loop[q]][y];
+                        for (int y = 0; y < 3; ++y) centre[y] /= (double)nl;
+                    }
+                    const int ntri = full_face ? nl : nl - 2;
+                    for (int q = 0; q < ntri; ++q) {
+                        const double* p3[3];
+                        int a3[3];
+                        if (full_face) {
+                            p3[0] = pos[loop[q]], a3[0] = vid[loop[q]];
+                            p3[1] = pos[loop[(q + 1) % nl]], a3[1] = vid[loop[(q + 1) % nl]];
+                            p3[2] = centre, a3[2] = centre_id;
+                        } else {
+                            p3[0] = pos[loop[0]], a3[0] = vid[loop[0]];
+                            p3[1] = pos[loop[q + 1]], a3[1] = vid[loop[q + 1]];
+                            p3[2] = pos[loop[q + 2]], a3[2] = vid[loop[q + 2]];
+                        }
+                        if (a3[0] == a3[1] || a3[1] == a3[2] || a3[0] == a3[2]) continue;
+                        for (int x = 0; x < 3; ++x)
+                            for (int y = 0; y < 3; ++y) o.verts->push_back(p3[x][y]);
+                        for (int x = 0; x < 3; ++x) o.blocks->push_back(b[x]);
+                        o.codes->push_back(((uint32_t)n << 30) | (vox << 15) | ((uint32_t)a3[0] << 10) |
+                                           ((uint32_t)a3[1] << 5) | (uint32_t)a3[2]);
+                        o.near->push_back(near ? 1 : 0);
+                    }
+                }
+            }
+}
+
+struct MeshCache {
+    std::vector<double> verts;
+    std::vector<int32_t> blocks;
+    std::vector<uint32_t> codes;
+    std::vector<uint8_t> near;
+};
+
 }  // namespace
 
 extern "C" {
@@ -659,6 +955,44 @@ int64_t orc_voxel_dda(const double a[3], const double e[3], const int32_t block[
     for (int64_t i = 0; i < n && i < cap; ++i)
         for (int k = 0; k < 3; ++k) cells[3 * i + k] = out[i][k];
     return n;
+}
+
+int64_t orc_mesh(const void* map, double collapse, const int32_t* only_keys, int64_t n_only, double* verts,
+                 int32_t* blocks, uint32_t* codes, uint8_t* near, int64_t cap) {
+    const Map& m = *static_cast<const Map*>(map);
+    MeshCache c;
+    MeshOut o{&c.verts, &c.blocks, &c.codes, &c.near};
+    if (only_keys) {
+        for (int64_t q = 0; q < n_only; ++q) {
+            const Key k{only_keys[3 * q], only_keys[3 * q + 1], only_keys[3 * q + 2]};
+            auto it = m.blocks.find(k);
+            if (it != m.blocks.end()) mesh_block(m, it->first, it->second, collapse, o);
+        }
+    } else {
+        for (const auto& kv : m.blocks) mesh_block(m, kv.first, kv.second, collapse, o);
+    }
+    const int64_t n = (int64_t)c.codes.size();
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        if (verts)
+            for (int q = 0; q < 9; ++q) verts[9 * i + q] = c.verts[9 * i + q];
+        if (blocks)
+            for (int q = 0; q < 3; ++q) blocks[3 * i + q] = c.blocks[3 * i + q];
+        if (codes) codes[i] = c.codes[i];
+        if (near) near[i] = c.near[i];
+    }
+    return n;
+}
+
+int orc_set_block(void* map, const int32_t key[3], int32_t level, const double* D, const uint32_t* W) {
+    Map& m = *static_cast<Map*>(map);
+    if (level < 0 || level >= m.cfg.levels) return -1;
+    Block& b = m.blocks[Key{key[0], key[1], key[2]}];
+    new_block(b, level);
+    for (size_t v = 0; v < b.D.size(); ++v) {
+        b.D[v] = D[v];
+        b.W[v] = W[v];
+    }
+    return 0;
 }
 
 }  // extern "C"

@@ -87,6 +87,25 @@ void orc_query_backward(const void* map, const float* pts, int64_t n, const doub
                         int32_t strict, const double* grad_sdf, double* grad_pts,
                         double grad_pose[6]);
 
+/* Multi-resolution Marching Cubes (Sec. 3.4) over the whole map, or over the blocks listed in
+ * only_keys (n_only keys, x y z each) when it is not NULL.  Each triangle gives 9 doubles (three
+ * vertices, world metres, counter-clockwise seen from outside, D >= 0), its block key (3 ints), a
+ * code (level << 30 | voxel << 15 | v0 << 10 | v1 << 5 | v2; voxel = i + m (j + m k); a vertex id
+ * is an edge 0..11, after collapse 12 + corner, or 20 + k for the centre of the cube's k-th loop
+ * when that loop is fanned around its centre) and a flag set when a decision of its cube
+ * (a corner sign, a collapse, a badly conditioned crossing) lay within rounding of its threshold.
+ * The rules (cube extents, transition truncation, corner interpolation, face segments, loop
+ * fans, collapse) are stated in oracle.cpp.  Returns the number of triangles; fills at most cap.
+ * Pinned by: vertices of linear fields on one level and across a level boundary lying on the
+ * field's zero plane; closed sphere meshes whose every directed edge has its reverse (watertight,
+ * consistently oriented) with vertices within the trilinear error of the sphere; the partition of
+ * space by the cubes of a two-level map; the collapse distance. */
+int64_t orc_mesh(const void* map, double collapse, const int32_t* only_keys, int64_t n_only, double* verts,
+                 int32_t* blocks, uint32_t* codes, uint8_t* near, int64_t cap);
+
+/* Test hook: replace block key[3] by a level-`level` block holding D, W (voxels x fastest). */
+int orc_set_block(void* map, const int32_t key[3], int32_t level, const double* D, const uint32_t* W);
+
 /* Eq. 4: (x p1 xor y p2 xor z p3) mod n_hash, products and xor in 32-bit unsigned arithmetic.
  * The oracle's own map does not need it (a std::map keyed by block coordinates holds the blocks);
  * it is here to write the stored hash vectors the library's hash is checked against. */
