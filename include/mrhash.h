@@ -197,6 +197,33 @@ mrh_status mrh_extract_blocks(mrh_map* map, int32_t* keys_dev, uint8_t* levels_d
                               int64_t block_cap, int64_t voxel_cap, int64_t* n_blocks,
                               int64_t* n_voxels);
 
+/* Multi-resolution Marching Cubes (Sec. 3.4): the zero set of the TSDF as a triangle soup.
+ * Each voxel (i, j, k) of a level-n block spans a cube from its centre to the next voxel centre
+ * along +x, +y, +z; on the block's upper face that is the first voxel-centre plane of the face
+ * neighbour, so a cube next to a finer block is truncated (the transition rule) and one next to a
+ * coarser block stretched; a block without a face neighbour has no cubes on that face.  Corner
+ * values are the trilinear interpolant of mrh_query_sdf (non-strict) at the corners; a cube with
+ * an invalid corner is skipped.  Corners with D < 0 are inside; per face, crossing edges are
+ * joined so that the inside corners of an ambiguous face stay connected; each loop of surface
+ * points is fanned from its lowest edge, or around the mean of its vertices when it passes
+ * through all four surface points of one face.  Vertex collapse: a surface point within
+ * collapse * nu_n of an end of its edge moves onto that end (0 <= collapse < 0.5; 0 = off), and
+ * triangles with two vertices on one point are dropped.
+ *   verts_dev:  device float32[cap][3][3], world metres, counter-clockwise seen from outside
+ *               (D >= 0), or NULL to count only;
+ *   blocks_dev: device int32[cap][3], the block key of each triangle's cube, or NULL;
+ *   codes_dev:  device uint32[cap], level << 30 | voxel << 15 | v0 << 10 | v1 << 5 | v2 with
+ *               voxel = i + m (j + m k) (m = 8 >> level) and vertex ids 0..11 (a surface point on
+ *               that cube edge), 12 + c (collapsed onto corner c = x + 2 y + 4 z) or 20 + k (the
+ *               centre of the cube's k-th loop), or NULL.
+ * Edge e lies along axis e / 4; bits 0 and 1 of e % 4 are its coordinates on the other two axes in
+ * increasing order.  Triangles come in no particular order.  *n_tris (host) receives the count;
+ * MRH_ERR_BUFFER_TOO_SMALL (count still set, the first cap triangles written) when it exceeds cap.
+ * Errors: MRH_ERR_INVALID_ARG (NULL map or n_tris, cap < 0, collapse outside [0, 0.5), blocks or
+ * codes without verts).  Synchronises the stream. */
+mrh_status mrh_extract_mesh(mrh_map* map, double collapse, float* verts_dev, int32_t* blocks_dev,
+                            uint32_t* codes_dev, int64_t cap, int64_t* n_tris);
+
 /* Kernel ids of the launch profiler. */
 enum {
     MRH_KERNEL_RESET = 0,
@@ -214,7 +241,8 @@ enum {
     MRH_KERNEL_BATCH_UPDATE = 12,   /* batched: update tasks of every map */
     MRH_KERNEL_BATCH_FINALIZE = 13, /* reserved, as MRH_KERNEL_FINALIZE; stays 0 */
     MRH_KERNEL_BATCH_GRAPH = 14,    /* batched: one replay of the captured step */
-    MRH_KERNEL_COUNT = 15
+    MRH_KERNEL_MESH = 15,           /* multi-resolution Marching Cubes */
+    MRH_KERNEL_COUNT = 16
 };
 
 /* Launch profiler (measurement support, not part of the method).  With on != 0 every kernel the

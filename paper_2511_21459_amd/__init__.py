@@ -231,6 +231,28 @@ class Map:
         return out
 
 
+    def mesh(self, collapse: float = 0.0, codes: bool = True) -> dict:
+        """Multi-resolution Marching Cubes of the map (mrh_extract_mesh): verts float32 [T, 3, 3]
+        (world metres, counter-clockwise seen from outside), and with codes the block key of each
+        triangle's cube (int32 [T, 3]) and its code (int32 [T], the bits of the uint32 code)."""
+        n = ctypes.c_int64()
+        L = _lib.load()
+        self._check(L.mrh_extract_mesh(self._h, float(collapse), None, None, None, 0, ctypes.byref(n)),
+                    "mrh_extract_mesh")
+        t = n.value
+        dev = torch.device("cuda", torch.cuda.current_device())
+        verts = torch.empty((t, 3, 3), dtype=torch.float32, device=dev)
+        out = {"verts": verts}
+        bp = cp = None
+        if codes:
+            out["blocks"] = torch.empty((t, 3), dtype=torch.int32, device=dev)
+            out["codes"] = torch.empty(t, dtype=torch.int32, device=dev)
+            bp, cp = ctypes.c_void_p(out["blocks"].data_ptr()), ctypes.c_void_p(out["codes"].data_ptr())
+        self._check(L.mrh_extract_mesh(self._h, float(collapse), ctypes.c_void_p(verts.data_ptr()), bp, cp, t,
+                                       ctypes.byref(n)), "mrh_extract_mesh")
+        return out
+
+
 class Batch:
     """Many maps fused together: one frame per map per ``integrate`` call, at most four launches in
     total, replayed from a captured HIP graph while the frame kinds and sizes stay the same."""

@@ -30,11 +30,11 @@ EXPORTS = [
     "mrh_query_sdf_backward", "mrh_extract_blocks", "mrh_last_error", "mrh_profile_enable",
     "mrh_profile_collect", "mrh_batch_create", "mrh_batch_destroy", "mrh_batch_integrate", "mrh_batch_set_launch",
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
-    "mrh_integrate_depth_noalloc",
+    "mrh_integrate_depth_noalloc", "mrh_extract_mesh",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
-           "batch_step"]
+           "batch_step", "mesh"]
 FRAME_NONE, FRAME_DEPTH, FRAME_POINTS = 0, 1, 2
 
 
@@ -103,6 +103,8 @@ def load():
     L.mrh_map_reset.argtypes = [P]
     L.mrh_integrate_depth.restype = i32
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_extract_mesh.restype = i32
+    L.mrh_extract_mesh.argtypes = [P, ctypes.c_double, P, P, P, i64, ctypes.POINTER(i64)]
     L.mrh_integrate_depth_noalloc.restype = i32
     L.mrh_integrate_depth_noalloc.argtypes = [P, P, i32, i32, P, P]
     L.mrh_integrate_points.restype = i32

@@ -128,7 +128,8 @@ const char* mrh_last_error(const mrh_map* map) { return map ? map->err : "null m
 
 static void free_all(mrh_map* m) {
     DevMap& d = m->dm;
-    void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out, m->dmd};
+    void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out, m->dmd,
+                    m->count_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);
@@ -225,6 +226,7 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     m->partials_cap = 1024;
     alloc((void**)&m->partials, (size_t)m->partials_cap * 6 * 8, "reduction partials");
     alloc((void**)&m->pose_out, 6 * 8, "pose gradient");
+    alloc((void**)&m->count_dev, 8, "extraction counter");
     alloc((void**)&m->dmd, sizeof(DevMap), "map descriptor");
     d.ctr = m->ctr;
     if (st == MRH_OK) st = upload_descriptor(m);
