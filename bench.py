@@ -405,6 +405,87 @@ def run_query(room, torch, np, mrh):
             "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1)}
 
 
+MESH_COLLAPSE = 0.1  # vertex collapse of the mesh record, as a fraction of the cube's voxel size
+MESH_BYTES_PER_TRIANGLE = 36 + 12 + 4  # vertices, block key, code
+
+
+def mesh_quality(verts, scene, np, n_ref=1_000_000):
+    """Accuracy, completeness, Chamfer-L1 and F-scores of a mesh against the analytic room (the
+    reconstruction metrics of the paper's evaluation): accuracy = mean distance of mesh points (the
+    vertices and the triangle centroids) to the true surface, exact from the scene's signed distance;
+    completeness = mean distance of reference points (sampled on the surfaces in proportion to area;
+    those inside another primitive or where the map holds no data left out) to the nearest mesh
+    point; F-score = harmonic mean of the fractions within each threshold.  Returns the mesh
+    points, their distances to the surface and the reference points."""
+    from workloads import surface_query_points
+
+    V = verts.reshape(-1, 3, 3)
+    # mesh points: every triangle's centroid, plus (for accuracy) a seeded sample of 2M vertices
+    cen = V.astype(np.float64).mean(axis=1)
+    rng = np.random.default_rng(20)
+    vs = V.reshape(-1, 3)[rng.choice(V.shape[0] * 3, min(2_000_000, V.shape[0] * 3), replace=False)]
+    pts = np.concatenate([cen, vs.astype(np.float64)])
+    acc_d = np.abs(scene.sdf(pts))
+    ref = surface_query_points(scene, n_ref, sigma=0.0, seed=21).astype(np.float64)
+    ref = ref[scene.sdf(ref) > -1e-6]
+    return pts, acc_d, ref
+
+
+def run_mesh(room, torch, np, mrh, configs):
+    """Multi-resolution Marching Cubes of the 100-frame room map (Sec. 3.4): kernel time, triangles,
+    the HBM roofline of the extraction launch, and the mesh's reconstruction quality against the
+    analytic scene."""
+    import ctypes
+
+    from scipy.spatial import cKDTree
+
+    fmap = room["fmap"]
+    L = mrh._lib.load()
+    n = ctypes.c_int64()
+    assert L.mrh_extract_mesh(fmap._h, MESH_COLLAPSE, None, None, None, 0, ctypes.byref(n)) == 0
+    t = n.value
+    verts = torch.empty((t, 3, 3), dtype=torch.float32, device="cuda")
+    blocks = torch.empty((t, 3), dtype=torch.int32, device="cuda")
+    codes = torch.empty(t, dtype=torch.int32, device="cuda")
+    args = (fmap._h, MESH_COLLAPSE, ctypes.c_void_p(verts.data_ptr()), ctypes.c_void_p(blocks.data_ptr()),
+            ctypes.c_void_p(codes.data_ptr()), t, ctypes.byref(n))
+    assert L.mrh_extract_mesh(*args) == 0
+    fmap.profile(True)
+    reps = 5
+    for _ in range(reps):
+        L.mrh_extract_mesh(*args)
+    prof = fmap.profile_collect()
+    fmap.profile(False)
+    k_ms = prof["mesh"][0] / prof["mesh"][1]
+    # algorithmic bytes: every block's D and W planes read once (4 + 4 B per voxel), one 8 B probe
+    # per neighbour lookup (27 per block), the triangles written
+    lv = fmap.extract(voxels=False)["levels"].cpu().numpy()
+    voxels = int(sum(int((lv == k).sum()) * (8 >> k) ** 3 for k in range(4)))
+    nbytes = voxels * 8 + len(lv) * 27 * 8 + t * MESH_BYTES_PER_TRIANGLE
+    achieved = nbytes / (k_ms / 1e3) / 1e9
+    pts, acc_d, ref = mesh_quality(verts.cpu().numpy(), room["scene"], np)
+    # completeness over the surface the map observed: reference points the map holds data at
+    _, rvalid, _ = fmap.query(torch.from_numpy(ref.astype(np.float32)).cuda())
+    ref = ref[rvalid.cpu().numpy().astype(bool)]
+    t0 = time.perf_counter()
+    comp_d, _ = cKDTree(pts).query(ref, workers=-1)
+    print(f"mesh quality: {len(pts)} mesh points, {len(ref)} reference points, tree {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    out = {"workload": f"room RGB-D orbit map after {len(room['depths'])} frames, FP32, 4 levels; "
+                       f"collapse {MESH_COLLAPSE} voxel", "triangles": t, "blocks": int(len(lv)), "voxels": voxels,
+           "kernel_ms": round(k_ms, 4), "m_triangles_per_s": round(t / (k_ms / 1e3) / 1e6, 1),
+           "roofline": {"kernel": "k_mesh", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes)},
+           "acc_cm": round(float(acc_d.mean()) * 100, 4), "comp_cm": round(float(comp_d.mean()) * 100, 4),
+           "chamfer_l1_cm": round(float(acc_d.mean() + comp_d.mean()) * 50, 4),
+           "reference_points": int(len(ref)), "mesh_points": int(len(pts))}
+    for th in (0.01, 0.1):
+        prec = float((acc_d < th).mean())
+        rec = float((comp_d < th).mean())
+        out[f"fscore_{int(th * 100)}cm_pct"] = round(200 * prec * rec / max(prec + rec, 1e-12), 3)
+    return out
+
+
 # merge thresholds of the sweep (m): a block merges once its mean voxel variance is below sigma^2;
 # 0 never merges, so every block stays at the finest level
 SWEEP_SIGMAS = (0.0, 0.01, 0.005, 0.001)
@@ -429,13 +510,17 @@ def run_sweep(room, torch, np, mrh, configs, n_points=200_000):
         lv = m.extract(voxels=False)["levels"].cpu().numpy()
         nb = [int((lv == n).sum()) for n in range(4)]
         voxels = sum(nb[n] * (8 >> n) ** 3 for n in range(4))
+        import ctypes
+
+        nt = ctypes.c_int64()
+        assert mrh._lib.load().mrh_extract_mesh(m._h, MESH_COLLAPSE, None, None, None, 0, ctypes.byref(nt)) == 0
         sdf, valid, _ = m.query(pts)
         sdf = sdf.cpu().numpy().astype(np.float64)
         valid = valid.cpu().numpy().astype(bool)
         near = np.abs(truth) < tau / 2
         err = (sdf - truth)[valid & near]
         rows.append({"sigma_thr_m": sig, "blocks_per_level": nb, "fine_block_frac": round(nb[0] / max(1, sum(nb)), 4),
-                     "voxels": voxels, "state_mb_f32": round(voxels * 12 / 1e6, 2),
+                     "voxels": voxels, "state_mb_f32": round(voxels * 12 / 1e6, 2), "mesh_faces": int(nt.value),
                      "query_valid_frac": round(float(valid[near].mean()), 4),
                      "rms_err_m": round(float(np.sqrt(np.mean(err ** 2))), 5),
                      "mean_abs_err_m": round(float(np.mean(np.abs(err))), 5)})
@@ -460,7 +545,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
-    ap.add_argument("--only", choices=["street", "batched", "sweep"],
+    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh"],
                     help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -484,6 +569,14 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched": run_batched(args, torch, np, mrh, configs)}), flush=True)
+        return
+    if args.only == "mesh":
+        depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
+        fm = mrh.Map(**configs.ROOM)
+        fm.integrate_depth_sequence(torch.from_numpy(depths).cuda(), cam.K, np.ascontiguousarray(poses))
+        fm.sync()
+        room = dict(depths=depths, cam=cam, poses=poses, scene=scene, fmap=fm)
+        print(json.dumps({"mesh": run_mesh(room, torch, np, mrh, configs)}), flush=True)
         return
     if args.only == "sweep":
         depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
@@ -529,6 +622,7 @@ def main():
     if not args.no_extras:
         result["batched"] = run_batched(args, torch, np, mrh, configs)
         result["query"] = run_query(room, torch, np, mrh)
+        result["mesh"] = run_mesh(room, torch, np, mrh, configs)
         result["sweep"] = run_sweep(room, torch, np, mrh, configs)
         street = run_street(args, torch, np, mrh, configs)
         result["street"] = street["out"]

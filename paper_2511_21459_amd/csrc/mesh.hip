@@ -21,7 +21,7 @@
 // outside.  Vertex collapse: a surface point closer than collapse * nu_n to an end of its edge is
 // moved onto that end, and triangles with two vertices on one point are dropped.
 //
-// Launch: one wave per block, four blocks per 256-thread workgroup.  The wave caches the 27 blocks
+// Launch: one wave per block, four blocks per workgroup.  The wave caches the 27 blocks
 // around its block (ids and levels, one probe per lane) and its block's TSDF (NaN where W = 0) in
 // LDS; cubes whose corners all lie in the block read LDS only, the others evaluate the interpolant
 // through the cached neighbours.  A first pass counts each cube's triangles, one atomic per
@@ -116,75 +116,121 @@ constexpr McTable make_mc_table() {
     return t;
 }
 
-__constant__ McTable kMc = make_mc_table();
+// The same table packed for the kernel: per case the loops' edges as 4-bit fields (position y at
+// bits 4 y .. 4 y + 3) and a word with the loop count (bits 0-2), the centre-fan mask (bits 3-6)
+// and the loop lengths (4 bits each from bit 8).
+struct McPacked {
+    unsigned long long edges[256];
+    uint32_t meta[256];
+};
+
+constexpr McPacked pack_mc_table(const McTable& t) {
+    McPacked p{};
+    for (int cs = 0; cs < 256; ++cs) {
+        const McCase& c = t.c[cs];
+        int total = 0;
+        uint32_t meta = (uint32_t)c.nloops | ((uint32_t)c.full << 3);
+        for (int q = 0; q < c.nloops; ++q) {
+            meta |= (uint32_t)c.len[q] << (8 + 4 * q);
+            total += c.len[q];
+        }
+        unsigned long long e = 0;
+        for (int y = 0; y < total; ++y) e |= (unsigned long long)c.edge[y] << (4 * y);
+        p.edges[cs] = e;
+        p.meta[cs] = meta;
+    }
+    return p;
+}
+
+__constant__ McPacked kMc = pack_mc_table(make_mc_table());
 
 // ---- device side ----------------------------------------------------------------------------
 
-constexpr int kMeshWaves = 4;  // blocks per 256-thread workgroup
+constexpr int kMeshWaves = 4;  // blocks per workgroup, one wave each
+constexpr int kMeshThreads = 64 * kMeshWaves;
 
-__device__ inline int floor16(int p) { return p >> 4; }  // floor(p / 16) for p in [-32, 48)
+// corners of edge e (compile-time after unrolling): low end and high end
+__host__ __device__ constexpr int edge_c0(int e) {
+    return (((e & 3) & 1) << ((e >> 2) == 0 ? 1 : 0)) | ((((e & 3) >> 1) & 1) << ((e >> 2) == 2 ? 1 : 2));
+}
+__host__ __device__ constexpr int edge_c1(int e) { return edge_c0(e) | (1 << (e >> 2)); }
 
-// The 27 blocks around the meshed one, per wave in LDS: table row (info) or NOBLOCK, and the
-// block's voxels (D, NaN where unobserved) in Morton order.
+// Morton position of (i, j, k), coordinates below 8
+__device__ inline int spread3(int x) { return (x & 1) | ((x & 2) << 2) | ((x & 4) << 4); }
+__device__ inline int morton_of(int i, int j, int k) { return spread3(i) | (spread3(j) << 1) | (spread3(k) << 2); }
+
+// Per workgroup: the case table, and per wave the 27 blocks around its block (table row or
+// NOBLOCK); the corner values of all the block's cubes, (m + 1)^3 values in x-fastest order (the
+// block's voxels, then the interpolant at the upper-face corners, which lie on the first
+// voxel-centre plane of each face neighbour; NaN where invalid) and per row of them the sign and
+// validity bits; each lane's edge parameters t of the cube it is writing; the block's surface
+// cubes and their triangle counts.
 struct MeshLds {
+    McPacked tab;
+    uint32_t rows[kMeshWaves][81];   // per lattice row (j, k): inside bits along x | valid bits << 16
     uint32_t nb[kMeshWaves][27];
-    float D[kMeshWaves][512];
-    uint32_t ntri[kMeshWaves][512 / 4];  // per cube, packed 8 bits x 4
+    float D[kMeshWaves][729];
+    float t[kMeshWaves][12][64];
+    uint16_t surf[kMeshWaves][512];  // the block's surface cubes (valid corners of both signs)
+    uint8_t cnt[kMeshWaves][512];    // their triangle counts
 };
 
 __device__ inline int nb_index(int ox, int oy, int oz) { return (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1); }
 
 template <int ST>
-__device__ inline bool voxel_value(const DevMap& m, uint32_t info, int i, int j, int k, float& v) {
+__device__ __forceinline__ bool voxel_value(const DevMap& m, uint32_t info, int i, int j, int k, float& v) {
     const int n = (int)((info >> kLevelShift) & 3u);
-    const int sh = 3 - n;
-    const size_t at = (size_t)(info & kSlotMask) * (size_t)(1 << (3 * sh)) + (size_t)morton3(i, j, k);
+    const size_t at = ((size_t)(info & kSlotMask) << (3 * (3 - n))) + (size_t)morton_of(i, j, k);
     if (Store<ST>::getW(m, n, at) == 0u) return false;
     v = Store<ST>::getD(m, n, at);
     return true;
 }
 
 // The interpolant at local lattice position P (half-finest units, relative to the meshed block),
-// through the cached neighbours.  Zero-weight corners are skipped (they change neither the value
-// nor the validity), which keeps every lookup inside the 3 x 3 x 3 neighbourhood.
+// through the cached neighbours.  A position on the home block's own lattice reads one voxel;
+// elsewhere zero-weight corners are skipped (they change neither the value nor the validity),
+// which keeps every lookup inside the 3 x 3 x 3 neighbourhood.
 template <int ST>
-__device__ inline bool lattice_value(const DevMap& m, const uint32_t* nbw, const int P[3], float& out) {
-    const int h0 = floor16(P[0]), h1 = floor16(P[1]), h2 = floor16(P[2]);
-    if (h0 < -1 || h0 > 1 || h1 < -1 || h1 > 1 || h2 < -1 || h2 > 1) return false;
-    const uint32_t hinfo = nbw[nb_index(h0, h1, h2)];
+__device__ __forceinline__ bool lattice_value(const DevMap& m, const uint32_t* nbw, int P0, int P1, int P2, float& out) {
+    const int hh[3] = {P0 >> 4, P1 >> 4, P2 >> 4};
+    if (hh[0] < -1 || hh[0] > 1 || hh[1] < -1 || hh[1] > 1 || hh[2] < -1 || hh[2] > 1) return false;
+    const uint32_t hinfo = nbw[nb_index(hh[0], hh[1], hh[2])];
     if (hinfo & kNoBlockBit) return false;
     const int n = (int)((hinfo >> kLevelShift) & 3u);
-    const int s = 2 << n, half = 1 << n;
-    const int hh[3] = {h0, h1, h2};
-    int i0[3];
-    float f[3];
+    const int sh = n + 1, half = 1 << n;
+    const float inv_s = __builtin_bit_cast(float, (uint32_t)(126 - n) << 23);  // 2^-(n + 1), exact
+    const int P[3] = {P0, P1, P2};
+    int i0[3], r[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int q = P[a] - 16 * hh[a] - half;  // in [-s, 16 + ...)
-        const int c = q >= 0 ? q / s : -((-q + s - 1) / s);
-        i0[a] = c;
-        f[a] = (float)(q - c * s) / (float)s;  // exact: s is a power of two
+        const int q = P[a] - 16 * hh[a] - half;
+        i0[a] = q >> sh;  // floor division by s = 2^(n + 1)
+        r[a] = q - (i0[a] << sh);
     }
+    if ((r[0] | r[1] | r[2]) == 0) return voxel_value<ST>(m, hinfo, i0[0], i0[1], i0[2], out);
+    const float f[3] = {(float)r[0] * inv_s, (float)r[1] * inv_s, (float)r[2] * inv_s};
     float wsum = 0.f, num = 0.f;
     bool any = false;
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int d0 = c & 1, d1 = (c >> 1) & 1, d2 = (c >> 2) & 1;
-        const float w = (d0 ? f[0] : 1.f - f[0]) * (d1 ? f[1] : 1.f - f[1]) * (d2 ? f[2] : 1.f - f[2]);
+        const int dd[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        const float w = (dd[0] ? f[0] : 1.f - f[0]) * (dd[1] ? f[1] : 1.f - f[1]) * (dd[2] ? f[2] : 1.f - f[2]);
         if (!(w > 0.f)) continue;
         int p2[3], ob[3];
-        const int dd[3] = {d0, d1, d2};
         bool inside = true;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            p2[a] = 16 * hh[a] + (i0[a] + dd[a]) * s + half;
-            ob[a] = floor16(p2[a]);
+            p2[a] = 16 * hh[a] + ((i0[a] + dd[a]) << sh) + half;
+            ob[a] = p2[a] >> 4;
             inside &= ob[a] >= -1 && ob[a] <= 1;
         }
         if (!inside) continue;
         const uint32_t info = nbw[nb_index(ob[0], ob[1], ob[2])];
         if (info & kNoBlockBit) continue;
-        const int n2 = (int)((info >> kLevelShift) & 3u);
+        const int s2 = (int)((info >> kLevelShift) & 3u) + 1;
         float v;
-        if (!voxel_value<ST>(m, info, (p2[0] - 16 * ob[0]) >> (n2 + 1), (p2[1] - 16 * ob[1]) >> (n2 + 1),
-                             (p2[2] - 16 * ob[2]) >> (n2 + 1), v))
+        if (!voxel_value<ST>(m, info, (p2[0] - 16 * ob[0]) >> s2, (p2[1] - 16 * ob[1]) >> s2,
+                             (p2[2] - 16 * ob[2]) >> s2, v))
             continue;
         wsum += w;
         num += w * v;
@@ -203,77 +249,82 @@ struct Cube {
 
 // Corner values of cube (i, j, k) of a level-n block of side ms; false when the cube is absent or
 // a corner is invalid.
-template <int ST>
-__device__ inline bool load_cube(const DevMap& m, const uint32_t* nbw, const float* sD, int n, int ms, const int nbl[3],
-                                 int i, int j, int k, Cube& cb) {
+// Corner values of cube (i, j, k) of a level-n block of side ms, from the staged corner lattice;
+// false when the cube is absent (no face neighbour) or a corner is invalid.
+__device__ __forceinline__ bool load_cube(const float* sD, int n, int ms, const int nbl[3], int i, int j, int k, Cube& cb) {
     const int s = 2 << n, half = 1 << n;
     const int idx[3] = {i, j, k};
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         cb.lo[a] = (2 * idx[a] + 1) * half;
-        if (idx[a] + 1 < ms) cb.hi[a] = cb.lo[a] + s;
-        else if (nbl[a] >= 0) cb.hi[a] = 16 + (1 << nbl[a]);
-        else return false;
+        const bool edge = idx[a] + 1 >= ms;
+        if (edge && nbl[a] < 0) return false;
+        cb.hi[a] = edge ? 16 + (1 << nbl[a]) : cb.lo[a] + s;
     }
     cb.inside = 0;
+    const int ma = ms + 1, base = i + ma * (j + ma * k);
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int d0 = c & 1, d1 = (c >> 1) & 1, d2 = (c >> 2) & 1;
-        float v;
-        if ((!d0 || i + 1 < ms) && (!d1 || j + 1 < ms) && (!d2 || k + 1 < ms)) {
-            v = sD[morton3(i + d0, j + d1, k + d2)];
-            if (v != v) return false;  // unobserved voxel
-        } else {
-            const int P[3] = {d0 ? cb.hi[0] : cb.lo[0], d1 ? cb.hi[1] : cb.lo[1], d2 ? cb.hi[2] : cb.lo[2]};
-            if (!lattice_value<ST>(m, nbw, P, v)) return false;
-        }
+        const float v = sD[base + (c & 1) + ma * (((c >> 1) & 1) + ma * ((c >> 2) & 1))];
+        if (v != v) return false;
         cb.v[c] = v;
-        if (v < 0.f) cb.inside |= 1 << c;
+        cb.inside |= (v < 0.f ? 1 : 0) << c;
     }
     return true;
 }
 
-// Vertex id and block-local position (half units) of the surface point of crossing edge e.
-__device__ inline int edge_vertex(const Cube& cb, int e, float snap_units, float pos[3]) {
-    const int a = e >> 2, r = e & 3;
-    const int o1 = a == 0 ? 1 : 0, o2 = a == 2 ? 1 : 2;
-    const int c0 = ((r & 1) << o1) | (((r >> 1) & 1) << o2), c1 = c0 | (1 << a);
-    const float L = (float)(cb.hi[a] - cb.lo[a]);
-    const float t = cb.v[c0] / (cb.v[c0] - cb.v[c1]);
-    const float d0 = t * L, d1 = (1.f - t) * L;
-    int corner = -1, id = e;
-    if (d0 < snap_units) corner = c0, id = 12 + c0;
-    else if (d1 < snap_units) corner = c1, id = 12 + c1;
-    for (int q = 0; q < 3; ++q) {
-        const float p0 = (float)(((c0 >> q) & 1) ? cb.hi[q] : cb.lo[q]);
-        const float p1 = (float)(((c1 >> q) & 1) ? cb.hi[q] : cb.lo[q]);
-        pos[q] = corner == c0 ? p0 : corner == c1 ? p1 : (q == a ? p0 + t * (p1 - p0) : p0);
+// Vertex ids (5 bits per edge, 12 edges) of a surface cube after the collapse; with tl, the edge
+// parameters t of the crossing edges are left in this lane's LDS column.
+__device__ __forceinline__ unsigned long long edge_ids(const Cube& cb, float snap_units, float (*tl)[64], int lane) {
+    unsigned long long ids = 0;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        // evaluated for every edge (no branch); only crossing edges are ever looked up
+        const int c0 = edge_c0(e), c1 = edge_c1(e), a = e >> 2;
+        const float t = cb.v[c0] * __builtin_amdgcn_rcpf(cb.v[c0] - cb.v[c1]);
+        const float L = (float)(cb.hi[a] - cb.lo[a]);
+        const float d0 = t * L, d1 = (1.f - t) * L;
+        const int id = d0 < snap_units ? 12 + c0 : d1 < snap_units ? 12 + c1 : e;
+        ids |= (unsigned long long)id << (5 * e);
+        if (tl) tl[e][lane] = t;
     }
-    return id;
+    return ids;
 }
 
-__device__ inline int edge_id(const Cube& cb, int e, float snap_units) {
-    float p[3];
-    return edge_vertex(cb, e, snap_units, p);
-}
+__device__ inline int vid_of(unsigned long long ids, int e) { return (int)((ids >> (5 * e)) & 31ull); }
 
-// Triangles of a cube after the collapse (count only).
-__device__ inline int count_triangles(const Cube& cb, float snap_units) {
-    const McCase& mc = kMc.c[cb.inside];
-    int ids[12];
-    for (int q = 0, at = 0; q < mc.nloops; ++q)
-        for (int y = 0; y < mc.len[q]; ++y, ++at) ids[at] = edge_id(cb, mc.edge[at], snap_units);
+__device__ inline int tab_edge(unsigned long long edges, int y) { return (int)((edges >> (4 * y)) & 15ull); }
+
+// Triangles of a surface cube (case edges / meta) after the collapse.
+__device__ __forceinline__ int count_triangles(unsigned long long edges, uint32_t meta, unsigned long long ids) {
     int cnt = 0;
-    for (int q = 0, at = 0; q < mc.nloops; at += mc.len[q], ++q) {
-        const int nl = mc.len[q];
-        if ((mc.full >> q) & 1) {
-            for (int y = 0; y < nl; ++y) cnt += ids[at + y] != ids[at + (y + 1) % nl];
+    const int nloops = (int)(meta & 7u);
+    for (int q = 0, at = 0; q < nloops; ++q) {
+        const int nl = (int)((meta >> (8 + 4 * q)) & 15u);
+        if ((meta >> (3 + q)) & 1u) {
+            for (int y = 0; y < nl; ++y)
+                cnt += vid_of(ids, tab_edge(edges, at + y)) != vid_of(ids, tab_edge(edges, at + (y + 1 == nl ? 0 : y + 1)));
         } else {
+            const int a0 = vid_of(ids, tab_edge(edges, at));
             for (int y = 1; y + 1 < nl; ++y) {
-                const int a0 = ids[at], a1 = ids[at + y], a2 = ids[at + y + 1];
+                const int a1 = vid_of(ids, tab_edge(edges, at + y)), a2 = vid_of(ids, tab_edge(edges, at + y + 1));
                 cnt += a0 != a1 && a1 != a2 && a0 != a2;
             }
         }
+        at += nl;
     }
     return cnt;
+}
+
+// Block-local position (half units) of the vertex on edge e with id `id`.
+__device__ __forceinline__ void vertex_pos(const Cube& cb, int e, int id, float t, float p[3]) {
+    const int c = id >= 12 ? id - 12 : edge_c0(e);
+    const int ax = id < 12 ? e >> 2 : -1;  // the axis along which the point lies inside its edge
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = (float)cb.lo[a], hi = (float)cb.hi[a];
+        p[a] = a == ax ? lo + t * (hi - lo) : (((c >> a) & 1) ? hi : lo);
+    }
 }
 
 struct MeshOut {
@@ -285,13 +336,18 @@ struct MeshOut {
     double h;            // metres per half-unit
 };
 
-__device__ inline void put_triangle(const MeshOut& o, long long at, const int32_t b[3], uint32_t code,
-                                    const float* p0, const float* p1, const float* p2) {
+__device__ __forceinline__ void put_triangle(const MeshOut& o, long long at, const double org[3], const int32_t b[3],
+                                    uint32_t code, const float* p0, const float* p1, const float* p2) {
     if (at >= o.cap) return;
     const float* p[3] = {p0, p1, p2};
-    for (int x = 0; x < 3; ++x)
-        for (int q = 0; q < 3; ++q)
-            o.verts[9 * at + 3 * x + q] = (float)((double)(16 * b[q]) * o.h + (double)p[x][q] * o.h);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        float3 w;
+        w.x = (float)(org[0] + (double)p[x][0] * o.h);
+        w.y = (float)(org[1] + (double)p[x][1] * o.h);
+        w.z = (float)(org[2] + (double)p[x][2] * o.h);
+        *reinterpret_cast<float3*>(o.verts + 9 * at + 3 * x) = w;
+    }
     if (o.blocks) {
         o.blocks[3 * at] = b[0];
         o.blocks[3 * at + 1] = b[1];
@@ -300,35 +356,50 @@ __device__ inline void put_triangle(const MeshOut& o, long long at, const int32_
     if (o.codes) o.codes[at] = code;
 }
 
-__device__ inline long long write_cube(const Cube& cb, float snap_units, const int32_t b[3], uint32_t code_base,
-                                       const MeshOut& o, long long at) {
-    const McCase& mc = kMc.c[cb.inside];
-    int ids[12];
-    float pos[12][3];
-    for (int q = 0, y = 0; q < mc.nloops; ++q)
-        for (int z = 0; z < mc.len[q]; ++z, ++y) ids[y] = edge_vertex(cb, mc.edge[y], snap_units, pos[y]);
-    for (int q = 0, st = 0; q < mc.nloops; st += mc.len[q], ++q) {
-        const int nl = mc.len[q];
-        if ((mc.full >> q) & 1) {
+__device__ __forceinline__ long long write_cube(const Cube& cb, unsigned long long edges, uint32_t meta,
+                                                unsigned long long ids, const float (*tl)[64], int lane,
+                                                const double org[3], const int32_t b[3], uint32_t code_base,
+                                                const MeshOut& o, long long at) {
+    const int nloops = (int)(meta & 7u);
+    for (int q = 0, st = 0; q < nloops; ++q) {
+        const int nl = (int)((meta >> (8 + 4 * q)) & 15u);
+        if ((meta >> (3 + q)) & 1u) {
             float c[3] = {0.f, 0.f, 0.f};
-            for (int y = 0; y < nl; ++y)
-                for (int x = 0; x < 3; ++x) c[x] += pos[st + y][x];
-            for (int x = 0; x < 3; ++x) c[x] /= (float)nl;
-            const int cid = 20 + q;
             for (int y = 0; y < nl; ++y) {
-                const int u = st + y, w = st + (y + 1) % nl;
-                if (ids[u] == ids[w]) continue;
-                put_triangle(o, at++, b, code_base | ((uint32_t)ids[u] << 10) | ((uint32_t)ids[w] << 5) | (uint32_t)cid,
-                             pos[u], pos[w], c);
+                const int e = tab_edge(edges, st + y);
+                float p[3];
+                vertex_pos(cb, e, vid_of(ids, e), tl[e][lane], p);
+                c[0] += p[0], c[1] += p[1], c[2] += p[2];
+            }
+            const float inv = 1.0f / (float)nl;
+            c[0] *= inv, c[1] *= inv, c[2] *= inv;
+            for (int y = 0; y < nl; ++y) {
+                const int eu = tab_edge(edges, st + y), ew = tab_edge(edges, st + (y + 1 == nl ? 0 : y + 1));
+                const int iu = vid_of(ids, eu), iw = vid_of(ids, ew);
+                if (iu == iw) continue;
+                float pu[3], pw[3];
+                vertex_pos(cb, eu, iu, tl[eu][lane], pu);
+                vertex_pos(cb, ew, iw, tl[ew][lane], pw);
+                put_triangle(o, at++, org, b, code_base | ((uint32_t)iu << 10) | ((uint32_t)iw << 5) | (uint32_t)(20 + q),
+                             pu, pw, c);
             }
         } else {
+            const int e0 = tab_edge(edges, st);
+            const int i0 = vid_of(ids, e0);
+            float p0[3];
+            vertex_pos(cb, e0, i0, tl[e0][lane], p0);
             for (int y = 1; y + 1 < nl; ++y) {
-                const int u = st, v = st + y, w = st + y + 1;
-                if (ids[u] == ids[v] || ids[v] == ids[w] || ids[u] == ids[w]) continue;
-                put_triangle(o, at++, b, code_base | ((uint32_t)ids[u] << 10) | ((uint32_t)ids[v] << 5) | (uint32_t)ids[w],
-                             pos[u], pos[v], pos[w]);
+                const int e1 = tab_edge(edges, st + y), e2 = tab_edge(edges, st + y + 1);
+                const int i1 = vid_of(ids, e1), i2 = vid_of(ids, e2);
+                if (i0 == i1 || i1 == i2 || i0 == i2) continue;
+                float p1[3], p2[3];
+                vertex_pos(cb, e1, i1, tl[e1][lane], p1);
+                vertex_pos(cb, e2, i2, tl[e2][lane], p2);
+                put_triangle(o, at++, org, b, code_base | ((uint32_t)i0 << 10) | ((uint32_t)i1 << 5) | (uint32_t)i2,
+                             p0, p1, p2);
             }
         }
+        st += nl;
     }
     return at;
 }
@@ -345,13 +416,19 @@ __device__ inline unsigned long long wave_excl_scan(unsigned long long v, unsign
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_mesh(const DevMap* __restrict__ pm, uint32_t n_blocks, float collapse,
+__global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict__ pm, uint32_t n_blocks, float collapse,
                                               MeshOut o) {
     const DevMap& m = *pm;
     __shared__ MeshLds L;
     __shared__ unsigned long long wbase[kMeshWaves];
     __shared__ unsigned long long gbase;
     const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
+    {
+        // the case table into LDS (256 x 12 bytes, copied as 32-bit words)
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&kMc);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&L.tab);
+        for (int w = threadIdx.x; w < (int)(sizeof(McPacked) / 4); w += kMeshThreads) dst[w] = src[w];
+    }
     const uint32_t id = blockIdx.x * kMeshWaves + (uint32_t)wv;
     uint32_t info = kNoBlockBit;
     unsigned long long key = 0;
@@ -368,7 +445,7 @@ __global__ __launch_bounds__(256) void k_mesh(const DevMap* __restrict__ pm, uin
     uint32_t* nbw = L.nb[wv];
     float* sD = L.D[wv];
     if (live) {
-        // the 27 surrounding blocks (one probe per lane) and the block's own voxels
+        // the 27 surrounding blocks (one probe per lane)
         if (lane < 27) {
             const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
             uint32_t ni = kNoBlockBit;
@@ -380,11 +457,6 @@ __global__ __launch_bounds__(256) void k_mesh(const DevMap* __restrict__ pm, uin
             }
             nbw[lane] = ni;
         }
-        const size_t base = (size_t)(info & kSlotMask) * (size_t)nvox;
-        for (int v = lane; v < nvox; v += 64) {
-            const bool seen = Store<ST>::getW(m, n, base + v) != 0u;
-            sD[v] = seen ? Store<ST>::getD(m, n, base + v) : __builtin_nanf("");
-        }
     }
     __syncthreads();
     int nbl[3] = {-1, -1, -1};
@@ -393,21 +465,92 @@ __global__ __launch_bounds__(256) void k_mesh(const DevMap* __restrict__ pm, uin
         nbl[0] = (fx & kNoBlockBit) ? -1 : (int)((fx >> kLevelShift) & 3u);
         nbl[1] = (fy & kNoBlockBit) ? -1 : (int)((fy >> kLevelShift) & 3u);
         nbl[2] = (fz & kNoBlockBit) ? -1 : (int)((fz >> kLevelShift) & 3u);
-    }
-    const float snap_units = collapse * (float)(2 << n);  // collapse * nu_n in half units
-    // pass 1: triangles per cube
-    unsigned long long mine = 0;
-    uint8_t* cnt8 = reinterpret_cast<uint8_t*>(L.ntri[wv]);
-    if (live) {
-        for (int cidx = lane; cidx < nvox; cidx += 64) {
-            const int i = cidx % ms, j = (cidx / ms) % ms, k = cidx / (ms * ms);
-            Cube cb;
-            int c = 0;
-            if (load_cube<ST>(m, nbw, sD, n, ms, nbl, i, j, k, cb) && cb.inside != 0 && cb.inside != 255)
-                c = count_triangles(cb, snap_units);
-            cnt8[cidx] = (uint8_t)c;
-            mine += (unsigned long long)c;
+        // the corner lattice: along each axis position (2 i + 1) 2^n for i < m, and the face
+        // neighbour's first voxel-centre plane 16 + 2^level for i = m
+        const int ma = ms + 1, na = ma * ma * ma, half = 1 << n;
+        const float inv_ma = 1.0f / (float)ma;
+        const size_t own = (size_t)(info & kSlotMask) * (size_t)nvox;
+        for (int v = lane; v < na; v += 64) {
+            // v = i + ma (j + ma k): quotients by ma through the reciprocal (v < 729, so the
+            // half-step offset keeps every quotient exact)
+            const int q1 = (int)(((float)v + 0.5f) * inv_ma), k = (int)(((float)q1 + 0.5f) * inv_ma);
+            const int i = v - ma * q1, j = q1 - ma * k;
+            float val = __builtin_nanf("");
+            if (i < ms && j < ms && k < ms) {
+                const size_t at = own + (size_t)morton_of(i, j, k);
+                if (Store<ST>::getW(m, n, at) != 0u) val = Store<ST>::getD(m, n, at);
+            } else if ((i < ms || nbl[0] >= 0) && (j < ms || nbl[1] >= 0) && (k < ms || nbl[2] >= 0)) {
+                const int P0 = i < ms ? (2 * i + 1) * half : 16 + (1 << nbl[0]);
+                const int P1 = j < ms ? (2 * j + 1) * half : 16 + (1 << nbl[1]);
+                const int P2 = k < ms ? (2 * k + 1) * half : 16 + (1 << nbl[2]);
+                float w;
+                if (lattice_value<ST>(m, nbw, P0, P1, P2, w)) val = w;
+            }
+            sD[v] = val;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // sign and validity bits per lattice row (j, k), x along the bits
+        for (int r = lane; r < ma * ma; r += 64) {
+            uint32_t bits = 0;
+            for (int i = 0; i < ma; ++i) {
+                const float v = sD[r * ma + i];
+                bits |= (v == v ? 1u : 0u) << (16 + i);
+                bits |= (v < 0.f ? 1u : 0u) << i;
+            }
+            L.rows[wv][r] = bits;
+        }
+    }
+    __syncthreads();
+    const float snap_units = collapse * (float)(2 << n);  // collapse * nu_n in half units
+    const int lg = 3 - n;                                 // log2 of the block side
+    // pass 1: the surface cubes (all 8 corners valid, both signs), one row of cubes along x per
+    // lane from the row bits, compacted into a list (the triangle work then runs on full waves)
+    uint16_t* surf = L.surf[wv];
+    uint8_t* cnt8 = L.cnt[wv];
+    int nsurf = 0;
+    if (live) {
+        const int ma = ms + 1, nrows = ms * ms;
+        uint32_t smask = 0;  // bit i: cube i of this lane's row is a surface cube
+        int row = lane;
+        if (row < nrows) {
+            const int j = row & (ms - 1), k = row >> lg;
+            const uint32_t r00 = L.rows[wv][j + ma * k], r10 = L.rows[wv][j + 1 + ma * k];
+            const uint32_t r01 = L.rows[wv][j + ma * (k + 1)], r11 = L.rows[wv][j + 1 + ma * (k + 1)];
+            // per cube i: corners (i, i + 1) of the four rows; valid bits from bit 16
+            const uint32_t both = (r00 & (r00 >> 1)) & (r10 & (r10 >> 1)) & (r01 & (r01 >> 1)) & (r11 & (r11 >> 1));
+            const uint32_t any_in = (r00 | (r00 >> 1) | r10 | (r10 >> 1) | r01 | (r01 >> 1) | r11 | (r11 >> 1)) & 0xFFFFu;
+            const uint32_t all_in = (r00 & (r00 >> 1) & r10 & (r10 >> 1) & r01 & (r01 >> 1) & r11 & (r11 >> 1)) & 0xFFFFu;
+            const uint32_t valid = (both >> 16) & ((1u << ms) - 1u);
+            smask = valid & any_in & ~all_in;
+        }
+        const int cnt = __popc(smask);
+        int tot = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(tot, o);
+            if (lane >= o) tot += y;
+        }
+        int at = tot - cnt;
+        nsurf = __shfl(tot, 63);
+        while (smask) {
+            const int i = __ffs(smask) - 1;
+            smask &= smask - 1;
+            surf[at++] = (uint16_t)(i + ms * row);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // pass 2: triangles per surface cube after the collapse
+    unsigned long long mine = 0;
+    for (int q = lane; q < nsurf; q += 64) {
+        const int cidx = surf[q];
+        Cube cb;
+        load_cube(sD, n, ms, nbl, cidx & (ms - 1), (cidx >> lg) & (ms - 1), cidx >> (2 * lg), cb);
+        const int c = count_triangles(L.tab.edges[cb.inside], L.tab.meta[cb.inside], edge_ids(cb, snap_units, nullptr, lane));
+        cnt8[q] = (uint8_t)c;
+        mine += (unsigned long long)c;
     }
     unsigned long long wtot = 0;
     const unsigned long long lane_off = wave_excl_scan(mine, wtot);
@@ -424,15 +567,18 @@ __global__ __launch_bounds__(256) void k_mesh(const DevMap* __restrict__ pm, uin
     }
     __syncthreads();
     if (!live || !o.verts || mine == 0) return;
-    // pass 2: the surface cubes again, written at this lane's range
+    // pass 3: the triangles, written at this lane's range
     long long at = (long long)(gbase + wbase[wv] + lane_off);
-    for (int cidx = lane; cidx < nvox; cidx += 64) {
-        if (cnt8[cidx] == 0) continue;
-        const int i = cidx % ms, j = (cidx / ms) % ms, k = cidx / (ms * ms);
+    const double org[3] = {(double)(16 * b[0]) * o.h, (double)(16 * b[1]) * o.h, (double)(16 * b[2]) * o.h};
+    float(*tl)[64] = L.t[wv];
+    for (int q = lane; q < nsurf; q += 64) {
+        if (cnt8[q] == 0) continue;
+        const int cidx = surf[q];
         Cube cb;
-        load_cube<ST>(m, nbw, sD, n, ms, nbl, i, j, k, cb);
+        load_cube(sD, n, ms, nbl, cidx & (ms - 1), (cidx >> lg) & (ms - 1), cidx >> (2 * lg), cb);
+        const unsigned long long ids = edge_ids(cb, snap_units, tl, lane);
         const uint32_t code_base = ((uint32_t)n << 30) | ((uint32_t)cidx << 15);
-        at = write_cube(cb, snap_units, b, code_base, o, at);
+        at = write_cube(cb, L.tab.edges[cb.inside], L.tab.meta[cb.inside], ids, tl, lane, org, b, code_base, o, at);
     }
 }
 
@@ -462,9 +608,9 @@ extern "C" mrh_status mrh_extract_mesh(mrh_map* map, double collapse, float* ver
         const float cf = (float)collapse;
         launch(map, K_MESH, [&] {
             switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_mesh<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, cf, o); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_mesh<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, cf, o); break;
-                default: hipLaunchKernelGGL(k_mesh<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, cf, o);
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_mesh<MRH_STORE_F16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_mesh<MRH_STORE_BF16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o); break;
+                default: hipLaunchKernelGGL(k_mesh<MRH_STORE_F32>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o);
             }
         });
         st = check_hip(map, hipGetLastError(), "mesh");
