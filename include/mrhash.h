@@ -186,7 +186,8 @@ mrh_status mrh_query_sdf_backward(mrh_map* map, const float* pts_dev, int64_t n,
                                   double grad_pose_host[6]);
 
 /* Copy the map out (Sec. 3.2 hash entries: key b_j, level n_j, and the block's voxels).
- * Blocks are written in block-table order; *n_blocks and *n_voxels (host) receive the counts.
+ * Blocks are written in block-table order (blocks streamed out to the host store are not on the
+ * GPU and are skipped); *n_blocks and *n_voxels (host) receive the counts.
  * Device outputs, each may be NULL: keys int32[n][3], levels uint8[n], offsets int64[n + 1]
  * (block i owns voxels [offsets[i], offsets[i+1])), D float32 (m), W uint32, S2 float32 (m^2)
  * with voxels x fastest.  With all outputs NULL only the counts are returned.  Returns
@@ -294,6 +295,61 @@ mrh_status mrh_batch_get_launch(const mrh_batch* batch, int32_t params[3]);
  * mrh_batch_integrate(frames) with HIP events; keep the fastest shape (written to best[3]) and
  * leave every map reset.  Meant for start-up, before the real stream of frames. */
 mrh_status mrh_batch_autotune(mrh_batch* batch, const mrh_frame* frames, int32_t reps, int32_t best[3]);
+
+/* ---- Capacity-driven streaming (Sec. 3.3) -------------------------------------------------
+ * Voxel blocks move between the GPU heaps and a host store owned by the map.  Streaming out is
+ * deferred until the fullest level heap is filled to a threshold; then every block outside the current
+ * sensor region leaves the GPU.  A block lies inside a region when its bounding sphere (block
+ * centre, radius half the block diagonal) meets the camera frustum (RGB-D: the image's pixel
+ * frustum up to max_depth + tau along the rays, the update's conservative cull) or the ball around
+ * the sensor origin (LiDAR).  Streaming out and in is exact: a block comes back with the bits it
+ * left with (voxels in the storage format, variance sums), so fusing frames with every region
+ * streamed in first gives the map of fusing them without streaming.  Block ids are not reused:
+ * max_blocks bounds the keys ever inserted (24 B each), the heaps bound the voxel memory.  The
+ * calls synchronise the stream and run between frames. */
+
+typedef struct mrh_region {
+    int32_t kind;          /* MRH_FRAME_DEPTH (camera frustum) or MRH_FRAME_POINTS (ball) */
+    int32_t width, height; /* DEPTH: image size */
+    double K[4];           /* DEPTH: fx, fy, cx, cy */
+    double T_ws[16];       /* sensor pose, row-major world-from-sensor */
+    double radius;         /* POINTS: ball radius (m) around the pose's origin */
+} mrh_region;
+
+/* Fill of the voxel memory: the largest fraction of a level's heap in use (slots not on its free
+ * stack).  Each level has its own heap, so the fullest one is the one that runs out. */
+mrh_status mrh_heap_usage(mrh_map* map, double* frac);
+
+/* If the heap usage is at least `threshold` (e.g. 0.85; 0 = always), move every block outside
+ * `region` to the host store; *n_out receives the number moved.  Errors: MRH_ERR_INVALID_ARG (bad
+ * region), MRH_ERR_OOM, MRH_ERR_HIP. */
+mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double threshold, int64_t* n_out);
+
+/* Move every stored block inside `region` back to the GPU (call before fusing a frame of that
+ * region); *n_in receives the number moved.  A stored key that exists on the GPU again (created by
+ * a frame fused while it was stored) stays in the store.  Errors: MRH_ERR_HEAP_FULL or
+ * MRH_ERR_BLOCK_LIMIT when the free heap slots or block ids cannot hold them (nothing is moved). */
+mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in);
+
+/* Counts of the host store: blocks, voxels and host bytes (each may be NULL). */
+mrh_status mrh_store_info(mrh_map* map, int64_t* n_blocks, int64_t* n_voxels, int64_t* bytes);
+
+/* Copy the host store out in ascending packed-key order, decoded as mrh_extract_blocks does but
+ * into host buffers: keys int32[n][3], levels uint8[n], offsets int64[n + 1], D float32, W uint32,
+ * S2 float32 (voxels x fastest).  NULL outputs are skipped; MRH_ERR_BUFFER_TOO_SMALL when
+ * block_cap / voxel_cap are below the counts (which are still set). */
+mrh_status mrh_store_extract(mrh_map* map, int32_t* keys_host, uint8_t* levels_host, int64_t* offsets_host,
+                             float* D_host, uint32_t* W_host, float* S2_host, int64_t block_cap, int64_t voxel_cap,
+                             int64_t* n_blocks, int64_t* n_voxels);
+
+/* Load blocks held by the caller (host arrays as mrh_extract_blocks returns them: keys int32[n][3],
+ * levels uint8[n], and the voxels of block after block, x fastest, (8 >> level)^3 each: D float32
+ * (m), W uint32, S2 float32 (m^2)) into the map, e.g. blocks saved from an earlier session.  Values
+ * are rounded to the storage format; the block's variance sums are recomputed from its voxels.
+ * Keys already in the map are left alone; *n_loaded receives the number loaded.  Errors:
+ * MRH_ERR_INVALID_ARG (bad level or key), MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT (nothing loaded). */
+mrh_status mrh_load_blocks(mrh_map* map, int64_t n, const int32_t* keys_host, const uint8_t* levels_host,
+                           const float* D_host, const uint32_t* W_host, const float* S2_host, int64_t* n_loaded);
 
 /* Text of the last error on this map (never NULL; "" when none). */
 const char* mrh_last_error(const mrh_map* map);

@@ -64,6 +64,8 @@ def lib():
         L.orc_mesh.argtypes = [P, ctypes.c_double, P, ctypes.c_int64, P, P, P, P, ctypes.c_int64]
         L.orc_set_block.restype = ctypes.c_int
         L.orc_set_block.argtypes = [P, P, ctypes.c_int32, P, P]
+        L.orc_region_holds.restype = ctypes.c_int
+        L.orc_region_holds.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double, P, P]
         _lib = L
     return _lib
 
@@ -173,6 +175,23 @@ class OracleMap:
     def mesh(self, collapse: float = 0.0, only_keys=None) -> Mesh:
         """Multi-resolution Marching Cubes (Sec. 3.4) of the whole map or of the listed blocks."""
         return _mesh(self._h, collapse, only_keys)
+
+    def region_holds(self, keys, kind: str, T, K=None, width=0, height=0, radius=0.0):
+        """Streaming region test per block key (Sec. 3.3): (inside bool [n], margin float64 [n] in
+        metres).  kind "depth" (camera frustum; K, width, height) or "points" (ball of radius)."""
+        keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3)
+        Kp = np.ascontiguousarray(K if K is not None else np.ones(4), dtype=np.float64)
+        Tp = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        inside = np.zeros(len(keys), bool)
+        margin = np.zeros(len(keys), np.float64)
+        mg = ctypes.c_double()
+        kd = 1 if kind == "depth" else 2
+        for i, k in enumerate(keys):
+            kk = np.ascontiguousarray(k)
+            inside[i] = bool(lib().orc_region_holds(self._h, kd, int(width), int(height), _p(Kp), _p(Tp), float(radius),
+                                                    _p(kk), ctypes.byref(mg)))
+            margin[i] = mg.value
+        return inside, margin
 
     def set_block(self, key, level: int, D: np.ndarray, W: np.ndarray):
         """Test hook: put a level-`level` block with the given voxels (x fastest) at `key`."""

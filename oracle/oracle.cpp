@@ -995,4 +995,49 @@ int orc_set_block(void* map, const int32_t key[3], int32_t level, const double* 
     return 0;
 }
 
+/*
+ * Streaming region (Sec. 3.3): does block key[3] stay on the GPU?  The block's bounding sphere
+ * (centre of the block, radius half its diagonal) is tested against the region: for a LiDAR scan
+ * the ball of the given radius around the sensor origin; for an RGB-D frame the frustum of the
+ * image's pixels (u in [-1/2, width - 1/2], v in [-1/2, height - 1/2]) in front of the camera,
+ * bounded by the sphere of radius lambda (max_depth + tau) around it, lambda the largest ray
+ * length per unit depth over the image corners.  The sphere meets the region when its centre lies
+ * no farther than the radius outside each bounding surface.  margin receives the smallest of those
+ * signed clearances (m): how far the decision is from flipping.
+ */
+int orc_region_holds(const void* map, int32_t kind, int32_t width, int32_t height, const double K[4],
+                     const double T_ws[16], double radius, const int32_t key[3], double* margin) {
+    const Map& m = *static_cast<const Map*>(map);
+    const double Bm = m.B;
+    const double c[3] = {((double)key[0] + 0.5) * Bm, ((double)key[1] + 0.5) * Bm, ((double)key[2] + 0.5) * Bm};
+    const double rb = 0.5 * std::sqrt(3.0) * Bm;
+    const Pose P(T_ws);
+    const double d[3] = {c[0] - P.t[0], c[1] - P.t[1], c[2] - P.t[2]};
+    double best;
+    if (kind == 2) {
+        best = radius + rb - std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    } else {
+        double x[3];
+        for (int r = 0; r < 3; ++r) x[r] = P.R[0][r] * d[0] + P.R[1][r] * d[1] + P.R[2][r] * d[2];
+        const double ax[2] = {(-0.5 - K[2]) / K[0], ((double)width - 0.5 - K[2]) / K[0]};
+        const double ay[2] = {(-0.5 - K[3]) / K[1], ((double)height - 0.5 - K[3]) / K[1]};
+        const double xlo = std::min(ax[0], ax[1]), xhi = std::max(ax[0], ax[1]);
+        const double ylo = std::min(ay[0], ay[1]), yhi = std::max(ay[0], ay[1]);
+        double lam = 1.0;
+        for (double a : ax)
+            for (double b : ay) lam = std::max(lam, std::sqrt(1.0 + a * a + b * b));
+        /* inward unit normals of the four side planes x = a z, y = b z */
+        const double planes[4][3] = {{1.0, 0.0, -xlo}, {-1.0, 0.0, xhi}, {0.0, 1.0, -ylo}, {0.0, -1.0, yhi}};
+        best = x[2] + rb;
+        for (const auto& pl : planes) {
+            const double nrm = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+            best = std::min(best, (pl[0] * x[0] + pl[1] * x[1] + pl[2] * x[2]) / nrm + rb);
+        }
+        const double range = lam * (m.cfg.max_depth + m.cfg.tau);
+        best = std::min(best, range + rb - std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+    }
+    if (margin) *margin = best;
+    return best >= 0.0 ? 1 : 0;
+}
+
 }  // extern "C"

@@ -103,6 +103,16 @@ void orc_query_backward(const void* map, const float* pts, int64_t n, const doub
 int64_t orc_mesh(const void* map, double collapse, const int32_t* only_keys, int64_t n_only, double* verts,
                  int32_t* blocks, uint32_t* codes, uint8_t* near, int64_t cap);
 
+/* Streaming region test (Sec. 3.3): 1 when block key[3] lies inside the region of a sensor at
+ * pose T_ws -- its bounding sphere meets the ball of `radius` around the sensor (kind 2, LiDAR) or
+ * the camera frustum of a width x height image with intrinsics K bounded by the sphere of radius
+ * lambda (max_depth + tau) (kind 1, RGB-D) -- else 0.  margin (may be NULL) receives the signed
+ * clearance of the decision in metres.  Pinned by: blocks straight ahead, behind the camera, beside
+ * the frustum and beyond its range at closed-form distances; every block holding a point of the
+ * frustum (or ball) is inside; blocks farther than their diagonal from the region are outside. */
+int orc_region_holds(const void* map, int32_t kind, int32_t width, int32_t height, const double K[4],
+                     const double T_ws[16], double radius, const int32_t key[3], double* margin);
+
 /* Test hook: replace block key[3] by a level-`level` block holding D, W (voxels x fastest). */
 int orc_set_block(void* map, const int32_t key[3], int32_t level, const double* D, const uint32_t* W);
 

@@ -253,6 +253,84 @@ class Map:
         return out
 
 
+    # -- streaming (capacity-driven, between the heaps and the map's host store) -------------
+    def heap_usage(self) -> float:
+        f = ctypes.c_double()
+        self._check(_lib.load().mrh_heap_usage(self._h, ctypes.byref(f)), "mrh_heap_usage")
+        return f.value
+
+    def stream_out(self, region, threshold: float = 0.85) -> int:
+        """Move every block outside `region` (see depth_region / points_region) to the host store
+        when the heaps are at least `threshold` full; returns the number moved."""
+        n = ctypes.c_int64()
+        self._check(_lib.load().mrh_stream_out(self._h, ctypes.byref(region), float(threshold), ctypes.byref(n)),
+                    "mrh_stream_out")
+        return n.value
+
+    def stream_in(self, region) -> int:
+        """Move every stored block inside `region` back to the GPU; returns the number moved."""
+        n = ctypes.c_int64()
+        self._check(_lib.load().mrh_stream_in(self._h, ctypes.byref(region), ctypes.byref(n)), "mrh_stream_in")
+        return n.value
+
+    def store_info(self):
+        """(blocks, voxels, host bytes) held in the host store."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.load().mrh_store_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                    "mrh_store_info")
+        return a.value, b.value, c.value
+
+    def store_extract(self) -> dict:
+        """The host store decoded (numpy): keys int32 [n, 3] in ascending packed-key order, levels
+        uint8 [n], offsets int64 [n + 1], D float32, W uint32, S2 float32 (voxels x fastest)."""
+        L = _lib.load()
+        nb, nv = ctypes.c_int64(), ctypes.c_int64()
+        self._check(L.mrh_store_extract(self._h, None, None, None, None, None, None, 0, 0, ctypes.byref(nb),
+                                        ctypes.byref(nv)), "mrh_store_extract")
+        out = {"keys": np.zeros((nb.value, 3), np.int32), "levels": np.zeros(nb.value, np.uint8),
+               "offsets": np.zeros(nb.value + 1, np.int64), "D": np.zeros(nv.value, np.float32),
+               "W": np.zeros(nv.value, np.uint32), "S2": np.zeros(nv.value, np.float32)}
+        ptr = [out[k].ctypes.data_as(ctypes.c_void_p) for k in ("keys", "levels", "offsets", "D", "W", "S2")]
+        self._check(L.mrh_store_extract(self._h, *ptr, nb.value, nv.value, ctypes.byref(nb), ctypes.byref(nv)),
+                    "mrh_store_extract")
+        return out
+
+    def load_blocks(self, keys, levels, D, W, S2) -> int:
+        """Load caller-held blocks (numpy, the layout of store_extract / extract) into the map."""
+        keys = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3)
+        levels = np.ascontiguousarray(levels, dtype=np.uint8)
+        D = np.ascontiguousarray(D, dtype=np.float32)
+        W = np.ascontiguousarray(W, dtype=np.uint32)
+        S2 = np.ascontiguousarray(S2, dtype=np.float32)
+        nv = int(sum((8 >> int(l)) ** 3 for l in levels))
+        if levels.shape[0] != keys.shape[0] or min(D.size, W.size, S2.size) < nv:
+            raise ValueError("load_blocks: arrays do not match the block list")
+        n = ctypes.c_int64()
+        ptr = [a.ctypes.data_as(ctypes.c_void_p) for a in (keys, levels, D, W, S2)]
+        self._check(_lib.load().mrh_load_blocks(self._h, keys.shape[0], *ptr, ctypes.byref(n)), "mrh_load_blocks")
+        return n.value
+
+
+def depth_region(width: int, height: int, K, T_ws) -> "_lib.MrhRegion":
+    """Streaming region of an RGB-D frame: the camera frustum."""
+    r = _lib.MrhRegion()
+    r.kind, r.width, r.height = _lib.FRAME_DEPTH, int(width), int(height)
+    for i, v in enumerate(np.asarray(K, np.float64).ravel()[:4]):
+        r.K[i] = float(v)
+    for i, v in enumerate(np.asarray(T_ws, np.float64).ravel()[:16]):
+        r.T_ws[i] = float(v)
+    return r
+
+
+def points_region(T_ws, radius: float) -> "_lib.MrhRegion":
+    """Streaming region of a LiDAR scan: the ball of `radius` around the sensor."""
+    r = _lib.MrhRegion()
+    r.kind, r.radius = _lib.FRAME_POINTS, float(radius)
+    for i, v in enumerate(np.asarray(T_ws, np.float64).ravel()[:16]):
+        r.T_ws[i] = float(v)
+    return r
+
+
 class Batch:
     """Many maps fused together: one frame per map per ``integrate`` call, at most four launches in
     total, replayed from a captured HIP graph while the frame kinds and sizes stay the same."""

@@ -30,12 +30,18 @@ EXPORTS = [
     "mrh_query_sdf_backward", "mrh_extract_blocks", "mrh_last_error", "mrh_profile_enable",
     "mrh_profile_collect", "mrh_batch_create", "mrh_batch_destroy", "mrh_batch_integrate", "mrh_batch_set_launch",
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
-    "mrh_integrate_depth_noalloc", "mrh_extract_mesh",
+    "mrh_integrate_depth_noalloc", "mrh_extract_mesh", "mrh_heap_usage", "mrh_stream_out", "mrh_stream_in",
+    "mrh_store_info", "mrh_store_extract", "mrh_load_blocks",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
            "batch_step", "mesh"]
 FRAME_NONE, FRAME_DEPTH, FRAME_POINTS = 0, 1, 2
+
+
+class MrhRegion(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("K", ctypes.c_double * 4), ("T_ws", ctypes.c_double * 16), ("radius", ctypes.c_double)]
 
 
 class MrhConfig(ctypes.Structure):
@@ -103,6 +109,18 @@ def load():
     L.mrh_map_reset.argtypes = [P]
     L.mrh_integrate_depth.restype = i32
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_heap_usage.restype = i32
+    L.mrh_heap_usage.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    L.mrh_stream_out.restype = i32
+    L.mrh_stream_out.argtypes = [P, ctypes.POINTER(MrhRegion), ctypes.c_double, ctypes.POINTER(i64)]
+    L.mrh_stream_in.restype = i32
+    L.mrh_stream_in.argtypes = [P, ctypes.POINTER(MrhRegion), ctypes.POINTER(i64)]
+    L.mrh_store_info.restype = i32
+    L.mrh_store_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.mrh_store_extract.restype = i32
+    L.mrh_store_extract.argtypes = [P, P, P, P, P, P, P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.mrh_load_blocks.restype = i32
+    L.mrh_load_blocks.argtypes = [P, i64, P, P, P, P, P, ctypes.POINTER(i64)]
     L.mrh_extract_mesh.restype = i32
     L.mrh_extract_mesh.argtypes = [P, ctypes.c_double, P, P, P, i64, ctypes.POINTER(i64)]
     L.mrh_integrate_depth_noalloc.restype = i32

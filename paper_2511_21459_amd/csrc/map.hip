@@ -74,29 +74,32 @@ __global__ void k_reset(const DevMap* __restrict__ pm, uint32_t n_hash) {
 
 // Copy blocks out: keys, levels and (optionally) voxels converted from Morton to x-fastest order.
 template <int ST>
-__global__ void k_extract(const DevMap* __restrict__ pm, uint32_t nb, const int64_t* __restrict__ offsets, int32_t* keys,
-                          uint8_t* levels, float* D, uint32_t* W, float* S2) {
+__global__ void k_extract(const DevMap* __restrict__ pm, uint32_t nb, const int32_t* __restrict__ pos,
+                          const int64_t* __restrict__ offsets, int32_t* keys, uint8_t* levels, float* D, uint32_t* W,
+                          float* S2) {
     const DevMap& m = *pm;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t id = wave; id < nb; id += nwaves) {
+        const int32_t row = pos[id];
+        if (row < 0) continue;  // streamed out
         const uint32_t info = m.binfo[id];
         const int lvl = (int)((info >> kLevelShift) & 3u);
         if (lane == 0) {
             if (keys) {
                 int32_t x, y, z;
                 unpack_key(m.bkey[id], x, y, z);
-                keys[3 * id] = x;
-                keys[3 * id + 1] = y;
-                keys[3 * id + 2] = z;
+                keys[3 * row] = x;
+                keys[3 * row + 1] = y;
+                keys[3 * row + 2] = z;
             }
-            if (levels) levels[id] = (info & kNoBlockBit) ? 0xFF : (uint8_t)lvl;
+            if (levels) levels[row] = (info & kNoBlockBit) ? 0xFF : (uint8_t)lvl;
         }
         if ((info & kNoBlockBit) || !(D || W || S2)) continue;
         const int mside = 8 >> lvl, nv = mside * mside * mside;
         const size_t base = (size_t)(info & kSlotMask) * nv;
-        const int64_t off = offsets[id];
+        const int64_t off = offsets[row];
         for (int p = lane; p < nv; p += 64) {
             int i, j, k;
             demorton3(p, i, j, k);
@@ -127,6 +130,7 @@ uint32_t mrh_block_hash(int32_t x, int32_t y, int32_t z, uint64_t n_hash) {
 const char* mrh_last_error(const mrh_map* map) { return map ? map->err : "null map"; }
 
 static void free_all(mrh_map* m) {
+    stream_free(m);
     DevMap& d = m->dm;
     void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out, m->dmd,
                     m->count_dev};
@@ -262,6 +266,7 @@ mrh_status mrh_map_reset(mrh_map* map) {
     if (!map) return MRH_ERR_INVALID_ARG;
     map->frames = map->frames_at_sync = 0;
     for (int s = 0; s < 16; ++s) map->stats_at_sync[s] = 0;
+    stream_clear(map);
     const uint32_t n_hash = map->dm.hmask + 1;
     launch(map, K_RESET, [&] { hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, map->stream, map->dmd, n_hash); });
     return check_hip(map, hipGetLastError(), "reset");
@@ -298,8 +303,9 @@ mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals) {
     }
     const uint32_t frames_since = map->frames - map->frames_at_sync;
     map->frames_at_sync = map->frames;
-    if (last) fill_stats(since, frames_since, nb, h.error_flags.v, last);
-    if (totals) fill_stats(tot, map->frames, nb, h.error_flags.v, totals);
+    const uint32_t live = nb - (uint32_t)(map->gone < nb ? map->gone : nb);
+    if (last) fill_stats(since, frames_since, live, h.error_flags.v, last);
+    if (totals) fill_stats(tot, map->frames, live, h.error_flags.v, totals);
     if (h.error_flags.v) {
         const uint32_t zero = 0;
         st = check_hip(map, hipMemcpyAsync(&map->ctr->error_flags.v, &zero, 4, hipMemcpyHostToDevice, map->stream),
@@ -329,41 +335,48 @@ mrh_status mrh_extract_blocks(mrh_map* map, int32_t* keys_dev, uint8_t* levels_d
         st = check_hip(map, hipMemcpy(info.data(), map->dm.binfo, (size_t)nb * 4, hipMemcpyDeviceToHost), "extract");
         if (st != MRH_OK) return st;
     }
-    std::vector<int64_t> offs(nb + 1, 0);
+    // rows of blocks streamed out to the host store are skipped; pos[id] is a row's output index
+    std::vector<int32_t> pos(nb, -1);
+    std::vector<int64_t> offs(1, 0);
+    uint32_t nout = 0;
     for (uint32_t i = 0; i < nb; ++i) {
+        if (info[i] & kGoneBit) continue;
         const int lvl = (int)((info[i] >> kLevelShift) & 3u);
         const int64_t nv = (info[i] & kNoBlockBit) ? 0 : (int64_t)side_of(lvl) * side_of(lvl) * side_of(lvl);
-        offs[i + 1] = offs[i] + nv;
+        pos[i] = (int32_t)nout++;
+        offs.push_back(offs.back() + nv);
     }
-    if (n_blocks) *n_blocks = nb;
-    if (n_voxels) *n_voxels = offs[nb];
+    if (n_blocks) *n_blocks = nout;
+    if (n_voxels) *n_voxels = offs[nout];
     const bool want_blocks = keys_dev || levels_dev || offsets_dev;
     const bool want_vox = D_dev || W_dev || S2_dev;
     if (!want_blocks && !want_vox) return MRH_OK;
-    if (block_cap < (int64_t)nb || (want_vox && voxel_cap < offs[nb]))
-        return set_error(map, MRH_ERR_BUFFER_TOO_SMALL, "extract needs %u blocks / %lld voxels", nb,
-                         (long long)offs[nb]);
-    if (nb == 0) {
+    if (block_cap < (int64_t)nout || (want_vox && voxel_cap < offs[nout]))
+        return set_error(map, MRH_ERR_BUFFER_TOO_SMALL, "extract needs %u blocks / %lld voxels", nout,
+                         (long long)offs[nout]);
+    if (nout == 0) {
         if (offsets_dev) return check_hip(map, hipMemcpy(offsets_dev, offs.data(), 8, hipMemcpyHostToDevice), "extract");
         return MRH_OK;
     }
+    // block voxel offsets per output row (the caller's buffer when given) and row positions per id
     int64_t* doffs = offsets_dev;
-    if (!doffs) {
-        st = check_hip(map, hipMalloc((void**)&doffs, (nb + 1) * 8), "extract offsets");
-        if (st != MRH_OK) return st;
-    }
-    st = check_hip(map, hipMemcpy(doffs, offs.data(), (nb + 1) * 8, hipMemcpyHostToDevice), "extract");
+    int32_t* dpos = nullptr;
+    if (!doffs) st = check_hip(map, hipMalloc((void**)&doffs, ((size_t)nout + 1) * 8), "extract offsets");
+    if (st == MRH_OK) st = check_hip(map, hipMalloc((void**)&dpos, (size_t)nb * 4), "extract rows");
+    if (st == MRH_OK) st = check_hip(map, hipMemcpy(doffs, offs.data(), ((size_t)nout + 1) * 8, hipMemcpyHostToDevice), "extract");
+    if (st == MRH_OK) st = check_hip(map, hipMemcpy(dpos, pos.data(), (size_t)nb * 4, hipMemcpyHostToDevice), "extract");
     if (st == MRH_OK) {
         const uint32_t grid = nb / 4 + 1 < 4096 ? nb / 4 + 1 : 4096;
         switch (map->cfg.storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL(k_extract<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL(k_extract<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
-            default: hipLaunchKernelGGL(k_extract<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev);
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_extract<MRH_STORE_F16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, dpos, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_extract<MRH_STORE_BF16>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, dpos, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev); break;
+            default: hipLaunchKernelGGL(k_extract<MRH_STORE_F32>, dim3(grid), dim3(256), 0, map->stream, map->dmd, nb, dpos, doffs, keys_dev, levels_dev, D_dev, W_dev, S2_dev);
         }
         st = check_hip(map, hipGetLastError(), "extract");
         if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "extract");
     }
-    if (!offsets_dev) (void)hipFree(doffs);
+    if (!offsets_dev && doffs) (void)hipFree(doffs);
+    if (dpos) (void)hipFree(dpos);
     return st;
 }
 

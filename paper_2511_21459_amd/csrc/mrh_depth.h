@@ -31,6 +31,9 @@ struct DepthFrame {
     int32_t tiles_x, tiles_y;
 };
 
+// Host: frame sizes the kernels accept (pixel indices 32-bit, pixel coordinates exact in FP32).
+bool depth_size_ok(int32_t width, int32_t height);
+
 // Host: fill a frame descriptor; false on a non-finite pose or intrinsics or a zero focal length.
 bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, int32_t height, const double K[4],
                       const double T_ws[16], DepthFrame& f);

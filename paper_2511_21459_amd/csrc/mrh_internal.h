@@ -26,6 +26,7 @@ constexpr int64_t kKeyLimit = (int64_t(1) << 20) - 2;  // |block coordinate| bou
 constexpr uint32_t kSlotMask = (1u << 27) - 1;
 constexpr int kLevelShift = 27;
 constexpr uint32_t kNewBit = 1u << 29;
+constexpr uint32_t kGoneBit = 1u << 30;     // block streamed out to the host store (always with NOBLOCK)
 constexpr uint32_t kNoBlockBit = 1u << 31;
 
 constexpr uint32_t kErrTableFull = 1u, kErrHeapFull = 2u, kErrBlockLimit = 4u;
@@ -375,6 +376,8 @@ struct ProfRec {
 
 }  // namespace mrh
 
+struct mrh_stream_state;  // host store and staging of the streaming calls
+
 struct mrh_map {
     mrh_config cfg{};
     hipStream_t stream = nullptr;
@@ -397,6 +400,8 @@ struct mrh_map {
     bool profiling = false;      // bracket every launch with events (mrh_profile_enable)
     std::vector<mrh::ProfRec> prof;
     std::vector<hipEvent_t> event_pool;
+    mrh_stream_state* stream_st = nullptr;
+    uint64_t gone = 0;           // blocks streamed out since the last reset (their ids stay used)
     char err[512] = {0};
 };
 
@@ -405,6 +410,8 @@ mrh_status set_error(mrh_map* m, mrh_status code, const char* fmt, ...);
 mrh_status check_hip(mrh_map* m, hipError_t e, const char* what);
 bool pose_from(const double* T, Pose& P);
 mrh_status upload_descriptor(mrh_map* m);
+void stream_free(mrh_map* m);   // release the host store and the streaming staging buffers
+void stream_clear(mrh_map* m);  // empty the host store (map reset)
 
 // Launch through `fn` (a callable that enqueues one kernel on m->stream), bracketed by events
 // when profiling is on.

@@ -175,6 +175,6 @@ template <>
 struct Store<MRH_STORE_BF16> : Store16<MRH_STORE_BF16> {};
 
 // host: bytes per voxel of each plane
-inline int plane_bytes(int storage) { return storage == MRH_STORE_F32 ? 4 : 2; }
+__host__ __device__ inline int plane_bytes(int storage) { return storage == MRH_STORE_F32 ? 4 : 2; }
 
 }  // namespace mrh
