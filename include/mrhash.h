@@ -351,6 +351,27 @@ mrh_status mrh_store_extract(mrh_map* map, int32_t* keys_host, uint8_t* levels_h
 mrh_status mrh_load_blocks(mrh_map* map, int64_t n, const int32_t* keys_host, const uint8_t* levels_host,
                            const float* D_host, const uint32_t* W_host, const float* S2_host, int64_t* n_loaded);
 
+/* ---- Image-space quadtree by contrast (Sec. 3.5, Eq. 10, Algorithm 1) ------------------------
+ * Standalone (no map).  Contrast of a node: the Rec. 601 luma weights (0.2989, 0.5870, 0.1140)
+ * times the per-channel mean squared deviation of its pixels' RGB values from their mean (Eq. 10).
+ * Breadth first from the whole image, a node whose contrast exceeds `threshold` and whose shorter
+ * side exceeds `min_size` (>= 1) is split at (x0 + w / 2, y0 + h / 2), rounded down, into top-left,
+ * bottom-left, top-right and bottom-right children (children without pixels dropped); every other
+ * node is a leaf.  Images of up to 2^23 pixels. */
+typedef struct mrh_quadtree mrh_quadtree;
+
+/* Buffers for images of up to max_width x max_height (summed-area tables, 36 B per pixel, and two
+ * node queues), bound to `stream`.  Errors: MRH_ERR_INVALID_ARG, MRH_ERR_OOM. */
+mrh_status mrh_quadtree_create(int32_t max_width, int32_t max_height, void* stream, mrh_quadtree** out);
+void mrh_quadtree_destroy(mrh_quadtree* qt);
+
+/* Leaves of the quadtree of an 8-bit RGB image (device uint8[height][width][3], interleaved):
+ * leaves_dev device int32[cap][4] = (x0, y0, w, h) and contrast_dev device float32[cap] (either may
+ * be NULL; both NULL counts only), in no particular order; *n_leaves (host) receives the count.
+ * MRH_ERR_BUFFER_TOO_SMALL (count still set) when it exceeds cap.  Synchronises the stream. */
+mrh_status mrh_quadtree_build(mrh_quadtree* qt, const uint8_t* rgb_dev, int32_t width, int32_t height, double threshold,
+                              int32_t min_size, int32_t* leaves_dev, float* contrast_dev, int64_t cap, int64_t* n_leaves);
+
 /* Text of the last error on this map (never NULL; "" when none). */
 const char* mrh_last_error(const mrh_map* map);
 

@@ -66,6 +66,9 @@ def lib():
         L.orc_set_block.argtypes = [P, P, ctypes.c_int32, P, P]
         L.orc_region_holds.restype = ctypes.c_int
         L.orc_region_holds.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_double, P, P]
+        L.orc_quadtree.restype = ctypes.c_int64
+        L.orc_quadtree.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P,
+                                   ctypes.c_int64, P]
         _lib = L
     return _lib
 
@@ -236,6 +239,19 @@ def _mesh(h, collapse: float, only_keys=None) -> Mesh:
     if n:
         lib().orc_mesh(h, float(collapse), okp, nok, _p(verts), _p(blocks), _p(codes), _p(near), n)
     return Mesh(verts, blocks, codes, near.astype(bool))
+
+
+def quadtree(rgb: np.ndarray, threshold: float, min_size: int):
+    """Quadtree leaves of an 8-bit RGB image [h, w, 3] (Eq. 10, Algorithm 1): (leaves int32 [n, 4]
+    as x0, y0, w, h in breadth-first order, contrast float64 [n], near-threshold decisions)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    h, w = rgb.shape[:2]
+    near = ctypes.c_int64()
+    n = int(lib().orc_quadtree(_p(rgb), w, h, float(threshold), int(min_size), None, None, 0, ctypes.byref(near)))
+    leaves = np.zeros((n, 4), np.int32)
+    con = np.zeros(n, np.float64)
+    lib().orc_quadtree(_p(rgb), w, h, float(threshold), int(min_size), _p(leaves), _p(con), n, ctypes.byref(near))
+    return leaves, con, int(near.value)
 
 
 def eq4_hash(x: int, y: int, z: int, n_hash: int) -> int:

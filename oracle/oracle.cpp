@@ -1040,4 +1040,71 @@ int orc_region_holds(const void* map, int32_t kind, int32_t width, int32_t heigh
     return best >= 0.0 ? 1 : 0;
 }
 
+/*
+ * Image-space quadtree by contrast (Sec. 3.5, Eq. 10, Algorithm 1).  Contrast of a node: the Rec. 601
+ * luma weights l = (0.2989, 0.5870, 0.1140) times the per-channel mean squared deviation of its
+ * pixels' RGB values from their mean (two passes, FP64).  Breadth first from the whole image: a
+ * node whose contrast exceeds the threshold and whose size (its shorter side) exceeds the minimum
+ * is split at the midpoints (x0 + w / 2, y0 + h / 2, rounded down) into top-left, bottom-left,
+ * top-right and bottom-right children (children without pixels dropped); every other node is a
+ * leaf.  Leaves are written as (x0, y0, w, h) in breadth-first order with their contrast; near
+ * counts the split decisions (of nodes large enough to split, with nonzero contrast: a flat node's
+ * zero is exact) within 1e-9 (relative) of the threshold.
+ */
+int64_t orc_quadtree(const uint8_t* rgb, int32_t width, int32_t height, double threshold, int32_t min_size,
+                     int32_t* leaves, double* contrast, int64_t cap, int64_t* near) {
+    struct Node {
+        int32_t x, y, w, h;
+    };
+    static const double l[3] = {0.2989, 0.5870, 0.1140};
+    if (min_size < 1 || width < 1 || height < 1) return -1;  /* a one-pixel node is always a leaf */
+    std::vector<Node> queue{{0, 0, width, height}};
+    int64_t nleaf = 0, nnear = 0;
+    while (!queue.empty()) {
+        std::vector<Node> next;
+        for (const Node& q : queue) {
+            const double n = (double)q.w * (double)q.h;
+            double mean[3] = {0.0, 0.0, 0.0};
+            for (int32_t y = q.y; y < q.y + q.h; ++y)
+                for (int32_t x = q.x; x < q.x + q.w; ++x)
+                    for (int c = 0; c < 3; ++c) mean[c] += (double)rgb[3 * ((size_t)y * width + x) + c];
+            for (int c = 0; c < 3; ++c) mean[c] /= n;
+            double sq[3] = {0.0, 0.0, 0.0};
+            for (int32_t y = q.y; y < q.y + q.h; ++y)
+                for (int32_t x = q.x; x < q.x + q.w; ++x)
+                    for (int c = 0; c < 3; ++c) {
+                        const double dv = (double)rgb[3 * ((size_t)y * width + x) + c] - mean[c];
+                        sq[c] += dv * dv;
+                    }
+            double con = 0.0;
+            for (int c = 0; c < 3; ++c) con += l[c] * (sq[c] / n);
+            /* a split decision within rounding of the threshold (a flat node's zero is exact) */
+            if (std::min(q.w, q.h) > min_size && con != 0.0 &&
+                std::fabs(con - threshold) <= 1e-9 * std::max(1.0, std::fabs(threshold)))
+                ++nnear;
+            if (con > threshold && std::min(q.w, q.h) > min_size) {
+                const int32_t wl = q.w / 2, ht = q.h / 2;
+                const Node kids[4] = {{q.x, q.y, wl, ht}, {q.x, q.y + ht, wl, q.h - ht},
+                                      {q.x + wl, q.y, q.w - wl, ht}, {q.x + wl, q.y + ht, q.w - wl, q.h - ht}};
+                for (const Node& k : kids)
+                    if (k.w > 0 && k.h > 0) next.push_back(k);
+            } else {
+                if (nleaf < cap) {
+                    if (leaves) {
+                        leaves[4 * nleaf] = q.x;
+                        leaves[4 * nleaf + 1] = q.y;
+                        leaves[4 * nleaf + 2] = q.w;
+                        leaves[4 * nleaf + 3] = q.h;
+                    }
+                    if (contrast) contrast[nleaf] = con;
+                }
+                ++nleaf;
+            }
+        }
+        queue.swap(next);
+    }
+    if (near) *near = nnear;
+    return nleaf;
+}
+
 }  // extern "C"

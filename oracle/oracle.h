@@ -113,6 +113,17 @@ int64_t orc_mesh(const void* map, double collapse, const int32_t* only_keys, int
 int orc_region_holds(const void* map, int32_t kind, int32_t width, int32_t height, const double K[4],
                      const double T_ws[16], double radius, const int32_t key[3], double* margin);
 
+/* Image-space quadtree by contrast (Sec. 3.5, Eq. 10, Algorithm 1) of an interleaved 8-bit RGB
+ * image (height x width x 3): breadth-first splitting of every node whose contrast (luma-weighted
+ * per-channel mean squared deviation) exceeds `threshold` and whose shorter side exceeds
+ * `min_size`, at the rounded-down midpoints.  Writes up to cap leaves (x0, y0, w, h) and their
+ * contrast in breadth-first order, and the number of split decisions within 1e-9 of the
+ * threshold to *near; returns the number of leaves.  Pinned by: a flat image (one leaf, zero
+ * contrast); two flat halves (contrast in closed form); a checkerboard splitting down to the
+ * minimum size; leaves tiling the image; every leaf below the threshold or at the minimum size. */
+int64_t orc_quadtree(const uint8_t* rgb, int32_t width, int32_t height, double threshold, int32_t min_size,
+                     int32_t* leaves, double* contrast, int64_t cap, int64_t* near);
+
 /* Test hook: replace block key[3] by a level-`level` block holding D, W (voxels x fastest). */
 int orc_set_block(void* map, const int32_t key[3], int32_t level, const double* D, const uint32_t* W);
 

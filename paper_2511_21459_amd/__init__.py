@@ -311,6 +311,50 @@ class Map:
         return n.value
 
 
+class Quadtree:
+    """Image-space quadtree by contrast (Eq. 10, Algorithm 1) for images up to max_width x max_height,
+    bound to torch's current stream."""
+
+    def __init__(self, max_width: int, max_height: int):
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = _lib.load().mrh_quadtree_create(int(max_width), int(max_height), ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(h))
+        if st != 0:
+            raise MrhError(st, "mrh_quadtree_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mrh_quadtree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, rgb: torch.Tensor, threshold: float, min_size: int):
+        """Leaves (int32 [n, 4] as x0, y0, w, h) and contrast (float32 [n]) of a uint8 [h, w, 3] image."""
+        if rgb.dim() != 3 or rgb.shape[2] != 3:
+            raise ValueError("rgb must be [H, W, 3]")
+        p = _dev(rgb, torch.uint8, name="rgb")
+        L = _lib.load()
+        n = ctypes.c_int64()
+        args = (self._h, p, rgb.shape[1], rgb.shape[0], float(threshold), int(min_size))
+        st = L.mrh_quadtree_build(*args, None, None, 0, ctypes.byref(n))
+        if st != 0:
+            raise MrhError(st, "mrh_quadtree_build")
+        leaves = torch.empty((n.value, 4), dtype=torch.int32, device=rgb.device)
+        con = torch.empty(n.value, dtype=torch.float32, device=rgb.device)
+        st = L.mrh_quadtree_build(*args, ctypes.c_void_p(leaves.data_ptr()), ctypes.c_void_p(con.data_ptr()), n.value,
+                                  ctypes.byref(n))
+        if st != 0:
+            raise MrhError(st, "mrh_quadtree_build")
+        return leaves, con
+
+
 def depth_region(width: int, height: int, K, T_ws) -> "_lib.MrhRegion":
     """Streaming region of an RGB-D frame: the camera frustum."""
     r = _lib.MrhRegion()

@@ -31,7 +31,8 @@ EXPORTS = [
     "mrh_profile_collect", "mrh_batch_create", "mrh_batch_destroy", "mrh_batch_integrate", "mrh_batch_set_launch",
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
     "mrh_integrate_depth_noalloc", "mrh_extract_mesh", "mrh_heap_usage", "mrh_stream_out", "mrh_stream_in",
-    "mrh_store_info", "mrh_store_extract", "mrh_load_blocks",
+    "mrh_store_info", "mrh_store_extract", "mrh_load_blocks", "mrh_quadtree_create", "mrh_quadtree_destroy",
+    "mrh_quadtree_build",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
@@ -109,6 +110,12 @@ def load():
     L.mrh_map_reset.argtypes = [P]
     L.mrh_integrate_depth.restype = i32
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_quadtree_create.restype = i32
+    L.mrh_quadtree_create.argtypes = [i32, i32, P, ctypes.POINTER(P)]
+    L.mrh_quadtree_destroy.restype = None
+    L.mrh_quadtree_destroy.argtypes = [P]
+    L.mrh_quadtree_build.restype = i32
+    L.mrh_quadtree_build.argtypes = [P, P, i32, i32, ctypes.c_double, i32, P, P, i64, ctypes.POINTER(i64)]
     L.mrh_heap_usage.restype = i32
     L.mrh_heap_usage.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     L.mrh_stream_out.restype = i32
