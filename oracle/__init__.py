@@ -69,6 +69,8 @@ def lib():
         L.orc_quadtree.restype = ctypes.c_int64
         L.orc_quadtree.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P,
                                    ctypes.c_int64, P]
+        L.orc_integrate_rgbd.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P]
+        L.orc_extract_color.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -125,6 +127,21 @@ class OracleMap:
         T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
         lib().orc_integrate_depth(self._h, _p(depth), depth.shape[1], depth.shape[0], _p(K), _p(T))
         return self.last_stats()
+
+    def integrate_rgbd(self, depth: np.ndarray, rgb: np.ndarray, K, T) -> dict:
+        depth = np.ascontiguousarray(depth, dtype=np.float32)
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+        assert rgb.shape == depth.shape + (3,)
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        lib().orc_integrate_rgbd(self._h, _p(depth), _p(rgb), depth.shape[1], depth.shape[0], _p(K), _p(T))
+        return self.last_stats()
+
+    def extract_color(self) -> np.ndarray:
+        """float64 [voxels, 3] colours in the voxel order of extract()."""
+        out = np.zeros((int(lib().orc_num_voxels(self._h)), 3), np.float64)
+        lib().orc_extract_color(self._h, _p(out))
+        return out
 
     def integrate_points(self, xyz: np.ndarray, T) -> dict:
         xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)

@@ -36,6 +36,7 @@ struct Block {
     int level = 0;
     std::vector<double> D, S2;   /* running mean (Eq. 3) and sum of squared deviations (Eq. 5) */
     std::vector<uint64_t> W;     /* integer weight, w_k = 1 per observation (Sec. 3.1) */
+    std::vector<double> C;       /* colour (Sec. 3): running mean of the RGB observations, 3 per voxel */
     bool touched = false;        /* some voxel was updated in the current frame */
 };
 
@@ -63,6 +64,7 @@ void new_block(Block& b, int level) {
     b.D.assign(size_t(m) * m * m, 0.0);
     b.S2.assign(size_t(m) * m * m, 0.0);
     b.W.assign(size_t(m) * m * m, 0);
+    b.C.assign(size_t(3) * m * m * m, 0.0);
     b.touched = false;
 }
 
@@ -238,13 +240,13 @@ void observe(Block& blk, int idx, double d) {
  */
 void merge_block(Map& m, Block& blk) {
     const int n = blk.level, mf = side(n), mc = mf / 2;
-    std::vector<double> D(size_t(mc) * mc * mc), S2(size_t(mc) * mc * mc);
+    std::vector<double> D(size_t(mc) * mc * mc), S2(size_t(mc) * mc * mc), C(size_t(3) * mc * mc * mc);
     std::vector<uint64_t> W(size_t(mc) * mc * mc);
     for (int K = 0; K < mc; ++K)
         for (int J = 0; J < mc; ++J)
             for (int I = 0; I < mc; ++I) {
                 uint64_t w = 0;
-                double sd = 0.0, s2 = 0.0;
+                double sd = 0.0, s2 = 0.0, sc[3] = {0.0, 0.0, 0.0};
                 for (int c = 0; c < 2; ++c)
                     for (int b = 0; b < 2; ++b)
                         for (int a = 0; a < 2; ++a) {
@@ -253,16 +255,20 @@ void merge_block(Map& m, Block& blk) {
                             w += blk.W[f];
                             sd += (double)blk.W[f] * blk.D[f];
                             s2 += blk.S2[f];
+                            for (int ch = 0; ch < 3; ++ch) sc[ch] += (double)blk.W[f] * blk.C[3 * (size_t)f + ch];
                         }
                 const int o = I + mc * (J + mc * K);
                 W[o] = w;
                 D[o] = w > 0 ? sd / (double)w : 0.0;
                 S2[o] = w > 0 ? s2 : 0.0;
+                /* colour pools like the TSDF: the weighted mean of the observed children */
+                for (int ch = 0; ch < 3; ++ch) C[3 * (size_t)o + ch] = w > 0 ? sc[ch] / (double)w : 0.0;
             }
     blk.level = n + 1;
     blk.D.swap(D);
     blk.W.swap(W);
     blk.S2.swap(S2);
+    blk.C.swap(C);
     (void)m;
 }
 
@@ -702,8 +708,16 @@ void* orc_create(const orc_config* cfg) {
 
 void orc_destroy(void* map) { delete static_cast<Map*>(map); }
 
+int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_t width, int32_t height,
+                       const double K[4], const double T_ws[16]);
+
 int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t height,
                         const double K[4], const double T_ws[16]) {
+    return orc_integrate_rgbd(map, depth, nullptr, width, height, K, T_ws);
+}
+
+int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_t width, int32_t height,
+                       const double K[4], const double T_ws[16]) {
     Map& m = *static_cast<Map*>(map);
     m.last = orc_stats{};
     const Pose P(T_ws);
@@ -761,8 +775,18 @@ int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t he
                     }
                     if (raw < -tau) continue; /* occluded beyond the truncation band */
                     const double obs = raw < tau ? raw : tau;
-                    observe(blk, i + mm * (j + mm * k), obs);
+                    const int vi = i + mm * (j + mm * k);
+                    observe(blk, vi, obs);
                     m.last.observations++;
+                    if (rgb) {
+                        /* colour of the same pixel, averaged like the TSDF (Eq. 3 with w = 1) */
+                        const size_t px = 3 * ((size_t)fv * width + (size_t)fu);
+                        const double Wn = (double)blk.W[vi];
+                        for (int ch = 0; ch < 3; ++ch) {
+                            double& c = blk.C[3 * (size_t)vi + ch];
+                            c = c + ((double)rgb[px + ch] - c) / Wn;
+                        }
+                    }
                 }
     }
 
@@ -1105,6 +1129,16 @@ int64_t orc_quadtree(const uint8_t* rgb, int32_t width, int32_t height, double t
     }
     if (near) *near = nnear;
     return nleaf;
+}
+
+void orc_extract_color(const void* map, double* rgb) {
+    const Map& m = *static_cast<const Map*>(map);
+    int64_t off = 0;
+    for (const auto& kv : m.blocks) {
+        const Block& b = kv.second;
+        for (size_t v = 0; v < b.C.size(); ++v) rgb[off + (int64_t)v] = b.C[v];
+        off += (int64_t)b.C.size();
+    }
 }
 
 }  // extern "C"

@@ -52,6 +52,17 @@ void orc_destroy(void* map);
 int orc_integrate_depth(void* map, const float* depth, int32_t width, int32_t height,
                         const double K[4], const double T_ws[16]);
 
+/* RGB-D fusion with colour (Sec. 3: a voxel stores a colour): orc_integrate_depth, and every voxel
+ * the frame updates also averages the RGB value of its pixel (rgb: 8-bit, H x W x 3 interleaved)
+ * into its colour, C <- C + (c - C) / W with the voxel's updated weight; merging pools colour as
+ * the weighted mean of the observed children.  Pinned by: a constant colour; the mean of the
+ * per-frame colours of a plane seen by a fixed camera, through merges. */
+int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_t width, int32_t height,
+                       const double K[4], const double T_ws[16]);
+
+/* Colours of all voxels, 3 per voxel, in the voxel order of orc_extract. */
+void orc_extract_color(const void* map, double* rgb);
+
 /* LiDAR ray fusion of one scan of n sensor-frame points (Eq. 1, 3, 5).
  * Pinned by: the exact voxel column of an axis-aligned beam holding clip(Zp - z); point-order
  * independence; free space merging to the coarsest level at exactly +tau; exact cell sets of the
