@@ -74,6 +74,9 @@ typedef struct mrh_config {
     int64_t heap_blocks[4];/* capacity of each level's block heap; 0 = max_blocks */
     int32_t storage;       /* MRH_STORE_* */
     int32_t max_probe;     /* linear-probe limit per lookup; 0 = 4096 */
+    int32_t color;         /* 1 = voxels also store a colour (RGB float32, 12 B per voxel); such a map
+                              fuses RGB-D frames through mrh_integrate_rgbd only, needs min_obs >= 2,
+                              and is not streamed or batched */
 } mrh_config;
 
 typedef struct mrh_stats {
@@ -127,6 +130,22 @@ mrh_status mrh_map_reset(mrh_map* map);
  * capacity errors are latched (see top). */
 mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
                                const double K[4], const double T_ws[16]);
+
+/* Fuse one RGB-D frame with colour into a map created with cfg.color = 1 (Sec. 3: a voxel stores a
+ * colour).  The depth part is exactly mrh_integrate_depth; then a separate colour launch takes, for
+ * every voxel the frame updated (the same projective decisions), the RGB value of its pixel into
+ * the voxel's colour, C <- C + (c - C) / W with the voxel's updated weight (Eq. 3 with w = 1), and
+ * pools the colour of a block the frame merged into its coarser block as the weighted mean of the
+ * observed children (as the TSDF is pooled).
+ *   rgb_dev: device uint8[height][width][3], interleaved, the same pixels as depth_dev.
+ * Errors as mrh_integrate_depth; MRH_ERR_INVALID_ARG on a map without colour. */
+mrh_status mrh_integrate_rgbd(mrh_map* map, const float* depth_dev, const uint8_t* rgb_dev, int32_t width,
+                              int32_t height, const double K[4], const double T_ws[16]);
+
+/* Colours of the map's voxels (device float32[n_voxels][3], RGB in [0, 255]; 0 where unobserved), in
+ * the voxel order of mrh_extract_blocks.  MRH_ERR_BUFFER_TOO_SMALL (count still set) when
+ * voxel_cap < n_voxels; rgb_dev NULL returns the count only.  Synchronises the stream. */
+mrh_status mrh_extract_color(mrh_map* map, float* rgb_dev, int64_t voxel_cap, int64_t* n_voxels);
 
 /* mrh_integrate_depth for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same two kernels and the same

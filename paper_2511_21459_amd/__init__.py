@@ -47,7 +47,7 @@ class Map:
                  min_obs: int = 2, max_depth: float = 1e9, min_range: float = 0.0,
                  max_range: float = 1e9, carve: bool = False, form: str = "range",
                  max_blocks: int = 1 << 18, hash_slots: int | None = None, heap_blocks=None,
-                 storage: str = "f32", max_probe: int = 0):
+                 storage: str = "f32", max_probe: int = 0, color: bool = False):
         L = _lib.load()
         cfg = MrhConfig()
         cfg.voxel = float(voxel)
@@ -68,6 +68,7 @@ class Map:
             cfg.heap_blocks[n] = int(hb[n]) if n < len(hb) else 0
         cfg.storage = STORAGE[storage]
         cfg.max_probe = int(max_probe)
+        cfg.color = int(bool(color))
         self.cfg = cfg
         self.stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -106,6 +107,28 @@ class Map:
         Ta, Tp = _host_doubles(T_ws, 16)
         self._check(_lib.load().mrh_integrate_depth(self._h, p, depth.shape[1], depth.shape[0], Kp, Tp),
                     "mrh_integrate_depth")
+
+    def integrate_rgbd(self, depth: torch.Tensor, rgb: torch.Tensor, K, T_ws):
+        """Fuse one RGB-D frame with colour (a map created with color=True): depth float32 [H, W]
+        and rgb uint8 [H, W, 3] on the GPU."""
+        if depth.dim() != 2 or tuple(rgb.shape) != tuple(depth.shape) + (3,):
+            raise ValueError("depth must be [H, W] and rgb [H, W, 3]")
+        p = _dev(depth, torch.float32, name="depth")
+        c = _dev(rgb, torch.uint8, name="rgb")
+        Ka, Kp = _host_doubles(K, 4)
+        Ta, Tp = _host_doubles(T_ws, 16)
+        self._check(_lib.load().mrh_integrate_rgbd(self._h, p, c, depth.shape[1], depth.shape[0], Kp, Tp),
+                    "mrh_integrate_rgbd")
+
+    def extract_color(self) -> torch.Tensor:
+        """float32 [voxels, 3] colours in the voxel order of extract()."""
+        n = ctypes.c_int64()
+        L = _lib.load()
+        self._check(L.mrh_extract_color(self._h, None, 0, ctypes.byref(n)), "mrh_extract_color")
+        out = torch.empty((n.value, 3), dtype=torch.float32, device=torch.device("cuda", torch.cuda.current_device()))
+        self._check(L.mrh_extract_color(self._h, ctypes.c_void_p(out.data_ptr()), n.value, ctypes.byref(n)),
+                    "mrh_extract_color")
+        return out
 
     def integrate_depth_noalloc(self, depth: torch.Tensor, K, T_ws):
         """integrate_depth through the entry point that allocates no device memory (the per-tile

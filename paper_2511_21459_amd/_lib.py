@@ -32,7 +32,7 @@ EXPORTS = [
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
     "mrh_integrate_depth_noalloc", "mrh_extract_mesh", "mrh_heap_usage", "mrh_stream_out", "mrh_stream_in",
     "mrh_store_info", "mrh_store_extract", "mrh_load_blocks", "mrh_quadtree_create", "mrh_quadtree_destroy",
-    "mrh_quadtree_build",
+    "mrh_quadtree_build", "mrh_integrate_rgbd", "mrh_extract_color",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
@@ -52,6 +52,7 @@ class MrhConfig(ctypes.Structure):
         ("min_range", ctypes.c_double), ("max_range", ctypes.c_double), ("carve", ctypes.c_int32),
         ("form", ctypes.c_int32), ("hash_slots", ctypes.c_int64), ("max_blocks", ctypes.c_int64),
         ("heap_blocks", ctypes.c_int64 * 4), ("storage", ctypes.c_int32), ("max_probe", ctypes.c_int32),
+        ("color", ctypes.c_int32),
     ]
 
 
@@ -110,6 +111,10 @@ def load():
     L.mrh_map_reset.argtypes = [P]
     L.mrh_integrate_depth.restype = i32
     L.mrh_integrate_depth.argtypes = [P, P, i32, i32, P, P]
+    L.mrh_integrate_rgbd.restype = i32
+    L.mrh_integrate_rgbd.argtypes = [P, P, P, i32, i32, P, P]
+    L.mrh_extract_color.restype = i32
+    L.mrh_extract_color.argtypes = [P, P, i64, ctypes.POINTER(i64)]
     L.mrh_quadtree_create.restype = i32
     L.mrh_quadtree_create.argtypes = [i32, i32, P, ctypes.POINTER(P)]
     L.mrh_quadtree_destroy.restype = None

@@ -224,7 +224,7 @@ mrh_status mrh_batch_create(mrh_map* const* maps, int32_t n_maps, mrh_batch** ou
         // one stream for every map: the batch enqueues on it, and the autotuner's per-map resets
         // must be ordered with the batched launches
         if (!maps[i] || maps[i]->device != maps[0]->device || maps[i]->cfg.storage != maps[0]->cfg.storage ||
-            maps[i]->stream != maps[0]->stream)
+            maps[i]->stream != maps[0]->stream || maps[i]->cfg.color)
             return MRH_ERR_INVALID_ARG;
         for (int j = 0; j < i; ++j)
             if (maps[j] == maps[i]) return MRH_ERR_INVALID_ARG;

@@ -105,8 +105,11 @@ __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restric
 
 using namespace mrh;
 
-extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
-                                          const double K[4], const double T_ws[16]) {
+namespace mrh {
+// The two launches of one RGB-D frame; the frame descriptor is returned for a launch that follows
+// on the same frame (colour).
+mrh_status integrate_depth_frame(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                                 const double K[4], const double T_ws[16], DepthFrame* frame_out) {
     if (!map || !depth_dev || !K || !T_ws || !depth_size_ok(width, height)) return MRH_ERR_INVALID_ARG;
     DepthFrame f;
     if (!make_depth_frame(map->cfg, depth_dev, width, height, K, T_ws, f))
@@ -129,7 +132,16 @@ extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, 
             default: hipLaunchKernelGGL(k_integrate_depth<MRH_STORE_F32>, g, b, 0, map->stream, map->dmd, f);
         }
     });
+    if (frame_out) *frame_out = f;
     return check_hip(map, hipGetLastError(), "integrate_depth");
+}
+}  // namespace mrh
+
+extern "C" mrh_status mrh_integrate_depth(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                                          const double K[4], const double T_ws[16]) {
+    if (map && map->cfg.color)
+        return set_error(map, MRH_ERR_INVALID_ARG, "a map with colour fuses RGB-D frames through mrh_integrate_rgbd");
+    return integrate_depth_frame(map, depth_dev, width, height, K, T_ws, nullptr);
 }
 
 // ---- the variant that allocates nothing ------------------------------------------------------
@@ -167,6 +179,8 @@ static hipError_t scratch_address(int device, float** out) {
 extern "C" mrh_status mrh_integrate_depth_noalloc(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
                                                   const double K[4], const double T_ws[16]) {
     if (!map || !depth_dev || !K || !T_ws || !depth_size_ok(width, height)) return MRH_ERR_INVALID_ARG;
+    if (map->cfg.color)
+        return set_error(map, MRH_ERR_INVALID_ARG, "a map with colour fuses RGB-D frames through mrh_integrate_rgbd");
     const size_t tiles_need = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
     if (tiles_need > kScratchTiles)
         return set_error(map, MRH_ERR_INVALID_ARG, "frame of %d x %d pixels has %zu tiles; the no-allocation entry point "

@@ -145,7 +145,7 @@ static void free_all(mrh_map* m) {
     for (int n = 0; n < 4; ++n)
         if (d.vis[n]) (void)hipFree(d.vis[n]);
     for (int n = 0; n < 4; ++n) {
-        void* lp[] = {d.stack[n], d.pend[n], d.D[n], d.W[n], d.S2[n], d.acc_sat[n], d.acc_band[n], d.acc_s1[n], d.acc_s2[n]};
+        void* lp[] = {d.stack[n], d.pend[n], d.D[n], d.W[n], d.S2[n], d.C[n], d.acc_sat[n], d.acc_band[n], d.acc_s1[n], d.acc_s2[n]};
         for (void* p : lp)
             if (p) (void)hipFree(p);
     }
@@ -159,7 +159,8 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
     if (!(c.voxel > 0.0) || !std::isfinite(c.voxel) || c.levels < 1 || c.levels > 4 || !(c.tau > 0.0) ||
         c.min_obs < 1 || !pow2 || c.max_blocks < 1 || c.hash_slots < 2 * c.max_blocks ||
         c.hash_slots > (int64_t(1) << 31) || c.max_blocks > (int64_t(1) << 30) || !(c.var_thr >= 0.0) ||
-        c.storage < MRH_STORE_F32 || c.storage > MRH_STORE_BF16 || c.form < 0 || c.form > 1)
+        c.storage < MRH_STORE_F32 || c.storage > MRH_STORE_BF16 || c.form < 0 || c.form > 1 || c.color < 0 ||
+        c.color > 1 || (c.color && c.min_obs < 2))
         return MRH_ERR_INVALID_ARG;
     for (int n = 0; n < 4; ++n)
         if (c.heap_blocks[n] < 0 || c.heap_blocks[n] > (int64_t)kSlotMask + 1) return MRH_ERR_INVALID_ARG;
@@ -226,6 +227,7 @@ mrh_status mrh_map_create(const mrh_config* cfg, void* stream, mrh_map** out) {
         alloc((void**)&d.D[n], nv * pb, "TSDF heap");
         alloc((void**)&d.W[n], nv * pb, "weight heap");
         alloc((void**)&d.S2[n], nv * pb, "variance heap");
+        if (c.color) alloc((void**)&d.C[n], nv * 12, "colour heap");
     }
     m->partials_cap = 1024;
     alloc((void**)&m->partials, (size_t)m->partials_cap * 6 * 8, "reduction partials");

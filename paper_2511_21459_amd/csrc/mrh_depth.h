@@ -34,6 +34,11 @@ struct DepthFrame {
 // Host: frame sizes the kernels accept (pixel indices 32-bit, pixel coordinates exact in FP32).
 bool depth_size_ok(int32_t width, int32_t height);
 
+// Host: enqueue the allocation and update launches of one RGB-D frame (no colour check);
+// *frame_out (may be NULL) receives the frame's descriptor.
+mrh_status integrate_depth_frame(mrh_map* map, const float* depth_dev, int32_t width, int32_t height,
+                                 const double K[4], const double T_ws[16], DepthFrame* frame_out);
+
 // Host: fill a frame descriptor; false on a non-finite pose or intrinsics or a zero focal length.
 bool make_depth_frame(const mrh_config& cfg, const float* depth, int32_t width, int32_t height, const double K[4],
                       const double T_ws[16], DepthFrame& f);

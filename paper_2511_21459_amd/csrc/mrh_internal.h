@@ -86,6 +86,7 @@ struct DevMap {
     void* D[4];   // per level, plane of the storage format (see mrh_store.h)
     void* W[4];
     void* S2[4];
+    float* C[4];  // per level, colour RGB float32 x 3 per voxel (maps created with colour; else null)
     // LiDAR per-frame accumulators, parallel to the heaps (zero between frames):
     // saturated (+tau) observation counts, band observation counts, and fixed-point sums of
     // (d - D) and (d - D)^2 relative to the voxel's mean at the start of the frame

@@ -96,6 +96,7 @@ using namespace mrh;
 
 extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, int64_t n, const double T_ws[16]) {
     if (!map || !T_ws || n < 0 || (n > 0 && !xyz_dev)) return MRH_ERR_INVALID_ARG;
+    if (map->cfg.color) return set_error(map, MRH_ERR_INVALID_ARG, "a map with colour fuses RGB-D frames only");
     ScanParams sp;
     if (!pose_from(T_ws, sp.P)) return set_error(map, MRH_ERR_INVALID_ARG, "non-finite pose");
     sp.xyz = xyz_dev;

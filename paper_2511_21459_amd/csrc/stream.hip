@@ -448,6 +448,7 @@ mrh_status mrh_heap_usage(mrh_map* map, double* frac) {
 
 mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double threshold, int64_t* n_out) {
     if (!map || !region || !n_out || !(threshold >= 0.0)) return MRH_ERR_INVALID_ARG;
+    if (map->cfg.color) return set_error(map, MRH_ERR_INVALID_ARG, "maps with colour are not streamed");
     *n_out = 0;
     Region r;
     if (!make_region(map, region, r)) return set_error(map, MRH_ERR_INVALID_ARG, "invalid streaming region");
@@ -506,6 +507,7 @@ mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double thresho
 
 mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in) {
     if (!map || !region || !n_in) return MRH_ERR_INVALID_ARG;
+    if (map->cfg.color) return set_error(map, MRH_ERR_INVALID_ARG, "maps with colour are not streamed");
     *n_in = 0;
     Region r;
     if (!make_region(map, region, r)) return set_error(map, MRH_ERR_INVALID_ARG, "invalid streaming region");
@@ -597,6 +599,7 @@ mrh_status mrh_store_extract(mrh_map* map, int32_t* keys, uint8_t* levels, int64
 mrh_status mrh_load_blocks(mrh_map* map, int64_t n, const int32_t* keys, const uint8_t* levels, const float* D,
                            const uint32_t* W, const float* S2, int64_t* n_loaded) {
     if (!map || n < 0 || !n_loaded || (n > 0 && (!keys || !levels || !D || !W || !S2))) return MRH_ERR_INVALID_ARG;
+    if (map->cfg.color) return set_error(map, MRH_ERR_INVALID_ARG, "maps with colour are not streamed");
     *n_loaded = 0;
     if (n == 0) return MRH_OK;
     const int st = map->cfg.storage, pb = plane_bytes(st);
