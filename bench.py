@@ -376,13 +376,26 @@ def run_street(args, torch, np, mrh, configs):
     m.close()
     valid = sum(f["valid_points"] for f in census)
     obs = sum(f["observations"] for f in census)
+    distinct = sum(f["distinct_voxels"] for f in census)
+    queued = sum(f["queued_blocks"] for f in census)
     rays_ms = prof["rays"][0] / prof["rays"][1]
+    # the scan's algorithmic HBM bytes: each input point read once (12 B), each distinct updated
+    # voxel's state read and written once (2 x 12 B), each touched block's queue entry (16 B)
+    scan_bytes = 12 * pts.shape[1] * n + 2 * STATE_BYTES["f32"] * distinct + 16 * queued
+    scan_s = sum(prof[k][0] for k in ("alloc_points", "rays", "apply_points")) / 1e3
+    achieved = scan_bytes / scan_s / 1e9
     return dict(pts=pts, poses=poses, n=n, out={
         "workload": f"street LiDAR, {n} scans of 64x2048 points, 5/10/20/40 cm levels, carving, tau 15 cm",
         "valid_points_per_step": valid, "observations_per_step": obs, "blocks_at_end": census[-1]["blocks"],
         "ms_per_step": round(t * 1e3, 3), "ms_per_scan": round(t * 1e3 / n, 3),
         "m_points_per_s": round(valid / t / 1e6, 3), "g_observations_per_s": round(obs / t / 1e9, 4),
         "kernels_ms_per_scan": {k: round(v[0] / n, 4) for k, v in prof.items()},
+        "distinct_voxels_per_step": distinct, "queued_blocks_per_step": queued,
+        "candidate_keys_per_step": sum(f["candidate_keys"] for f in census),
+        "roofline": {"kernel": "scan (k_alloc_points + k_rays + k_apply_points)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_scan": int(scan_bytes / n), "kernel_ms_per_scan": round(scan_s * 1e3 / n, 4)},
         "rays_kernel": {"bound": "atomics/latency", "avg_launch_ms": round(rays_ms, 4),
                         "observations_per_s_g": round(obs / n / (rays_ms / 1e3) / 1e9, 3)}})
 

@@ -91,6 +91,11 @@ typedef struct mrh_stats {
     int64_t blocks;         /* distinct blocks in the map after the frame */
     uint32_t error_flags;   /* bit 0 table full, bit 1 heap full, bit 2 block limit */
     uint32_t reserved;
+    int64_t distinct_voxels;/* voxels that received at least one observation (per frame; RGB-D: the
+                               observations, LiDAR: fewer, a voxel crossed by several rays counts once) */
+    int64_t candidate_keys; /* block keys the allocation walks produced, before deduplication */
+    int64_t queued_blocks;  /* blocks queued for the update: RGB-D, the existing blocks the visibility
+                               cull keeps (new blocks are updated too); LiDAR, the blocks rays touched */
 } mrh_stats;
 
 typedef struct mrh_map mrh_map;
@@ -185,6 +190,37 @@ mrh_status mrh_integrate_points_sequence(mrh_map* map, const float* xyz_dev, int
  * creation or reset.  last / totals may be NULL.  Returns the first latched capacity error
  * (MRH_ERR_TABLE_FULL, MRH_ERR_HEAP_FULL, MRH_ERR_BLOCK_LIMIT) or MRH_OK, and clears the latch. */
 mrh_status mrh_sync(mrh_map* map, mrh_stats* last, mrh_stats* totals);
+
+/* Consistency of the map's bookkeeping (Sec. 3.1: the spatial hash of Eq. 4 from block keys to
+ * blocks, and the per-level voxel heaps whose slots the blocks hold), for tests and debugging.
+ * Waits for the stream, copies the hash table, the block rows, the free stacks and the pending-
+ * free lists to host memory (about 25 bytes per hash slot and block row) and checks them against
+ * each other; the device is not changed.  Call between frames.  Returns MRH_OK when the check ran
+ * (out filled; out->consistent says whether every violation count is zero), or a HIP error.
+ * With a latched capacity error the counts describe the degraded map and need not be zero. */
+typedef struct mrh_check {
+    int64_t blocks;            /* block rows handed out (up to max_blocks) */
+    int64_t live_blocks;       /* rows holding a heap slot */
+    int64_t slotless_blocks;   /* rows whose key found its level-0 heap empty */
+    int64_t gone_blocks;       /* rows streamed out to the host store */
+    int64_t table_keys;        /* keys in the hash table */
+    int64_t tombstones;        /* table slots of streamed-out keys */
+    int64_t idless_keys;       /* table keys inserted when the block table was full */
+    int64_t free_slots[4];     /* free-stack entries per level */
+    int64_t pending_slots[4];  /* slots freed by the last frame, returned by the next one */
+    double mean_probe;         /* mean probe length of the present keys, slots (1 = home slot) */
+    int32_t max_probe;         /* longest one */
+    int32_t consistent;        /* 1 when the five counts below are all zero */
+    /* violations */
+    int64_t duplicate_keys;    /* a key in two table slots */
+    int64_t unreachable_keys;  /* keys a probe from the home slot misses (empty slot first, beyond the
+                                  probe limit) and rows the table does not lead to */
+    int64_t bad_table_entries; /* table entries naming a row out of range, streamed out, or with
+                                  another key */
+    int64_t slot_conflicts;    /* heap slots out of range or claimed twice (rows, stacks, lists) */
+    int64_t lost_slots;        /* heap slots neither held, free nor pending */
+} mrh_check;
+mrh_status mrh_map_check(mrh_map* map, mrh_check* out);
 
 /* Trilinear SDF query (Sec. 3.4).  For each point p_i (device float32[n][3]) the world point is
  * x = T_wq p (T_wq host double[16] or NULL for identity).  The point's block fixes the lattice

@@ -85,7 +85,9 @@ class _Config(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("valid_points", ctypes.c_int64), ("new_blocks", ctypes.c_int64),
                 ("observations", ctypes.c_int64), ("dropped_points", ctypes.c_int64),
-                ("merges", ctypes.c_int64 * 4), ("near_threshold", ctypes.c_int64)]
+                ("merges", ctypes.c_int64 * 4), ("near_threshold", ctypes.c_int64),
+                ("distinct_voxels", ctypes.c_int64), ("candidate_keys", ctypes.c_int64),
+                ("touched_blocks", ctypes.c_int64)]
 
 
 def _p(a: np.ndarray):
@@ -154,7 +156,9 @@ class OracleMap:
         lib().orc_last_stats(self._h, ctypes.byref(s))
         return {"valid_points": s.valid_points, "new_blocks": s.new_blocks,
                 "observations": s.observations, "dropped_points": s.dropped_points,
-                "merges": list(s.merges), "near_threshold": s.near_threshold}
+                "merges": list(s.merges), "near_threshold": s.near_threshold,
+                "distinct_voxels": s.distinct_voxels, "candidate_keys": s.candidate_keys,
+                "touched_blocks": s.touched_blocks}
 
     @property
     def num_blocks(self) -> int:

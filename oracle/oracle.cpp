@@ -203,6 +203,7 @@ bool in_key_range(const double a[3], const double e[3], double invB) {
 void allocate(Map& m, const double a[3], const double e[3]) {
     std::vector<std::array<int64_t, 3>> cells;
     block_walk(a, e, m.invB, cells);
+    m.last.candidate_keys += (int64_t)cells.size();
     for (const auto& c : cells) {
         const Key k{(int32_t)c[0], (int32_t)c[1], (int32_t)c[2]};
         auto it = m.blocks.find(k);
@@ -750,6 +751,7 @@ int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_
         const Key& b = kv.first;
         Block& blk = kv.second;
         const int mm = side(blk.level);
+        const int64_t obs_before = m.last.observations;
         for (int k = 0; k < mm; ++k)
             for (int j = 0; j < mm; ++j)
                 for (int i = 0; i < mm; ++i) {
@@ -778,6 +780,7 @@ int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_
                     const int vi = i + mm * (j + mm * k);
                     observe(blk, vi, obs);
                     m.last.observations++;
+                    m.last.distinct_voxels++; /* one pixel per voxel: each update is a distinct voxel */
                     if (rgb) {
                         /* colour of the same pixel, averaged like the TSDF (Eq. 3 with w = 1) */
                         const size_t px = 3 * ((size_t)fv * width + (size_t)fu);
@@ -788,6 +791,7 @@ int orc_integrate_rgbd(void* map, const float* depth, const uint8_t* rgb, int32_
                         }
                     }
                 }
+        if (m.last.observations > obs_before) m.last.touched_blocks++;
     }
 
     /* 4: variance and merging criterion. */
@@ -835,6 +839,7 @@ int orc_integrate_points(void* map, const float* xyz, int64_t n, const double T_
      * (Eq. 1); observations are applied in point order, then in walk order along each ray. */
     std::vector<std::array<int64_t, 3>> cells;
     std::vector<std::array<int, 3>> vox;
+    std::map<Key, std::vector<char>> seen; /* voxels observed this scan, for the distinct count */
     for (const Seg& s : segs) {
         cells.clear();
         block_walk(s.a, s.e, m.invB, cells);
@@ -849,11 +854,20 @@ int orc_integrate_points(void* map, const float* xyz, int64_t n, const double T_
                 voxel_centre(m, b, blk.level, v[0], v[1], v[2], x);
                 const double sd = ((s.p[0] - x[0]) * s.n[0] + (s.p[1] - x[1]) * s.n[1]) + (s.p[2] - x[2]) * s.n[2];
                 const double obs = sd < -tau ? -tau : (sd > tau ? tau : sd);
-                observe(blk, v[0] + mm * (v[1] + mm * v[2]), obs);
+                const int vi = v[0] + mm * (v[1] + mm * v[2]);
+                observe(blk, vi, obs);
                 m.last.observations++;
+                std::vector<char>& sv = seen[b];
+                if (sv.empty()) sv.assign((size_t)mm * mm * mm, 0);
+                if (!sv[(size_t)vi]) {
+                    sv[(size_t)vi] = 1;
+                    m.last.distinct_voxels++;
+                }
             }
         }
     }
+
+    m.last.touched_blocks = (int64_t)seen.size();
 
     /* 4: variance and merging criterion. */
     variance_and_merge(m);

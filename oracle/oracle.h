@@ -39,6 +39,9 @@ typedef struct orc_stats {
     int64_t dropped_points;    /* valid points whose segment left the key range */
     int64_t merges[4];         /* merges out of level n this frame */
     int64_t near_threshold;    /* merge decisions with |mv - thr| / thr < 1e-3 this frame */
+    int64_t distinct_voxels;   /* voxels with at least one observation this frame */
+    int64_t candidate_keys;    /* block keys the allocation walks visited, repeats included */
+    int64_t touched_blocks;    /* blocks with at least one observed voxel this frame */
 } orc_stats;
 
 void* orc_create(const orc_config* cfg);

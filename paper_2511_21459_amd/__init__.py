@@ -276,6 +276,14 @@ class Map:
         return out
 
 
+    def check(self) -> dict:
+        """Consistency of the hash table, the block rows and the heaps' free stacks and pending
+        lists (host copies; between frames).  'consistent' is True when no violation was found;
+        'mean_probe' / 'max_probe' give the probe lengths of the present keys."""
+        c = _lib.MrhCheck()
+        self._check(_lib.load().mrh_map_check(self._h, ctypes.byref(c)), "mrh_map_check")
+        return c.as_dict()
+
     # -- streaming (capacity-driven, between the heaps and the map's host store) -------------
     def heap_usage(self) -> float:
         f = ctypes.c_double()

@@ -32,7 +32,7 @@ EXPORTS = [
     "mrh_batch_get_launch", "mrh_batch_autotune", "mrh_integrate_depth_sequence", "mrh_integrate_points_sequence",
     "mrh_integrate_depth_noalloc", "mrh_extract_mesh", "mrh_heap_usage", "mrh_stream_out", "mrh_stream_in",
     "mrh_store_info", "mrh_store_extract", "mrh_load_blocks", "mrh_quadtree_create", "mrh_quadtree_destroy",
-    "mrh_quadtree_build", "mrh_integrate_rgbd", "mrh_extract_color",
+    "mrh_quadtree_build", "mrh_integrate_rgbd", "mrh_extract_color", "mrh_map_check",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
@@ -63,6 +63,7 @@ class MrhStats(ctypes.Structure):
         ("failed_inserts", ctypes.c_int64), ("fresh_observations", ctypes.c_int64),
         ("blocks", ctypes.c_int64), ("error_flags", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("distinct_voxels", ctypes.c_int64), ("candidate_keys", ctypes.c_int64), ("queued_blocks", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -70,8 +71,28 @@ class MrhStats(ctypes.Structure):
                 "dropped_points": self.dropped_points, "new_blocks": self.new_blocks,
                 "observations": self.observations, "merges": list(self.merges),
                 "failed_inserts": self.failed_inserts, "fresh_observations": self.fresh_observations,
-                "blocks": self.blocks,
+                "blocks": self.blocks, "distinct_voxels": self.distinct_voxels,
+                "candidate_keys": self.candidate_keys, "queued_blocks": self.queued_blocks,
                 "error_flags": self.error_flags}
+
+
+class MrhCheck(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int64), ("live_blocks", ctypes.c_int64), ("slotless_blocks", ctypes.c_int64),
+        ("gone_blocks", ctypes.c_int64), ("table_keys", ctypes.c_int64), ("tombstones", ctypes.c_int64),
+        ("idless_keys", ctypes.c_int64), ("free_slots", ctypes.c_int64 * 4), ("pending_slots", ctypes.c_int64 * 4),
+        ("mean_probe", ctypes.c_double), ("max_probe", ctypes.c_int32), ("consistent", ctypes.c_int32),
+        ("duplicate_keys", ctypes.c_int64), ("unreachable_keys", ctypes.c_int64),
+        ("bad_table_entries", ctypes.c_int64), ("slot_conflicts", ctypes.c_int64), ("lost_slots", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name.endswith("_slots") and not isinstance(v, int) else v
+        out["consistent"] = bool(self.consistent)
+        return out
 
 
 class MrhFrame(ctypes.Structure):
@@ -121,6 +142,8 @@ def load():
     L.mrh_quadtree_destroy.argtypes = [P]
     L.mrh_quadtree_build.restype = i32
     L.mrh_quadtree_build.argtypes = [P, P, i32, i32, ctypes.c_double, i32, P, P, i64, ctypes.POINTER(i64)]
+    L.mrh_map_check.restype = i32
+    L.mrh_map_check.argtypes = [P, ctypes.POINTER(MrhCheck)]
     L.mrh_heap_usage.restype = i32
     L.mrh_heap_usage.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     L.mrh_stream_out.restype = i32

@@ -90,14 +90,14 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
     const CEntry* ce = (const CEntry*)ents;
     __shared__ TaskCounts cnt[kMaxBatch];
     __shared__ uint32_t pre[kMaxBatch + 1];
-    __shared__ unsigned long long wst[kMaxBatch][5];
+    __shared__ unsigned long long wst[kMaxBatch][6];
     if ((int)blockIdx.x < n && ents[blockIdx.x].kind == KIND)
         update_duties(maps[blockIdx.x], entry_parity(ents[blockIdx.x]));
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         if (ents[i].kind != KIND) cnt[i] = TaskCounts{{0u, 0u, 0u, 0u}, 0u, 0u};
         else cnt[i] = frame_task_counts(maps[i], KIND == MRH_FRAME_DEPTH, entry_parity(ents[i]));
     }
-    for (int k = threadIdx.x; k < 5 * n; k += blockDim.x) wst[k / 5][k % 5] = 0ull;
+    for (int k = threadIdx.x; k < 6 * n; k += blockDim.x) wst[k / 6][k % 6] = 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
         pre[0] = 0;
@@ -118,6 +118,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
             atomicAdd(&wst[i][2], ts.merge0);
             atomicAdd(&wst[i][3], ts.merge1);
             atomicAdd(&wst[i][4], ts.merge2);
+            atomicAdd(&wst[i][5], KIND == MRH_FRAME_DEPTH ? ts.obs : ts.distinct);
         }
     };
     for (uint32_t t = wave; t < total; t += nwaves) {
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(256) void k_batch_update(const DevMap* __restrict__
     }
     if (cur >= 0) flush(cur);
     __syncthreads();
-    const int sid[5] = {S_OBS, S_OBS_FRESH, S_MERGE0, S_MERGE1, S_MERGE2};
-    for (int k = threadIdx.x; k < 5 * n; k += blockDim.x)
-        if (wst[k / 5][k % 5]) stat_add(maps[k / 5], sid[k % 5], wst[k / 5][k % 5]);
+    const int sid[6] = {S_OBS, S_OBS_FRESH, S_MERGE0, S_MERGE1, S_MERGE2, S_DISTINCT};
+    for (int k = threadIdx.x; k < 6 * n; k += blockDim.x)
+        if (wst[k / 6][k % 6]) stat_add(maps[k / 6], sid[k % 6], wst[k / 6][k % 6]);
 }
 
 

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_integrate_depth(const DevMap* __restric
     const uint32_t ntask = update_task_count(n);
     TaskStats ts;
     for (uint32_t t = wave; t < ntask; t += nwaves) ts.add(depth_update_task<ST>(m, f, t, n));
-    flush_task_stats(m, ts);
+    flush_task_stats(m, ts, true);
 }
 
 }  // namespace mrh

@@ -285,6 +285,9 @@ static void fill_stats(const unsigned long long* s, unsigned long long frames, u
     for (int n = 0; n < 4; ++n) out->merges[n] = (int64_t)s[S_MERGE0 + n];
     out->failed_inserts = (int64_t)s[S_FAILED];
     out->fresh_observations = (int64_t)s[S_OBS_FRESH];
+    out->distinct_voxels = (int64_t)s[S_DISTINCT];
+    out->candidate_keys = (int64_t)s[S_CAND];
+    out->queued_blocks = (int64_t)s[S_QUEUED];
     out->blocks = (int64_t)nblocks;
     out->error_flags = flags;
 }

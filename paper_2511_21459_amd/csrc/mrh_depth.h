@@ -242,13 +242,13 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
         in_range = segment_in_range(a, e, m.invB);
         if (in_range) w.init(a, e, m.invB);
     }
-    __shared__ uint32_t cnt[2];
+    __shared__ uint32_t cnt[3];
     __shared__ float tmx[4];
     __shared__ unsigned long long nkey[kTileNew];
     __shared__ uint32_t nslot[kTileNew];
     __shared__ uint32_t ncount;
     __shared__ unsigned long long nold;
-    if (threadIdx.x == 0) cnt[0] = cnt[1] = ncount = 0;
+    if (threadIdx.x == 0) cnt[0] = cnt[1] = cnt[2] = ncount = 0;
     const float wmax = wave_max(ok ? (float)d : -1.0f);
     if (lane == 0) tmx[wave] = wmax;
     __syncthreads();
@@ -258,7 +258,9 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
         atomicAdd(&cnt[1], (uint32_t)__popcll(dmask));
     }
     bool active = in_range;
-    while (__ballot(active)) {
+    uint32_t ncand = 0;  // keys this wave's walks produce (wave-uniform)
+    while (unsigned long long amask = __ballot(active)) {
+        ncand += (uint32_t)__popcll(amask);
         const unsigned long long key = active ? pack_key(w.c0, w.c1, w.c2) : 0ull;
         uint32_t slot = 0;
         const bool is_new = claim_keys(m, active, key, &slot);
@@ -281,6 +283,7 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
         }
         if (active) active = w.next();
     }
+    if (lane == 0 && ncand) atomicAdd(&cnt[2], ncand);
     __syncthreads();
     const uint32_t nnew = ncount < (uint32_t)kTileNew ? ncount : (uint32_t)kTileNew;
     if (threadIdx.x == 0 && nnew) nold = take_new_blocks(m, nnew);
@@ -290,6 +293,7 @@ __device__ inline void depth_alloc_tile(const DevMap& m, const DepthFrame& f, ui
     if (threadIdx.x == 0) {
         stat_add(m, S_VALID, cnt[0]);
         stat_add(m, S_DROPPED, cnt[1]);
+        stat_add(m, S_CAND, cnt[2]);
         f.tile_max[tile] = __builtin_fmaxf(__builtin_fmaxf(tmx[0], tmx[1]), __builtin_fmaxf(tmx[2], tmx[3]));
     }
 }

@@ -32,7 +32,8 @@ constexpr uint32_t kNoBlockBit = 1u << 31;
 constexpr uint32_t kErrTableFull = 1u, kErrHeapFull = 2u, kErrBlockLimit = 4u;
 
 // per-frame statistics slots (u64)
-enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, S_MERGE3, S_FAILED, S_OBS_FRESH, S_COUNT };
+enum Stat { S_VALID = 0, S_DROPPED, S_NEW, S_OBS, S_MERGE0, S_MERGE1, S_MERGE2, S_MERGE3, S_FAILED, S_OBS_FRESH,
+            S_DISTINCT, S_CAND, S_QUEUED, S_COUNT };
 
 // Per-frame statistics are accumulated in kStripes cache-line-sized stripes (a workgroup adds to
 // the stripe of its index) so that atomics from different workgroups rarely meet on one line; the
@@ -94,7 +95,9 @@ struct DevMap {
     uint32_t* acc_band[4];
     unsigned long long* acc_s1[4];
     unsigned long long* acc_s2[4];
-    uint32_t* btouch;  // per block: touched by a ray this frame
+    // per block: the lane groups rays touched this frame, bit g = the voxels lane g of the update
+    // owns (level 0: Morton positions 8g .. 8g+7, level 1: position g; levels 2, 3: bit 0)
+    unsigned long long* btouch;
     // LiDAR: the block keys each ray's walk visits, in walk order (rcap_k per ray, written by the
     // allocation launch), and their count per ray (may exceed rcap_k)
     unsigned long long* rkeys;

@@ -112,6 +112,8 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (mine && i < sp.n) m.rcount[i] = steps;
+    const int ncand = wave_sum(mine ? (int)steps : 0);
+    if (lane == 0 && ncand) stat_add(m, S_CAND, (unsigned long long)ncand);
 }
 
 // Saturated (+tau) observations of voxels near the sensor origin are first counted in a
@@ -262,32 +264,42 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
     const uint32_t id = find_block(m, key);
     const uint32_t info = id == kInvalidId ? kNoBlockBit : m.binfo[id];
     const int level = (int)((info >> kLevelShift) & 3u);
-    // first touch of the block in this scan: queue it for the update (active lanes only)
-    const bool first = !(info & kNoBlockBit) && m.btouch[id] == 0u && atomicExch(&m.btouch[id], 1u) == 0u;
-    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key, sp.parity);
-    if (info & kNoBlockBit) return;
-    const bool fresh = (info & kNewBit) != 0;
-    const int side = 8 >> level;
-    const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
-    const double nu = m.nu[level];
-    BoxWalk bw;
-    bw.init(a, e, b, m.B, m.inv_nu[level], side);
-    for (int s = 0;; ++s) {
-        // observation of the voxel centre (Eq. 1)
-        const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
-        const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
-        const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
-        const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
-        const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
-        bool near = false;
-        if (d >= m.tau) {
-            const double r0 = x0 - sp.P.t[0], r1 = x1 - sp.P.t[1], r2 = x2 - sp.P.t[2];
-            const double il = m.inv_nu[level];
-            near = ((r0 * r0 + r1 * r1) + r2 * r2) * (il * il) < kSatNear2;
+    const bool has = !(info & kNoBlockBit);
+    unsigned long long groups = 0ull;  // the update's lane groups this ray touches in the block
+    if (has) {
+        const bool fresh = (info & kNewBit) != 0;
+        const int side = 8 >> level;
+        const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
+        const double nu = m.nu[level];
+        BoxWalk bw;
+        bw.init(a, e, b, m.B, m.inv_nu[level], side);
+        for (int s = 0;; ++s) {
+            // observation of the voxel centre (Eq. 1)
+            const double x0 = (double)b[0] * m.B + ((double)bw.c0 + 0.5) * nu;
+            const double x1 = (double)b[1] * m.B + ((double)bw.c1 + 0.5) * nu;
+            const double x2 = (double)b[2] * m.B + ((double)bw.c2 + 0.5) * nu;
+            const double sd = ((p[0] - x0) * nn[0] + (p[1] - x1) * nn[1]) + (p[2] - x2) * nn[2];
+            const double d = sd < -m.tau ? -m.tau : (sd > m.tau ? m.tau : sd);
+            bool near = false;
+            if (d >= m.tau) {
+                const double r0 = x0 - sp.P.t[0], r1 = x1 - sp.P.t[1], r2 = x2 - sp.P.t[2];
+                const double il = m.inv_nu[level];
+                near = ((r0 * r0 + r1 * r1) + r2 * r2) * (il * il) < kSatNear2;
+            }
+            const uint32_t mo = morton3(bw.c0, bw.c1, bw.c2);
+            groups |= 1ull << (level == 0 ? mo >> 3 : (level == 1 ? mo : 0u));
+            accumulate<ST>(m, level, base + (size_t)mo, fresh, d, near, tab);
+            if (s == 3 * side || !bw.next()) break;
         }
-        accumulate<ST>(m, level, base + (size_t)morton3(bw.c0, bw.c1, bw.c2), fresh, d, near, tab);
-        if (s == 3 * side || !bw.next()) break;
     }
+    // mark the groups; the ray that sets the block's first bit this scan queues it for the update
+    // (exactly one: the walk observes at least one voxel, so groups != 0)
+    bool first = false;
+    if (has) {
+        const unsigned long long cur = m.btouch[id];
+        if ((cur & groups) != groups) first = atomicOr(&m.btouch[id], groups) == 0ull;
+    }
+    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key, sp.parity);
 }
 
 // Rays per wave of the ray launch, and per 256-thread workgroup.
@@ -392,8 +404,10 @@ __device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par, D
     const uint32_t bvc = m.bvcnt[id];
     const bool fresh = (info & kNewBit) != 0;
     const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
-    uint32_t ns[8], nb[8];
-    {
+    // lanes whose group no ray touched have zero accumulators: they read nothing
+    const unsigned long long touched = m.btouch[id];
+    uint32_t ns[8] = {0, 0, 0, 0, 0, 0, 0, 0}, nb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if ((touched >> lane) & 1ull) {
         const uint4* a = reinterpret_cast<const uint4*>(m.acc_sat[0] + base);
         const uint4* b = reinterpret_cast<const uint4*>(m.acc_band[0] + base);
         const uint4 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
@@ -412,7 +426,8 @@ __device__ inline TaskOut apply_fine(const DevMap& m, const uint4 eq, int par, D
     TaskOut out;
     out.obs = (uint32_t)wobs;
     out.fresh = fresh ? (uint32_t)wobs : 0u;
-    if (lane == 0) m.btouch[id] = 0u;
+    out.distinct = (uint32_t)wave_sum((int)__popc(upd));
+    if (lane == 0) m.btouch[id] = 0ull;
     float D[8], S2[8];
     uint32_t W[8];
     bool have = false;
@@ -472,14 +487,15 @@ __device__ inline TaskOut apply_level1(const DevMap& m, const uint4 eq, int par,
     const double bvs = m.bvsum[id];
     const uint32_t bvc = m.bvcnt[id];
     const size_t at = (size_t)(info & kSlotMask) * 64 + lane;
-    uint32_t ns, nb;
-    unsigned long long s1, s2;
-    take_accumulators(m, 1, at, ns, nb, s1, s2);
-    if (lane == 0) m.btouch[id] = 0u;
+    uint32_t ns = 0, nb = 0;
+    unsigned long long s1 = 0ull, s2 = 0ull;
+    if ((m.btouch[id] >> lane) & 1ull) take_accumulators(m, 1, at, ns, nb, s1, s2);
+    if (lane == 0) m.btouch[id] = 0ull;
     const bool upd = ns + nb > 0;
     const int wobs = wave_sum((int)(ns + nb));
     TaskOut out;
     out.obs = (uint32_t)wobs;
+    out.distinct = (uint32_t)wave_sum(upd ? 1 : 0);
     float D, S2;
     uint32_t W;
     Store<ST>::get(m, 1, at, D, W, S2);
@@ -514,7 +530,7 @@ __device__ inline TaskOut apply_packed(const DevMap& m, const uint4* list, uint3
         info = e.y;
         const size_t at = (size_t)(info & kSlotMask) * seg + (lane % seg);
         take_accumulators(m, level, at, ns, nb, s1, s2);
-        if (lane % seg == 0) m.btouch[id] = 0u;
+        if (lane % seg == 0) m.btouch[id] = 0ull;
         Store<ST>::get(m, level, at, D, W, S2);
     }
     const bool upd = ns + nb > 0;
@@ -530,6 +546,7 @@ __device__ inline TaskOut apply_packed(const DevMap& m, const uint4* list, uint3
     }
     TaskOut out;
     out.obs = (uint32_t)wave_sum((int)(ns + nb));
+    out.distinct = (uint32_t)wave_sum(upd ? 1 : 0);
     out.merge2 = (uint32_t)wave_sum(finish_packed<ST>(m, live, id, info, level, seg, D, W, S2, upd, upd ? 1 : 0, dsum, dcnt));
     return out;
 }

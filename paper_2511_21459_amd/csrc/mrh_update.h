@@ -415,17 +415,19 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
 // be merged into one dynamically addressed update, which forces the sums into scratch memory.
 struct TaskOut {
     uint32_t obs = 0, fresh = 0, merge0 = 0, merge1 = 0, merge2 = 0;
+    uint32_t distinct = 0;  // LiDAR: voxels with at least one observation (RGB-D: equal to obs, not set)
 };
 
 // Statistics gathered by one wave over its tasks.
 struct TaskStats {
-    unsigned long long obs = 0, fresh = 0, merge0 = 0, merge1 = 0, merge2 = 0;
+    unsigned long long obs = 0, fresh = 0, merge0 = 0, merge1 = 0, merge2 = 0, distinct = 0;
     __device__ inline void add(const TaskOut& o) {
         obs += o.obs;
         fresh += o.fresh;
         merge0 += o.merge0;
         merge1 += o.merge1;
         merge2 += o.merge2;
+        distinct += o.distinct;
     }
     // the same with the (wave-uniform) counts summed in scalar registers: for kernels that are
     // short of vector registers but not of scalar ones
@@ -435,6 +437,7 @@ struct TaskStats {
         merge0 += uniform(o.merge0);
         merge1 += uniform(o.merge1);
         merge2 += uniform(o.merge2);
+        distinct += uniform(o.distinct);
     }
 };
 
@@ -460,10 +463,12 @@ __device__ inline TaskCounts frame_task_counts(const DevMap& m, bool with_new, i
     return c;
 }
 
-// flush one wave's statistics (lane 0)
-__device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts) {
+// flush one wave's statistics (lane 0); an RGB-D frame updates a voxel at most once, so its
+// distinct voxels are its observations
+__device__ inline void flush_task_stats(const DevMap& m, const TaskStats& ts, bool depth_frame) {
     if (lane_id() == 0) {
         stat_add(m, S_OBS, ts.obs);
+        stat_add(m, S_DISTINCT, depth_frame ? ts.obs : ts.distinct);
         stat_add(m, S_OBS_FRESH, ts.fresh);
         stat_add(m, S_MERGE0, ts.merge0);
         stat_add(m, S_MERGE1, ts.merge1);
@@ -524,6 +529,9 @@ __device__ inline void update_duties(const DevMap& m, int par) {
         const uint32_t pops = c->pops0;
         s_t0 = t0 - (int32_t)(pops < avail ? pops : avail);
         s_p = c->pending0[par ^ 1].v;
+        unsigned long long q = 0;  // blocks the frame queued for this launch (all levels)
+        for (int l = 0; l < 4; ++l) q += c->vis_n[par][l].v;
+        stat_add(m, S_QUEUED, q);
         c->pops0 = 0;
         c->n_prev[par ^ 1] = c->n_blocks < m.max_blocks ? c->n_blocks : m.max_blocks;
     }

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_apply_points(const DevMap* __restrict__
     run_deferred<ST>(m, dl, par, m0, m1);
     as.merge0 += m0;
     as.merge1 += m1;
-    flush_task_stats(m, as);
+    flush_task_stats(m, as, false);
 }
 
 // Blocks a ray's walk can visit: the guard of the block walk bounds it by 4 + the sum over the
@@ -64,7 +64,7 @@ mrh_status ensure_lidar(mrh_map* map, int64_t n) {
         changed = true;
     };
     if (!map->lidar_ready) {
-        alloc((void**)&d.btouch, (size_t)d.max_blocks * 4, "touch flags");
+        alloc((void**)&d.btouch, (size_t)d.max_blocks * 8, "touch masks");
         for (int l = 0; l < map->cfg.levels; ++l) {
             const size_t nv = (size_t)d.heap_cap[l] * (size_t)(side_of(l) * side_of(l) * side_of(l));
             alloc((void**)&d.acc_sat[l], nv * 4, "scan accumulators");

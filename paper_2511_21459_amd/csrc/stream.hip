@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_stream_in(const DevMap* __restrict__ pm
                     slot = m.stack[level][t - 1];
                     m.bkey[id] = key;
                     m.hvals[h] = id;
-                    if (m.btouch) m.btouch[id] = 0u;
+                    if (m.btouch) m.btouch[id] = 0ull;
                     outcome = 1;
                 }
             }

@@ -23,8 +23,21 @@ class Sorted:
     S2: np.ndarray
 
 
+def assert_consistent(fmap) -> dict:
+    """The map's bookkeeping checks out: every key once in the hash table and reachable from its
+    home slot, table and block rows agree, and each heap's slots are held, free or pending exactly
+    once."""
+    c = fmap.check()
+    assert c["consistent"], c
+    assert c["live_blocks"] + c["slotless_blocks"] + c["gone_blocks"] == c["blocks"], c
+    assert c["table_keys"] == c["blocks"] - c["gone_blocks"] + c["idless_keys"], c
+    return c
+
+
 def gpu_sorted(fmap) -> Sorted:
-    """Extract a GPU map and order its blocks by ascending (x, y, z) like the oracle."""
+    """Extract a GPU map (after checking its bookkeeping) and order its blocks by ascending
+    (x, y, z) like the oracle."""
+    assert_consistent(fmap)
     e = fmap.extract(voxels=True)
     keys = e["keys"].cpu().numpy()
     levels = e["levels"].cpu().numpy()

@@ -45,7 +45,11 @@ def _streams(host=False):
     return cfgs, frames
 
 
-def _single(mrh, cfg, frames_of_map, storage="f32"):
+_COUNTS = ("valid_points", "dropped_points", "new_blocks", "observations", "fresh_observations",
+           "distinct_voxels", "candidate_keys", "merges")
+
+
+def _single(mrh, cfg, frames_of_map, storage="f32", totals=None):
     m = mrh.Map(**dict(cfg, storage=storage))
     for fr in frames_of_map:
         if fr is None:
@@ -54,7 +58,9 @@ def _single(mrh, cfg, frames_of_map, storage="f32"):
             m.integrate_depth(fr[1], fr[2], fr[3])
         else:
             m.integrate_points(fr[1], fr[2])
-    m.sync()
+    _, tot = m.sync()
+    if totals is not None:
+        totals.update(tot)
     return gpu_sorted(m)
 
 
@@ -76,8 +82,11 @@ def test_batch_equals_single_maps(mrh, graph):
     for fr in frames:
         b.integrate(fr)
     for i, c in enumerate(cfgs):
-        maps[i].sync()
-        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames]))
+        _, tb = maps[i].sync()
+        ts = {}
+        _same(gpu_sorted(maps[i]), _single(mrh, c, [fr[i] for fr in frames], totals=ts))
+        for name in _COUNTS:  # the batched launches keep each map's statistics
+            assert tb[name] == ts[name], (i, name)
 
 
 def _oracle_map(orc, cfg, frames_of_map):

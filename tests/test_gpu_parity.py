@@ -34,6 +34,8 @@ def test_sphere_plane_frame(mrh, orc):
     assert last["valid_points"] == st["valid_points"] == 76800
     assert last["new_blocks"] == st["new_blocks"] == o.num_blocks
     assert last["observations"] == st["observations"]
+    assert last["distinct_voxels"] == st["distinct_voxels"]
+    assert last["candidate_keys"] == st["candidate_keys"]
     rep = compare_maps(gpu_sorted(g), o.extract(), tau=0.06)
     print(rep)
 
@@ -145,6 +147,8 @@ def test_occluded_blocks(mrh, orc, form):
         last, _ = g.sync()
         st = o.integrate_depth(d, K, T)
         assert last["observations"] == st["observations"], k
+        assert last["distinct_voxels"] == st["distinct_voxels"], k
+        assert last["candidate_keys"] == st["candidate_keys"], k
         assert last["new_blocks"] == st["new_blocks"], k
     rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"])
     print(rep)
@@ -167,6 +171,8 @@ def test_room_ragged_frame_sizes(mrh, orc, size):
         assert last["valid_points"] == st["valid_points"], k
         assert last["new_blocks"] == st["new_blocks"], k
         assert last["observations"] == st["observations"], k
+        assert last["distinct_voxels"] == st["distinct_voxels"], k
+        assert last["candidate_keys"] == st["candidate_keys"], k
     assert o.num_blocks > 0
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"]))
 
@@ -236,6 +242,9 @@ def test_street_sequence_multires(mrh, orc):
         assert last["valid_points"] == st["valid_points"]
         assert last["new_blocks"] == st["new_blocks"]
         assert last["observations"] == st["observations"]
+        assert last["distinct_voxels"] == st["distinct_voxels"]
+        assert last["candidate_keys"] == st["candidate_keys"]
+        assert last["queued_blocks"] == st["touched_blocks"]
         merges += sum(st["merges"])
     rep = compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o))
     print(rep, "merges", merges)
@@ -256,6 +265,9 @@ def test_street_full_size_first_scans(mrh, orc):
         assert last["valid_points"] == st["valid_points"]
         assert last["new_blocks"] == st["new_blocks"]
         assert last["observations"] == st["observations"]
+        assert last["distinct_voxels"] == st["distinct_voxels"]
+        assert last["candidate_keys"] == st["candidate_keys"]
+        assert last["queued_blocks"] == st["touched_blocks"]
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)))
 
 
@@ -275,6 +287,9 @@ def test_street_full_sequence(mrh, orc):
         assert last["valid_points"] == st["valid_points"], k
         assert last["new_blocks"] == st["new_blocks"], k
         assert last["observations"] == st["observations"], k
+        assert last["distinct_voxels"] == st["distinct_voxels"], k
+        assert last["candidate_keys"] == st["candidate_keys"], k
+        assert last["queued_blocks"] == st["touched_blocks"], k
         merges += sum(st["merges"])
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o)), "merges", merges)
 
@@ -316,6 +331,9 @@ def test_lidar_long_rays(mrh, orc):
         last, _ = g.sync()
         st = o.integrate_points(pts, T)
         assert last["observations"] == st["observations"], k
+        assert last["distinct_voxels"] == st["distinct_voxels"], k
+        assert last["candidate_keys"] == st["candidate_keys"], k
+        assert last["queued_blocks"] == st["touched_blocks"], k
         assert last["new_blocks"] == st["new_blocks"], k
     assert o.num_blocks > 4 * 1100
     print(compare_maps(gpu_sorted(g), o.extract(), excused=excused_keys(o), tau=cfg["tau"]))

@@ -332,6 +332,69 @@ def test_lidar_point_order_independence(orc):
     assert ea.W.max() > 20
 
 
+def test_lidar_distinct_voxels_and_candidate_keys(orc):
+    """The per-scan counts: the allocation visits, per valid ray, exactly the block cells its
+    segment [o, p + tau n] meets (exact rational intersection), repeats across rays included; the
+    update counts a voxel once however many rays cross it -- in a fresh single-level map W after
+    one scan is the number of crossings, so the distinct voxels are those with W > 0 -- and a
+    block once, every block a ray's walk allocates holding at least one voxel the ray crosses.
+    Sending the scan twice doubles the visits and the observations but not the distinct voxels."""
+    rng = np.random.default_rng(11)
+    voxel, tau = 0.2, 0.6
+    B = 8 * voxel
+    n = 24
+    dirs = rng.normal(size=(n, 3))
+    dirs[:, 2] *= 0.3
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pts = (dirs * rng.uniform(2.0, 9.0, size=(n, 1))).astype(np.float32)
+    pts[0] = [0.1, 0.2, 0.3]  # inside min_range: not valid, not walked
+    T = np.eye(4)
+    T[:3, 3] = [0.37, -1.21, 0.52]
+    cfg = dict(voxel=voxel, tau=tau, min_range=1.0, max_range=40.0, carve=1)
+    m = orc.OracleMap(**cfg)
+    st = m.integrate_points(pts, T)
+    want = 0
+    for q in pts[1:].astype(np.float64):
+        p = q + T[:3, 3]
+        nn = (p - T[:3, 3]) / np.linalg.norm(p - T[:3, 3])
+        want += len(_brute_cells(T[:3, 3] / B, (p + tau * nn) / B))
+    assert st["valid_points"] == n - 1
+    assert st["candidate_keys"] == want
+    ext = m.extract()
+    assert st["distinct_voxels"] == int((ext.W > 0).sum())
+    assert st["observations"] == int(ext.W.sum()) > st["distinct_voxels"]  # rays share voxels near o
+    observed = np.add.reduceat((ext.W > 0).astype(np.int64), ext.offsets[:-1]) > 0
+    assert st["touched_blocks"] == int(observed.sum()) == st["new_blocks"]  # every walked block is observed
+    m2 = orc.OracleMap(**cfg)
+    st2 = m2.integrate_points(np.concatenate([pts, pts]), T)
+    assert st2["candidate_keys"] == 2 * want
+    assert st2["observations"] == 2 * st["observations"]
+    assert st2["distinct_voxels"] == st["distinct_voxels"]
+
+
+def test_rgbd_distinct_voxels_are_the_updates(orc):
+    """A depth frame gives each voxel one pixel, so its distinct voxels are its observations; its
+    allocation visits the block cells of every valid pixel's band [p - tau n, p + tau n]."""
+    depth, _, T = plane_frame(1.37, width=16, height=12)
+    K = np.array([9.0, 9.5, 7.63, 5.29])  # off-centre: no pixel ray runs along a block face
+    voxel, tau = 0.05, 0.15
+    m = orc.OracleMap(voxel=voxel, tau=tau, max_depth=10.0)
+    st = m.integrate_depth(depth, K, T)
+    ext = m.extract()
+    assert st["distinct_voxels"] == st["observations"] == int((ext.W > 0).sum()) > 0
+    observed = np.add.reduceat((ext.W > 0).astype(np.int64), ext.offsets[:-1]) > 0
+    assert st["touched_blocks"] == int(observed.sum()) > 0
+    fx, fy, cx, cy = K
+    want = 0
+    for v in range(depth.shape[0]):
+        for u in range(depth.shape[1]):
+            d = float(depth[v, u])
+            ps = np.array([((u - cx) * (1.0 / fx)) * d, ((v - cy) * (1.0 / fy)) * d, d])
+            nn = ps / np.linalg.norm(ps)
+            want += len(_brute_cells((ps - tau * nn) / (8 * voxel), (ps + tau * nn) / (8 * voxel)))
+    assert st["candidate_keys"] == want > st["new_blocks"] > 0
+
+
 # ------------------------------------------------------------------------------------------
 # merging criterion (Sec. 3.2.1): conservation and the constant-field case
 # ------------------------------------------------------------------------------------------
