@@ -13,7 +13,8 @@ Also reported on the same JSON line:
   * `batched`: 16 independent streams (8 RGB-D 320x240..640x480, 8 LiDAR 32x1024..64x2048), 20
     launches, fused by the batched FP16 graph path against plain FP32 per-map calls;
   * `query`: 1M trilinear queries near the room's surfaces, forward and adjoint;
-  * `street`: 20 full-size LiDAR scans (64 x 2048) with carving, throughput and per-kernel times;
+  * `street`: the 200 full-size LiDAR scans (64 x 2048) with carving, throughput, per-kernel times and
+    the scan roofline; the same scans with capacity-driven streaming through a smaller coarsest heap;
   * `sweep`: the room sequence at merge thresholds 0 / 10 / 5 / 1 mm: blocks per level, state
     memory and query error against the scene's exact signed distance;
   * `cpu_baseline`: the FP64 oracle on the headline workload (one thread), and the FP32 / FP16 /
@@ -345,17 +346,35 @@ def run_batched(args, torch, np, mrh, configs):
             "blocks_level_differs": sum(a["blocks_level_differs"] for a in accs)}
 
 
-def run_street(args, torch, np, mrh, configs):
-    """LiDAR street (64 x 2048 rings x azimuths, carving, 5/10/20/40 cm levels): the first
-    `--scans` scans fused as one sequence per step."""
+def _street_chunk(scans):
     from workloads import street_sequence
 
+    pts, poses, _ = street_sequence(rings=64, azimuths=2048, scans=scans)
+    return pts, poses
+
+
+def street_scans(n, np):
+    """The first n scans of the 64 x 2048 street, generated in parallel chunks of 10 scans."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    chunks = [list(range(i, min(i + 10, n))) for i in range(0, n, 10)]
+    with ProcessPoolExecutor(max(1, min(16, len(chunks), os.cpu_count() or 1))) as ex:
+        res = list(ex.map(_street_chunk, chunks))
+    return np.concatenate([r[0] for r in res]), np.ascontiguousarray(np.concatenate([r[1] for r in res]))
+
+
+# heaps of the street runs: the 200-scan map ends with about 94k / 44k / 54k / 1.23M blocks at
+# levels 0..3 (its free-space carving merges most blocks to the coarsest level)
+STREET_HEAPS = [1 << 20, 1 << 20, 1 << 20, 1 << 21]
+
+
+def run_street(args, torch, np, mrh, configs):
+    """LiDAR street (64 x 2048 rings x azimuths, carving, 5/10/20/40 cm levels, hash table of 2^22
+    slots): the first `--scans` scans fused as one sequence per step."""
     n = args.scans
-    pts, poses, _ = street_sequence(rings=64, azimuths=2048, scans=range(n))
-    poses = np.ascontiguousarray(poses)
+    pts, poses = street_scans(n, np)
     dev = torch.from_numpy(pts).cuda()
-    cfg = dict(configs.STREET, max_blocks=1 << 22, hash_slots=1 << 23,
-               heap_blocks=[1 << 21, 1 << 21, 1 << 21, 1 << 22])
+    cfg = dict(configs.STREET, heap_blocks=STREET_HEAPS)
     m = mrh.Map(**cfg)
     m.reset()
     census = []
@@ -373,7 +392,10 @@ def run_street(args, torch, np, mrh, configs):
     step()
     prof = m.profile_collect()
     m.profile(False)
+    _, tot = m.sync()
+    chk = m.check()
     m.close()
+    stream = run_street_streaming(np, mrh, cfg, dev, poses, tot["blocks"])
     valid = sum(f["valid_points"] for f in census)
     obs = sum(f["observations"] for f in census)
     distinct = sum(f["distinct_voxels"] for f in census)
@@ -397,7 +419,41 @@ def run_street(args, torch, np, mrh, configs):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_scan": int(scan_bytes / n), "kernel_ms_per_scan": round(scan_s * 1e3 / n, 4)},
         "rays_kernel": {"bound": "atomics/latency", "avg_launch_ms": round(rays_ms, 4),
-                        "observations_per_s_g": round(obs / n / (rays_ms / 1e3) / 1e9, 3)}})
+                        "observations_per_s_g": round(obs / n / (rays_ms / 1e3) / 1e9, 3)},
+        "map_check": {"consistent": chk["consistent"], "mean_probe": round(chk["mean_probe"], 3),
+                      "max_probe": chk["max_probe"], "table_load": round(chk["table_keys"] / cfg["hash_slots"], 4)},
+        "errors": tot["error_flags"],
+        "streaming": stream})
+
+
+def run_street_streaming(np, mrh, cfg, dev, poses, blocks_plain):
+    """The same scans with a coarsest heap of 2^20 blocks, below the 1.23M coarsest blocks the map
+    ends with: before each scan the stored blocks within 90 m of the sensor come back, after it the
+    blocks beyond 90 m move to the host store whenever a heap is 85% full (Sec. 3.3).  GPU and
+    store together must hold as many blocks as the plain run."""
+    import time as _t
+
+    import torch
+
+    n = dev.shape[0]
+    m = mrh.Map(**dict(cfg, heap_blocks=[1 << 20, 1 << 20, 1 << 20, 1 << 20]))
+    outs = ins = 0
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for k in range(n):
+        region = mrh.points_region(poses[k], 90.0)
+        ins += m.stream_in(region)
+        m.integrate_points(dev[k], poses[k])
+        outs += m.stream_out(region, threshold=0.85)
+    _, tot = m.sync()
+    t = _t.perf_counter() - t0
+    stored = m.store_info()
+    chk = m.check()
+    m.close()
+    return {"ms_per_step": round(t * 1e3, 3), "ms_per_scan": round(t * 1e3 / n, 3), "streamed_out": outs,
+            "streamed_in": ins, "blocks_on_gpu": tot["blocks"], "blocks_in_store": stored[0],
+            "store_bytes": stored[2], "blocks_match_plain": tot["blocks"] + stored[0] == blocks_plain,
+            "consistent": chk["consistent"], "errors": tot["error_flags"]}
 
 
 def run_query(room, torch, np, mrh):
@@ -553,7 +609,7 @@ def main():
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--launches", type=int, default=20, help="batched workload: frames per stream")
     ap.add_argument("--cpu-frames", type=int, default=100, help="oracle sample: first N frames")
-    ap.add_argument("--scans", type=int, default=20, help="LiDAR street workload: scans per step")
+    ap.add_argument("--scans", type=int, default=200, help="LiDAR street workload: scans per step")
     ap.add_argument("--cpu-scans", type=int, default=3, help="LiDAR oracle sample: first N scans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "mrh_depth.h"
@@ -35,12 +36,9 @@ struct Region {
     double radius;     // POINTS: ball radius
 };
 
-// Bounding sphere of block (bx, by, bz) against the region (host and device evaluate the same
-// expression).
-__host__ __device__ inline bool region_holds(const Region& r, double B, int32_t bx, int32_t by, int32_t bz) {
-    const double hb = 0.5 * B;
-    const double c[3] = {(double)bx * B + hb, (double)by * B + hb, (double)bz * B + hb};
-    const double rb = B * 0.8660254037844387 * (1.0 + 1e-9) + 1e-9;
+// Does the sphere of centre c and radius rb reach into the region?  Every test only grows with
+// rb, so a sphere that misses the region contains no smaller sphere that reaches it.
+__host__ __device__ inline bool region_meets(const Region& r, const double c[3], double rb) {
     if (r.kind == MRH_FRAME_POINTS) {
         const double d0 = c[0] - r.o[0], d1 = c[1] - r.o[1], d2 = c[2] - r.o[2];
         return __builtin_sqrt((d0 * d0 + d1 * d1) + d2 * d2) - rb <= r.radius;
@@ -54,6 +52,14 @@ __host__ __device__ inline bool region_holds(const Region& r, double B, int32_t 
     for (int p = 0; p < 4; ++p)
         if (f.plane[p][0] * x[0] + f.plane[p][1] * x[1] + f.plane[p][2] * x[2] < -rb) return false;
     return true;
+}
+
+// Bounding sphere of block (bx, by, bz) against the region (host and device evaluate the same
+// expression).
+__host__ __device__ inline bool region_holds(const Region& r, double B, int32_t bx, int32_t by, int32_t bz) {
+    const double hb = 0.5 * B;
+    const double c[3] = {(double)bx * B + hb, (double)by * B + hb, (double)bz * B + hb};
+    return region_meets(r, c, B * 0.8660254037844387 * (1.0 + 1e-9) + 1e-9);
 }
 
 // Blocks outside the region, appended to per-level id lists (one atomic per level per wave).
@@ -331,8 +337,20 @@ mrh_status grow(mrh_map* map, T** p, size_t& cap, size_t need, const char* what)
 using namespace mrh;
 
 // Host store and staging of a map (created on first use).
+// The host store is indexed by buckets of kBucketSide^3 blocks, so that bringing a region back
+// tests the buckets' bounding spheres first and only the blocks of the buckets that reach it.
+constexpr int kBucketShift = 5;
+constexpr int kBucketSide = 1 << kBucketShift;
+
+inline unsigned long long bucket_of(unsigned long long key) {
+    int32_t x, y, z;
+    unpack_key(key, x, y, z);
+    return pack_key(x >> kBucketShift, y >> kBucketShift, z >> kBucketShift);
+}
+
 struct mrh_stream_state {
     std::unordered_map<unsigned long long, HostBlock> store;
+    std::unordered_map<unsigned long long, std::unordered_set<unsigned long long>> buckets;  // bucket -> keys
     uint32_t* ids = nullptr;
     size_t ids_cap = 0;
     uint32_t* counts = nullptr;
@@ -365,7 +383,10 @@ void stream_free(mrh_map* map) {
 }
 
 void stream_clear(mrh_map* map) {
-    if (map->stream_st) map->stream_st->store.clear();
+    if (map->stream_st) {
+        map->stream_st->store.clear();
+        map->stream_st->buckets.clear();
+    }
     map->gone = 0;
 }
 
@@ -494,6 +515,7 @@ mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double thresho
         if (st != MRH_OK) return st;
         for (uint32_t q = 0; q < n; ++q) {
             HostBlock& hb = S->store[hk[q]];
+            S->buckets[bucket_of(hk[q])].insert(hk[q]);
             hb.level = lv;
             hb.vsum = hs[q];
             hb.vcnt = hc[q];
@@ -517,15 +539,24 @@ mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in) 
     std::vector<const uint8_t*> words;
     std::vector<double> vsum;
     std::vector<uint32_t> vcnt;
-    for (const auto& kv : S->store) {
-        int32_t x, y, z;
-        unpack_key(kv.first, x, y, z);
-        if (!region_holds(r, map->dm.B, x, y, z)) continue;
-        keys.push_back(kv.first);
-        levels.push_back(kv.second.level);
-        words.push_back(kv.second.bytes.data());
-        vsum.push_back(kv.second.vsum);
-        vcnt.push_back(kv.second.vcnt);
+    const double B = map->dm.B, bb = B * kBucketSide;
+    const double brad = bb * 0.8660254037844387 * (1.0 + 1e-9) + 1e-9;
+    for (const auto& bk : S->buckets) {
+        int32_t cx, cy, cz;
+        unpack_key(bk.first, cx, cy, cz);
+        const double c[3] = {((double)cx + 0.5) * bb, ((double)cy + 0.5) * bb, ((double)cz + 0.5) * bb};
+        if (!region_meets(r, c, brad)) continue;
+        for (unsigned long long key : bk.second) {
+            int32_t x, y, z;
+            unpack_key(key, x, y, z);
+            if (!region_holds(r, B, x, y, z)) continue;
+            const HostBlock& hb = S->store.at(key);
+            keys.push_back(key);
+            levels.push_back(hb.level);
+            words.push_back(hb.bytes.data());
+            vsum.push_back(hb.vsum);
+            vcnt.push_back(hb.vcnt);
+        }
     }
     if (keys.empty()) return MRH_OK;
     // the free slots must hold every block brought back
@@ -547,6 +578,9 @@ mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in) 
         // restored blocks leave the store; a key present on the GPU keeps its stored copy
         if (outcome[i] == 1) {
             S->store.erase(keys[i]);
+            auto b = S->buckets.find(bucket_of(keys[i]));
+            b->second.erase(keys[i]);
+            if (b->second.empty()) S->buckets.erase(b);
             ++*n_in;
         }
     }
