@@ -474,6 +474,59 @@ def run_query(room, torch, np, mrh):
             "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1)}
 
 
+def run_color(room, torch, np, mrh, configs):
+    """Colour integration (mrh_integrate_rgbd) of the room sequence: the 100 frames with a colour
+    image each; the colour launch re-takes every updated voxel's projective decision and averages
+    its pixel's RGB into the voxel's colour (12 B read and written per updated voxel)."""
+    from workloads import colour_image
+
+    n = len(room["poses"])
+    rgb = torch.from_numpy(np.stack([colour_image(room["depths"][k], room["cam"], room["poses"][k]) for k in range(n)])).cuda()
+    dev = torch.from_numpy(room["depths"]).cuda()
+    K = room["cam"].K
+    m = mrh.Map(**dict(configs.ROOM, color=True))
+
+    def step():
+        m.reset()
+        for k in range(n):
+            m.integrate_rgbd(dev[k], rgb[k], K, room["poses"][k])
+
+    step()
+    t = timed(step, 3, torch)
+    m.profile(True)
+    step()
+    prof = m.profile_collect()
+    m.profile(False)
+    _, tot = m.sync()
+    m.close()
+    col_s = prof["color"][0] / 1e3
+    byts = 24 * tot["observations"] + rgb.numel()  # colour read and written per update, the RGB images
+    return {"workload": f"room RGB-D orbit with colour, {n} frames 640x480", "ms_per_step": round(t * 1e3, 3),
+            "ms_per_frame": round(t * 1e3 / n, 4), "colour_kernel_ms_per_frame": round(prof["color"][0] / n, 4),
+            "colour_kernel_gb_per_s": round(byts / col_s / 1e9, 1),
+            "m_points_per_s": round(tot["valid_points"] / t / 1e6, 1), "errors": tot["error_flags"]}
+
+
+def run_quadtree(room, torch, np, mrh):
+    """Image quadtree by contrast (Eq. 10, Algorithm 1) of 20 of the room's 640x480 colour images."""
+    from workloads import colour_image
+
+    imgs = [torch.from_numpy(colour_image(room["depths"][k], room["cam"], room["poses"][k])).cuda() for k in range(0, 100, 5)]
+    qt = mrh.Quadtree(640, 480)
+    out = {}
+    for thr in (100.0, 400.0):
+        qt.build(imgs[0], thr, 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        leaves = 0
+        for im in imgs:
+            leaves += qt.build(im, thr, 4)[0].shape[0]
+        dt = time.perf_counter() - t0
+        out[f"threshold_{int(thr)}"] = {"ms_per_image": round(dt * 1e3 / len(imgs), 4), "leaves_per_image": leaves // len(imgs)}
+    qt.close()
+    return {"workload": "20 colour images 640x480, minimum node side 4", **out}
+
+
 MESH_COLLAPSE = 0.1  # vertex collapse of the mesh record, as a fraction of the cube's voxel size
 MESH_BYTES_PER_TRIANGLE = 36 + 12 + 4  # vertices, block key, code
 
@@ -614,7 +667,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
-    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh"],
+    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh", "color"],
                     help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -646,6 +699,12 @@ def main():
         fm.sync()
         room = dict(depths=depths, cam=cam, poses=poses, scene=scene, fmap=fm)
         print(json.dumps({"mesh": run_mesh(room, torch, np, mrh, configs)}), flush=True)
+        return
+    if args.only == "color":
+        depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
+        room = dict(depths=depths, cam=cam, poses=np.ascontiguousarray(poses), scene=scene)
+        print(json.dumps({"color": run_color(room, torch, np, mrh, configs),
+                          "quadtree": run_quadtree(room, torch, np, mrh)}), flush=True)
         return
     if args.only == "sweep":
         depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
@@ -692,6 +751,8 @@ def main():
         result["batched"] = run_batched(args, torch, np, mrh, configs)
         result["query"] = run_query(room, torch, np, mrh)
         result["mesh"] = run_mesh(room, torch, np, mrh, configs)
+        result["color"] = run_color(room, torch, np, mrh, configs)
+        result["quadtree"] = run_quadtree(room, torch, np, mrh)
         result["sweep"] = run_sweep(room, torch, np, mrh, configs)
         street = run_street(args, torch, np, mrh, configs)
         result["street"] = street["out"]

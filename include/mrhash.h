@@ -298,7 +298,8 @@ enum {
     MRH_KERNEL_BATCH_FINALIZE = 13, /* reserved, as MRH_KERNEL_FINALIZE; stays 0 */
     MRH_KERNEL_BATCH_GRAPH = 14,    /* batched: one replay of the captured step */
     MRH_KERNEL_MESH = 15,           /* multi-resolution Marching Cubes */
-    MRH_KERNEL_COUNT = 16
+    MRH_KERNEL_COLOR = 16,          /* colour integration of an RGB-D frame */
+    MRH_KERNEL_COUNT = 17
 };
 
 /* Launch profiler (measurement support, not part of the method).  With on != 0 every kernel the
@@ -426,6 +427,16 @@ void mrh_quadtree_destroy(mrh_quadtree* qt);
  * MRH_ERR_BUFFER_TOO_SMALL (count still set) when it exceeds cap.  Synchronises the stream. */
 mrh_status mrh_quadtree_build(mrh_quadtree* qt, const uint8_t* rgb_dev, int32_t width, int32_t height, double threshold,
                               int32_t min_size, int32_t* leaves_dev, float* contrast_dev, int64_t cap, int64_t* n_leaves);
+
+/* ---- Storage conversions (for checking the 16-bit formats) ---------------------------------
+ * The conversions the 16-bit storage formats apply, element by element: storage MRH_STORE_F16
+ * (IEEE binary16) or MRH_STORE_BF16 (bfloat16), both rounding to nearest with ties to even and
+ * keeping NaN a NaN.  decode = 0: float32[n] -> uint16[n] bit patterns; decode = 1: uint16[n] ->
+ * float32[n].  mrh_codec_device runs the device codecs the fusion kernels use (device pointers,
+ * the null stream, synchronous); mrh_codec_host their host counterparts (host pointers; no GPU
+ * needed).  Errors: MRH_ERR_INVALID_ARG (another storage, n < 0, NULL with n > 0); MRH_ERR_HIP. */
+mrh_status mrh_codec_device(int32_t storage, int32_t decode, const void* in_dev, void* out_dev, int64_t n);
+mrh_status mrh_codec_host(int32_t storage, int32_t decode, const void* in, void* out, int64_t n);
 
 /* Text of the last error on this map (never NULL; "" when none). */
 const char* mrh_last_error(const mrh_map* map);

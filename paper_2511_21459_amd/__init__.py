@@ -386,6 +386,29 @@ class Quadtree:
         return leaves, con
 
 
+def convert(values, storage: str, decode: bool = False):
+    """The conversion of a 16-bit storage format ("f16" or "bf16"), element by element: float32 to
+    uint16 bit patterns (decode=False) or back.  A CUDA tensor runs the device codec the fusion
+    kernels use; a numpy array runs the host codec."""
+    st = STORAGE[storage]
+    if st == STORAGE["f32"]:
+        raise ValueError("convert: storage must be 'f16' or 'bf16'")
+    if isinstance(values, torch.Tensor):
+        want = torch.int16 if decode else torch.float32
+        if values.dtype != want or not values.is_cuda or not values.is_contiguous():
+            raise ValueError(f"convert: a contiguous CUDA {want} tensor is required")
+        out = torch.empty(values.shape, dtype=torch.float32 if decode else torch.int16, device=values.device)
+        code = _lib.load().mrh_codec_device(st, int(decode), ctypes.c_void_p(values.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), values.numel())
+    else:
+        x = np.ascontiguousarray(values, dtype=np.uint16 if decode else np.float32)
+        out = np.empty(x.shape, dtype=np.float32 if decode else np.uint16)
+        code = _lib.load().mrh_codec_host(st, int(decode), x.ctypes.data, out.ctypes.data, x.size)
+    if code != 0:
+        raise MrhError(code, "convert")
+    return out
+
+
 def depth_region(width: int, height: int, K, T_ws) -> "_lib.MrhRegion":
     """Streaming region of an RGB-D frame: the camera frustum."""
     r = _lib.MrhRegion()

@@ -33,10 +33,11 @@ EXPORTS = [
     "mrh_integrate_depth_noalloc", "mrh_extract_mesh", "mrh_heap_usage", "mrh_stream_out", "mrh_stream_in",
     "mrh_store_info", "mrh_store_extract", "mrh_load_blocks", "mrh_quadtree_create", "mrh_quadtree_destroy",
     "mrh_quadtree_build", "mrh_integrate_rgbd", "mrh_extract_color", "mrh_map_check",
+    "mrh_codec_device", "mrh_codec_host",
 ]
 KERNELS = ["reset", "alloc_depth", "integrate_depth", "finalize", "alloc_points", "rays", "apply_points",
            "query", "query_backward", "reduce", "batch_alloc", "batch_rays", "batch_update", "batch_finalize",
-           "batch_step", "mesh"]
+           "batch_step", "mesh", "color"]
 FRAME_NONE, FRAME_DEPTH, FRAME_POINTS = 0, 1, 2
 
 
@@ -142,6 +143,9 @@ def load():
     L.mrh_quadtree_destroy.argtypes = [P]
     L.mrh_quadtree_build.restype = i32
     L.mrh_quadtree_build.argtypes = [P, P, i32, i32, ctypes.c_double, i32, P, P, i64, ctypes.POINTER(i64)]
+    for fn in (L.mrh_codec_device, L.mrh_codec_host):
+        fn.restype = i32
+        fn.argtypes = [i32, i32, P, P, ctypes.c_int64]
     L.mrh_map_check.restype = i32
     L.mrh_map_check.argtypes = [P, ctypes.POINTER(MrhCheck)]
     L.mrh_heap_usage.restype = i32

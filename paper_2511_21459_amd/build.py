@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmrhash.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["map.hip", "depth.hip", "points.hip", "query.hip", "batch.hip", "mesh.hip", "stream.hip", "quadtree.hip", "color.hip", "check.hip"]
+SOURCES = ["map.hip", "depth.hip", "points.hip", "query.hip", "batch.hip", "mesh.hip", "stream.hip", "quadtree.hip", "color.hip", "check.hip", "codec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

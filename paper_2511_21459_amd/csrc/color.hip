@@ -153,11 +153,13 @@ extern "C" mrh_status mrh_integrate_rgbd(mrh_map* map, const float* depth_dev, c
     DepthFrame f;
     const mrh_status st = integrate_depth_frame(map, depth_dev, width, height, K, T_ws, &f);
     if (st != MRH_OK) return st;
-    switch (map->cfg.storage) {
-        case MRH_STORE_F16: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_F16>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev); break;
-        case MRH_STORE_BF16: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_BF16>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev); break;
-        default: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_F32>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev);
-    }
+    launch(map, K_COLOR, [&] {
+        switch (map->cfg.storage) {
+            case MRH_STORE_F16: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_F16>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_BF16>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev); break;
+            default: hipLaunchKernelGGL(k_integrate_color<MRH_STORE_F32>, dim3(1024), dim3(256), 0, map->stream, map->dmd, f, rgb_dev);
+        }
+    });
     return check_hip(map, hipGetLastError(), "integrate_rgbd");
 }
 

@@ -370,7 +370,7 @@ enum KernelId { K_RESET = MRH_KERNEL_RESET, K_ALLOC_DEPTH = MRH_KERNEL_ALLOC_DEP
                 K_APPLY_POINTS = MRH_KERNEL_APPLY_POINTS, K_QUERY = MRH_KERNEL_QUERY, K_QUERY_BACKWARD = MRH_KERNEL_QUERY_BACKWARD,
                 K_REDUCE = MRH_KERNEL_REDUCE, K_BATCH_ALLOC = MRH_KERNEL_BATCH_ALLOC, K_BATCH_RAYS = MRH_KERNEL_BATCH_RAYS,
                 K_BATCH_UPDATE = MRH_KERNEL_BATCH_UPDATE, K_BATCH_FINALIZE = MRH_KERNEL_BATCH_FINALIZE,
-                K_BATCH_GRAPH = MRH_KERNEL_BATCH_GRAPH, K_MESH = MRH_KERNEL_MESH };
+                K_BATCH_GRAPH = MRH_KERNEL_BATCH_GRAPH, K_MESH = MRH_KERNEL_MESH, K_COLOR = MRH_KERNEL_COLOR };
 
 // one profiled launch: kernel id and its bracketing events on the map's stream
 struct ProfRec {

@@ -12,6 +12,8 @@
 
 #include <hip/hip_fp16.h>
 
+#include <cstring>
+
 #include "mrh_internal.h"
 
 namespace mrh {
@@ -28,6 +30,33 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b) {
 
 __device__ inline uint16_t f32_to_f16(float x) { return __half_as_ushort(__float2half_rn(x)); }
 __device__ inline float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+// The same conversions on the host (clang's _Float16 rounds to nearest even; bfloat16 by integer
+// rounding to nearest even, NaN kept NaN).
+inline float h_f16(uint16_t b) {
+    _Float16 x;
+    std::memcpy(&x, &b, 2);
+    return (float)x;
+}
+inline uint16_t h_to_f16(float f) {
+    const _Float16 x = (_Float16)f;
+    uint16_t b;
+    std::memcpy(&b, &x, 2);
+    return b;
+}
+inline float h_bf16(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+inline uint16_t h_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 template <int ST>
 struct Store;

@@ -258,31 +258,6 @@ double heap_usage(const mrh_map* map, const DevCounters& h) {
 // decoded only for inspection; blocks loaded from outside are encoded with an exact division in
 // place of the device's reciprocal for the variance, which can differ from a device store by one
 // 16-bit ulp.
-inline float h_f16(uint16_t b) {
-    _Float16 x;
-    std::memcpy(&x, &b, 2);
-    return (float)x;
-}
-inline uint16_t h_to_f16(float f) {
-    const _Float16 x = (_Float16)f;
-    uint16_t b;
-    std::memcpy(&b, &x, 2);
-    return b;
-}
-inline float h_bf16(uint16_t b) {
-    const uint32_t u = (uint32_t)b << 16;
-    float x;
-    std::memcpy(&x, &u, 4);
-    return x;
-}
-inline uint16_t h_to_bf16(float f) {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 // voxel p of a block of nv voxels held as three planes in `buf`
 inline void host_decode(int st, const uint8_t* buf, int nv, int p, float tau_f, float tau2_f, float& D, uint32_t& W,
                         float& S2) {

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from parity_util import announce, compare_maps, excused_keys, gpu_sorted
-from workloads import configs, room_sequence
+from workloads import colour_image, configs, room_sequence
 
 pytestmark = pytest.mark.gpu
 
@@ -21,19 +21,6 @@ def mrh():
 
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
-
-
-def colour_image(depth, cam, T):
-    """A colour per pixel from the world point it sees (a fixed function of position, so every view
-    of a surface point agrees); black where the depth is invalid."""
-    h, w = depth.shape
-    v, u = np.mgrid[0:h, 0:w]
-    x = np.stack([(u - cam.cx) / cam.fx * depth, (v - cam.cy) / cam.fy * depth, depth], axis=-1)
-    p = x @ T[:3, :3].T + T[:3, 3]
-    c = np.stack([128 + 100 * np.sin(7 * p[..., 0]), 128 + 100 * np.sin(5 * p[..., 1] + 1),
-                  128 + 100 * np.sin(3 * p[..., 2] + 2)], axis=-1)
-    c[~np.isfinite(depth) | (depth <= 0)] = 0
-    return np.clip(np.nan_to_num(c), 0, 255).astype(np.uint8)
 
 
 def _sorted_colour(fmap):

@@ -15,4 +15,5 @@ from .scenes import (  # noqa: F401
     lidar_directions,
     plane_frame,
     surface_query_points,
+    colour_image,
 )

@@ -411,3 +411,16 @@ def surface_query_points(scene: RoomScene, n: int, sigma: float, seed: int = 100
     if with_offsets:
         return pts[perm].astype(np.float32), np.concatenate(offs)[perm]
     return pts[perm].astype(np.float32)
+
+
+def colour_image(depth, cam, T):
+    """A colour per pixel from the world point it sees (a fixed function of position, so every view
+    of a surface point agrees); black where the depth is invalid."""
+    h, w = depth.shape
+    v, u = np.mgrid[0:h, 0:w]
+    x = np.stack([(u - cam.cx) / cam.fx * depth, (v - cam.cy) / cam.fy * depth, depth], axis=-1)
+    p = x @ T[:3, :3].T + T[:3, 3]
+    c = np.stack([128 + 100 * np.sin(7 * p[..., 0]), 128 + 100 * np.sin(5 * p[..., 1] + 1),
+                  128 + 100 * np.sin(3 * p[..., 2] + 2)], axis=-1)
+    c[~np.isfinite(depth) | (depth <= 0)] = 0
+    return np.clip(np.nan_to_num(c), 0, 255).astype(np.uint8)
