@@ -24,6 +24,7 @@
 namespace {
 
 constexpr int64_t kMaxPixels = int64_t(1) << 23;
+constexpr int kMaxLevels = 32;  // levels of the breadth-first build (at most log2(2^23) + 3 are used)
 
 struct QtNode {
     int32_t x, y, w, h;
@@ -78,18 +79,67 @@ __global__ __launch_bounds__(256) void k_sat_rows(const uint8_t* __restrict__ rg
     }
 }
 
-// Column pass: running sums down each column (one thread per column; rows are read coalesced).
-__global__ __launch_bounds__(256) void k_sat_cols(int32_t W, int32_t H, uint32_t* __restrict__ S,
-                                                  unsigned long long* __restrict__ Q) {
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+// Column pass: running sums down each column, in chunks of kColChunk rows so that the image's
+// height is covered by many threads (consecutive threads take consecutive columns, so every row
+// access is coalesced): the chunks' column sums, their exclusive prefix down each column, then the
+// running sums within each chunk from its prefix.
+constexpr int kColChunk = 16;
+
+__global__ __launch_bounds__(64) void k_sat_cols_part(int32_t W, int32_t H, const uint32_t* __restrict__ S,
+                                                      const unsigned long long* __restrict__ Q, uint32_t* __restrict__ TS,
+                                                      unsigned long long* __restrict__ TQ) {
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
     if (x > W) return;
     const size_t pitch = (size_t)W + 1, plane = pitch * ((size_t)H + 1);
+    const int32_t y0 = k * kColChunk + 1, y1 = min(H, y0 + kColChunk - 1);
     for (int c = 0; c < 3; ++c) {
-        S[c * plane + x] = 0u;
-        Q[c * plane + x] = 0ull;
         uint32_t s = 0;
         unsigned long long q = 0;
-        for (int32_t y = 1; y <= H; ++y) {
+        for (int32_t y = y0; y <= y1; ++y) {
+            const size_t at = c * plane + (size_t)y * pitch + x;
+            s += S[at];
+            q += Q[at];
+        }
+        TS[((size_t)k * 3 + c) * pitch + x] = s;
+        TQ[((size_t)k * 3 + c) * pitch + x] = q;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sat_cols_scan(int32_t W, int32_t nchunks, uint32_t* __restrict__ TS,
+                                                      unsigned long long* __restrict__ TQ) {
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > W) return;
+    const size_t pitch = (size_t)W + 1;
+    for (int c = 0; c < 3; ++c) {
+        uint32_t s = 0;
+        unsigned long long q = 0;
+        for (int32_t k = 0; k < nchunks; ++k) {
+            const size_t at = ((size_t)k * 3 + c) * pitch + x;
+            const uint32_t ts = TS[at];
+            const unsigned long long tq = TQ[at];
+            TS[at] = s;
+            TQ[at] = q;
+            s += ts;
+            q += tq;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sat_cols_apply(int32_t W, int32_t H, uint32_t* __restrict__ S,
+                                                       unsigned long long* __restrict__ Q, const uint32_t* __restrict__ TS,
+                                                       const unsigned long long* __restrict__ TQ) {
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+    if (x > W) return;
+    const size_t pitch = (size_t)W + 1, plane = pitch * ((size_t)H + 1);
+    const int32_t y0 = k * kColChunk + 1, y1 = min(H, y0 + kColChunk - 1);
+    for (int c = 0; c < 3; ++c) {
+        if (k == 0) {
+            S[c * plane + x] = 0u;
+            Q[c * plane + x] = 0ull;
+        }
+        uint32_t s = TS[((size_t)k * 3 + c) * pitch + x];
+        unsigned long long q = TQ[((size_t)k * 3 + c) * pitch + x];
+        for (int32_t y = y0; y <= y1; ++y) {
             const size_t at = c * plane + (size_t)y * pitch + x;
             s += S[at];
             q += Q[at];
@@ -187,9 +237,11 @@ struct mrh_quadtree {
     uint32_t* S = nullptr;
     unsigned long long* Q = nullptr;
     QtNode* queue[2] = {nullptr, nullptr};
-    uint32_t* counts = nullptr;  // two queue lengths
+    uint32_t* counts = nullptr;  // queue length of every level (kMaxLevels), then the leaf count (u64)
     unsigned long long* n_leaves = nullptr;
     size_t queue_cap = 0;
+    uint32_t* TS = nullptr;      // column pass: per chunk of rows, channel and column
+    unsigned long long* TQ = nullptr;
 };
 
 extern "C" {
@@ -204,10 +256,14 @@ mrh_status mrh_quadtree_create(int32_t max_width, int32_t max_height, void* stre
     const size_t plane = ((size_t)max_width + 1) * ((size_t)max_height + 1);
     // a level never holds more nodes than pixels
     q->queue_cap = (size_t)max_width * (size_t)max_height;
+    const size_t chunks = ((size_t)max_height + kColChunk - 1) / kColChunk;
     bool ok = hipMalloc((void**)&q->S, 3 * plane * 4) == hipSuccess && hipMalloc((void**)&q->Q, 3 * plane * 8) == hipSuccess &&
               hipMalloc((void**)&q->queue[0], q->queue_cap * sizeof(QtNode)) == hipSuccess &&
               hipMalloc((void**)&q->queue[1], q->queue_cap * sizeof(QtNode)) == hipSuccess &&
-              hipMalloc((void**)&q->counts, 8) == hipSuccess && hipMalloc((void**)&q->n_leaves, 8) == hipSuccess;
+              hipMalloc((void**)&q->counts, kMaxLevels * 4 + 8) == hipSuccess &&
+              hipMalloc((void**)&q->TS, chunks * 3 * ((size_t)max_width + 1) * 4) == hipSuccess &&
+              hipMalloc((void**)&q->TQ, chunks * 3 * ((size_t)max_width + 1) * 8) == hipSuccess;
+    if (ok) q->n_leaves = reinterpret_cast<unsigned long long*>(q->counts + kMaxLevels);
     if (!ok) {
         mrh_quadtree_destroy(q);
         return MRH_ERR_OOM;
@@ -220,7 +276,7 @@ void mrh_quadtree_destroy(mrh_quadtree* q) {
     if (!q) return;
     if (q->stream) (void)hipStreamSynchronize(q->stream);
     else (void)hipDeviceSynchronize();
-    void* ptrs[] = {q->S, q->Q, q->queue[0], q->queue[1], q->counts, q->n_leaves};
+    void* ptrs[] = {q->S, q->Q, q->queue[0], q->queue[1], q->counts, q->TS, q->TQ};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete q;
@@ -233,12 +289,16 @@ mrh_status mrh_quadtree_build(mrh_quadtree* q, const uint8_t* rgb_dev, int32_t w
         return MRH_ERR_INVALID_ARG;
     hipStream_t s = q->stream;
     hipLaunchKernelGGL(k_sat_rows, dim3(height), dim3(256), 0, s, rgb_dev, width, height, q->S, q->Q);
-    hipLaunchKernelGGL(k_sat_cols, dim3((width + 1 + 255) / 256), dim3(256), 0, s, width, height, q->S, q->Q);
+    const int32_t chunks = (height + kColChunk - 1) / kColChunk;
+    const dim3 cg((unsigned)((width + 1 + 63) / 64), (unsigned)chunks);
+    hipLaunchKernelGGL(k_sat_cols_part, cg, dim3(64), 0, s, width, height, q->S, q->Q, q->TS, q->TQ);
+    hipLaunchKernelGGL(k_sat_cols_scan, dim3((unsigned)((width + 1 + 63) / 64)), dim3(64), 0, s, width, chunks, q->TS, q->TQ);
+    hipLaunchKernelGGL(k_sat_cols_apply, cg, dim3(64), 0, s, width, height, q->S, q->Q, q->TS, q->TQ);
+    // the root, level 0 of one node, zero nodes at the other levels and no leaves yet
     const QtNode root{0, 0, width, height};
-    const uint32_t one = 1;
+    uint32_t init[kMaxLevels + 2] = {1};
     if (hipMemcpyAsync(q->queue[0], &root, sizeof(root), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(q->counts, &one, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemsetAsync(q->n_leaves, 0, 8, s) != hipSuccess)
+        hipMemcpyAsync(q->counts, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess)
         return MRH_ERR_HIP;
     // levels: a node's shorter side halves at each split, so the tree is at most
     // log2(min(width, height)) + 2 levels deep
@@ -248,10 +308,9 @@ mrh_status mrh_quadtree_build(mrh_quadtree* q, const uint8_t* rgb_dev, int32_t w
     int64_t bound = 1;
     for (int d = 0; d <= depth; ++d) {
         const int cur = d & 1;
-        if (hipMemsetAsync(q->counts + (cur ^ 1), 0, 4, s) != hipSuccess) return MRH_ERR_HIP;
         const unsigned grid = (unsigned)((std::min(bound, pixels) + 255) / 256);
         hipLaunchKernelGGL(k_qt_level, dim3(grid), dim3(256), 0, s, q->S, q->Q, width, height, threshold, min_size,
-                           q->queue[cur], q->counts + cur, q->queue[cur ^ 1], q->counts + (cur ^ 1), leaves_dev,
+                           q->queue[cur], q->counts + d, q->queue[cur ^ 1], q->counts + d + 1, leaves_dev,
                            contrast_dev, q->n_leaves, (long long)(leaves_dev || contrast_dev ? cap : 0));
         bound *= 4;
     }
