@@ -31,6 +31,61 @@ __device__ inline bool observe_pixel(const DevMap& m, const DepthFrame& f, doubl
     return observe_exact(m, x0, x1, x2, (double)d, obs);
 }
 
+// A level-0 block (one wave; lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7): the update's
+// decisions for the group, the weights after the frame (W + 1 for an updated voxel of a block that
+// merged, whose slot kept the values from before the frame), and the colours of the group, which
+// are the 8 children of coarse voxel l when the block merged.
+template <int ST>
+__device__ inline void color_fine_block(const DevMap& m, const DepthFrame& f, const uint8_t* __restrict__ rgb, int32_t bx,
+                                        int32_t by, int32_t bz, uint32_t info, uint32_t now, bool fresh, bool merged) {
+    const int lane = lane_id();
+    int I, J, K;
+    demorton3(lane, I, J, K);
+    int pix[8];
+    float obs[8];
+    const uint32_t upd = fine_decisions(m, f, f.depth, bx, by, bz, I, J, K, pix, obs);
+    if (!__ballot(upd != 0) && !fresh) return;
+    const size_t base = (size_t)(info & kSlotMask) * 512 + (size_t)lane * 8;
+    uint32_t W[8];
+    Store<ST>::getW8(m, base, W);
+    float c[24];
+    float4* cp = reinterpret_cast<float4*>(m.C[0] + 3 * base);  // 96 B per group, 16 B aligned
+    if (fresh) {
+        for (int k = 0; k < 24; ++k) c[k] = 0.f;
+    } else {
+        for (int k = 0; k < 6; ++k) {
+            const float4 v = cp[k];
+            c[4 * k] = v.x, c[4 * k + 1] = v.y, c[4 * k + 2] = v.z, c[4 * k + 3] = v.w;
+        }
+    }
+    float sw = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const bool u = (upd >> q) & 1;
+        const uint32_t Wp = merged ? W[q] + (u ? 1u : 0u) : W[q];
+        if (u) {
+            const float inv = 1.0f / (float)Wp;
+            for (int ch = 0; ch < 3; ++ch)
+                c[3 * q + ch] = c[3 * q + ch] + ((float)rgb[3 * (size_t)pix[q] + ch] - c[3 * q + ch]) * inv;
+        }
+        const float w = (float)Wp;
+        sw += w;
+        s0 += w * c[3 * q];
+        s1 += w * c[3 * q + 1];
+        s2 += w * c[3 * q + 2];
+    }
+    if (merged) {
+        const size_t at = (size_t)(now & kSlotMask) * 64 + (size_t)lane;
+        const float inv = sw > 0.f ? 1.0f / sw : 0.f;
+        float* Cc = m.C[1];
+        Cc[3 * at] = s0 * inv;
+        Cc[3 * at + 1] = s1 * inv;
+        Cc[3 * at + 2] = s2 * inv;
+    } else if (upd || fresh) {
+        for (int k = 0; k < 6; ++k) cp[k] = make_float4(c[4 * k], c[4 * k + 1], c[4 * k + 2], c[4 * k + 3]);
+    }
+}
+
 // One block (one wave): entry e as queued at the frame's start (or a new block of the frame).
 template <int ST>
 __device__ inline void color_block(const DevMap& m, const DepthFrame& f, const uint8_t* __restrict__ rgb, uint4 e,
@@ -44,6 +99,10 @@ __device__ inline void color_block(const DevMap& m, const DepthFrame& f, const u
     const uint32_t now = m.binfo[id];
     const bool merged = !fresh && !(now & kNoBlockBit) && (int)((now >> kLevelShift) & 3u) == lvl + 1;
     if (!fresh && block_hidden(m, f, bx, by, bz)) return;  // no voxel of it can be updated
+    if (lvl == 0) {
+        color_fine_block<ST>(m, f, rgb, bx, by, bz, info, now, fresh, merged);
+        return;
+    }
     const int lane = lane_id();
     float* C = m.C[lvl];
     for (int r = 0; r < nv; r += 64) {

@@ -312,22 +312,14 @@ __device__ inline void voxel_camera(const DevMap& m, const DepthFrame& f, int64_
     x2 = (f.P.R[0][2] * d0 + f.P.R[1][2] * d1) + f.P.R[2][2] * d2;
 }
 
-// Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
-template <int ST>
-__device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
-                                            const uint4 eq) {
-    const int lane = lane_id();
-    const uint4 e = uniform(eq);  // one block per wave
-    const uint32_t id = e.x, info = e.y;
-    if (info & kNoBlockBit) return TaskOut{};
-    int32_t bx, by, bz;
-    unpack_key(entry_key(e), bx, by, bz);
-    const bool fresh = (info & kNewBit) != 0;
-    const double bvs = m.bvsum[id];
-    const uint32_t bvc = m.bvcnt[id];
-    if (!fresh && block_hidden(m, f, bx, by, bz)) return TaskOut{};
-    int I, J, K;
-    demorton3(lane, I, J, K);
+// The projective decisions of lane group (I, J, K) of level-0 block (bx, by, bz): the 2x2x2 voxels
+// 2I + a, 2J + b, 2K + c at Morton positions q = a + 2 b + 4 c.  pix[q] receives the voxel's pixel
+// (-1: none), obs[q] its observation, and the returned mask has bit q set when the frame updates the
+// voxel.  Every launch that needs these decisions (the update, the colour launch) calls this one
+// function, so they agree voxel for voxel.
+__device__ inline uint32_t fine_decisions(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                          int32_t bx, int32_t by, int32_t bz, int I, int J, int K, int pix[8],
+                                          float obs[8]) {
     const double nu = m.nu[0];
     // camera-frame products of R^T (c - t), one per axis coordinate of this lane's group
     double px[2][3], py[2][3], pz[2][3];
@@ -345,7 +337,6 @@ __device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame
     // pixels first (FP64 only where FP32 cannot decide), then all depth loads at once, then the
     // observations; x recomputed by voxel_camera equals these sums bit for bit (same products, same
     // order, no contraction)
-    int pix[8];
     float lam[8];
     uint32_t exact = 0;
 #pragma unroll
@@ -370,7 +361,6 @@ __device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame
     float dq[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) dq[q] = pix[q] >= 0 ? depth[pix[q]] : -1.f;
-    float obs[8];
     uint32_t upd = 0, slow = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -397,6 +387,28 @@ __device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame
                 if (k == q) obs[k] = o;
         }
     }
+    return upd;
+}
+
+// Level-0 block: lane l owns the 2x2x2 group of Morton positions 8l .. 8l+7.
+template <int ST>
+__device__ inline TaskOut integrate_fine_block(const DevMap& m, const DepthFrame& f, const float* __restrict__ depth,
+                                            const uint4 eq) {
+    const int lane = lane_id();
+    const uint4 e = uniform(eq);  // one block per wave
+    const uint32_t id = e.x, info = e.y;
+    if (info & kNoBlockBit) return TaskOut{};
+    int32_t bx, by, bz;
+    unpack_key(entry_key(e), bx, by, bz);
+    const bool fresh = (info & kNewBit) != 0;
+    const double bvs = m.bvsum[id];
+    const uint32_t bvc = m.bvcnt[id];
+    if (!fresh && block_hidden(m, f, bx, by, bz)) return TaskOut{};
+    int I, J, K;
+    demorton3(lane, I, J, K);
+    int pix[8];
+    float obs[8];
+    const uint32_t upd = fine_decisions(m, f, depth, bx, by, bz, I, J, K, pix, obs);
     const int nupd = wave_sum((int)__popc(upd));
     if (nupd == 0 && !fresh) return TaskOut{};
     TaskOut out;

@@ -81,6 +81,12 @@ struct Store<MRH_STORE_F32> {
     __device__ static inline uint32_t getW(const DevMap& m, int lvl, size_t i) {
         return static_cast<const uint32_t*>(m.W[lvl])[i];
     }
+    // the weights of 8 consecutive level-0 voxels starting at base (a multiple of 8)
+    __device__ static inline void getW8(const DevMap& m, size_t base, uint32_t W[8]) {
+        const uint4* wp = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(m.W[0]) + base);
+        const uint4 w0 = wp[0], w1 = wp[1];
+        W[0] = w0.x, W[1] = w0.y, W[2] = w0.z, W[3] = w0.w, W[4] = w1.x, W[5] = w1.y, W[6] = w1.z, W[7] = w1.w;
+    }
     // 8 consecutive level-0 voxels starting at base (a multiple of 8)
     __device__ static inline void get8(const DevMap& m, size_t base, float D[8], uint32_t W[8], float S2[8]) {
         const float4* dp = reinterpret_cast<const float4*>(static_cast<const float*>(m.D[0]) + base);
@@ -169,6 +175,11 @@ struct Store16 {
     __device__ static inline uint4 pack8(const uint16_t o[8]) {
         return make_uint4((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16),
                           (uint32_t)o[4] | ((uint32_t)o[5] << 16), (uint32_t)o[6] | ((uint32_t)o[7] << 16));
+    }
+    __device__ static inline void getW8(const DevMap& m, size_t base, uint32_t W[8]) {
+        uint16_t wb[8];
+        unpack8(*reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(m.W[0]) + base), wb);
+        for (int q = 0; q < 8; ++q) W[q] = decW(wb[q]);
     }
     __device__ static inline void get8(const DevMap& m, size_t base, float D[8], uint32_t W[8], float S2[8]) {
         const uint4 d = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(m.D[0]) + base);
