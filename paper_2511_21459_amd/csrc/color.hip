@@ -133,12 +133,10 @@ __device__ inline void color_block(const DevMap& m, const DepthFrame& f, const u
         if (merged) {
             // the 8 children of coarse voxel v / 8 are 8 consecutive lanes (Morton order)
             float sw = (float)Wp, s0 = sw * c[0], s1 = sw * c[1], s2 = sw * c[2];
-            for (int o = 1; o < 8; o <<= 1) {
-                sw += __shfl_xor(sw, o);
-                s0 += __shfl_xor(s0, o);
-                s1 += __shfl_xor(s1, o);
-                s2 += __shfl_xor(s2, o);
-            }
+            sw = group8_sum(sw);
+            s0 = group8_sum(s0);
+            s1 = group8_sum(s1);
+            s2 = group8_sum(s2);
             if (act && (v & 7) == 0) {
                 const size_t at = (size_t)(now & kSlotMask) * (size_t)(nv / 8) + (size_t)(v >> 3);
                 float* Cc = m.C[lvl + 1];

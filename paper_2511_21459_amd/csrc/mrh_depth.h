@@ -150,19 +150,17 @@ __device__ inline bool block_hidden(const DevMap& m, const DepthFrame& f, int32_
     const double x2 = (f.P.R[0][2] * w0 + f.P.R[1][2] * w1) + f.P.R[2][2] * w2;
     // every group of 8 lanes holds the 8 corners, so these reductions are wave-uniform
     double zmin = x2;
-    for (int o = 1; o < 8; o <<= 1) zmin = __builtin_fmin(zmin, __shfl_xor(zmin, o));
+    zmin = group8_fmin(zmin);
     if (!(zmin > 1e-3)) return false;
     const double iz = 1.0 / x2;
     const double u = __builtin_fmin(__builtin_fmax(f.fx * (x0 * iz) + f.cx, -1e8), 1e8);
     const double v = __builtin_fmin(__builtin_fmax(f.fy * (x1 * iz) + f.cy, -1e8), 1e8);
     int u0 = (int)__builtin_floor(u) - 1, u1 = (int)__builtin_ceil(u) + 1;
     int v0 = (int)__builtin_floor(v) - 1, v1 = (int)__builtin_ceil(v) + 1;
-    for (int o = 1; o < 8; o <<= 1) {
-        u0 = min(u0, __shfl_xor(u0, o));
-        u1 = max(u1, __shfl_xor(u1, o));
-        v0 = min(v0, __shfl_xor(v0, o));
-        v1 = max(v1, __shfl_xor(v1, o));
-    }
+    u0 = group8_min(u0);
+    u1 = group8_max(u1);
+    v0 = group8_min(v0);
+    v1 = group8_max(v1);
     if (u1 < 0 || v1 < 0 || u0 > f.width - 1 || v0 > f.height - 1) return true;
     const int tu0 = max(u0, 0) >> 4, tu1 = min(u1, f.width - 1) >> 4;
     const int tv0 = max(v0, 0) >> 4, tv1 = min(v1, f.height - 1) >> 4;

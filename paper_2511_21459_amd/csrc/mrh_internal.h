@@ -225,24 +225,106 @@ __device__ inline unsigned long long shfl_u64(unsigned long long v, int src) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+// Cross-lane moves by DPP (gfx9): each lane reads a lane of its own 16-lane row, in the VALU, with
+// no LDS round trip.  XOR1 / XOR2 read lane i ^ 1 / i ^ 2 (quad permutations), HALF_MIRROR lane
+// 7 - i of its group of 8, ROW_MIRROR lane 15 - i of its row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ inline int dpp(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
+template <int CTRL>
+__device__ inline uint32_t dpp(uint32_t v) {
+    return (uint32_t)dpp<CTRL>((int)v);
+}
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __builtin_bit_cast(float, dpp<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ inline unsigned long long dpp(unsigned long long v) {
+    const uint32_t lo = dpp<CTRL>((uint32_t)v), hi = dpp<CTRL>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+template <int CTRL>
+__device__ inline double dpp(double v) {
+    return __builtin_bit_cast(double, dpp<CTRL>(__builtin_bit_cast(unsigned long long, v)));
+}
+
+// Sum over each group of 8 consecutive lanes, on every lane of the group, associated as
+// ((x0 + x1) + (x2 + x3)) + ((x4 + x5) + (x6 + x7)) whatever the lane (after the pairs and the quads
+// every lane of a quad holds the same value, so the mirror lane 7 - i brings the other quad's sum).
+template <typename T>
+__device__ inline T group8_sum(T v) {
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    return v + dpp<kDppHalfMirror>(v);
+}
+// The same for min / max (exact, so the order does not matter).
+template <typename T>
+__device__ inline T group8_min(T v) {
+    v = min(v, dpp<kDppXor1>(v));
+    v = min(v, dpp<kDppXor2>(v));
+    return min(v, dpp<kDppHalfMirror>(v));
+}
+template <typename T>
+__device__ inline T group8_max(T v) {
+    v = max(v, dpp<kDppXor1>(v));
+    v = max(v, dpp<kDppXor2>(v));
+    return max(v, dpp<kDppHalfMirror>(v));
+}
+__device__ inline double group8_fmin(double v) {
+    v = __builtin_fmin(v, dpp<kDppXor1>(v));
+    v = __builtin_fmin(v, dpp<kDppXor2>(v));
+    return __builtin_fmin(v, dpp<kDppHalfMirror>(v));
+}
+
+// Sum over each 16-lane row (group8_sum, then the row's other half by the row mirror).
+template <typename T>
+__device__ inline T row16_sum(T v) {
+    v = group8_sum(v);
+    return v + dpp<kDppRowMirror>(v);
+}
+
+template <typename T>
+__device__ inline T lane_value(T v, int lane);
+template <>
+__device__ inline int lane_value(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+template <>
+__device__ inline float lane_value(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+template <>
+__device__ inline unsigned long long lane_value(unsigned long long v, int lane) {
+    return ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+}
+template <>
+__device__ inline double lane_value(double v, int lane) {
+    return __builtin_bit_cast(double, lane_value(__builtin_bit_cast(unsigned long long, v), lane));
+}
+
+// Sums over the wave (all 64 lanes active), returned wave-uniform: the four row sums, then
+// (r0 + r1) + (r2 + r3).
+template <typename T>
+__device__ inline T wave_sum_rows(T v) {
+    v = row16_sum(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+__device__ inline double wave_sum(double v) { return wave_sum_rows(v); }
+__device__ inline int wave_sum(int v) { return wave_sum_rows(v); }
+__device__ inline unsigned long long wave_sum(unsigned long long v) { return wave_sum_rows(v); }
 
 __device__ inline float wave_max(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = __builtin_fmaxf(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ inline int wave_sum(int v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ inline unsigned long long wave_sum(unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
-    return v;
+    v = __builtin_fmaxf(v, dpp<kDppXor1>(v));
+    v = __builtin_fmaxf(v, dpp<kDppXor2>(v));
+    v = __builtin_fmaxf(v, dpp<kDppHalfMirror>(v));
+    v = __builtin_fmaxf(v, dpp<kDppRowMirror>(v));
+    return __builtin_fmaxf(__builtin_fmaxf(lane_value(v, 0), lane_value(v, 16)),
+                           __builtin_fmaxf(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // add to a per-frame statistic (striped by workgroup)

@@ -130,11 +130,9 @@ __device__ inline void merge_level1_into(const DevMap& m, uint32_t id, uint32_t 
     const int lane = lane_id();
     uint32_t Wc = W;
     float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
-    for (int o = 1; o < 8; o <<= 1) {
-        Wc += (uint32_t)__shfl_xor((int)Wc, o);
-        sd += __shfl_xor(sd, o);
-        s2 += __shfl_xor(s2, o);
-    }
+    Wc = group8_sum(Wc);
+    sd = group8_sum(sd);
+    s2 = group8_sum(s2);
     const bool writer = (lane & 7) == 0;
     float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
     float Sc = Wc > 0 ? s2 : 0.f;
@@ -333,11 +331,9 @@ __device__ inline int finish_coarse(const DevMap& m, uint32_t id, uint32_t info,
     }
     uint32_t Wc = W;
     float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
-    for (int o = 1; o < 8; o <<= 1) {
-        Wc += (uint32_t)__shfl_xor((int)Wc, o);
-        sd += __shfl_xor(sd, o);
-        s2 += __shfl_xor(s2, o);
-    }
+    Wc = group8_sum(Wc);
+    sd = group8_sum(sd);
+    s2 = group8_sum(s2);
     const bool writer = lane < nv && (lane & 7) == 0;
     float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
     float Sc = Wc > 0 ? s2 : 0.f;
@@ -362,10 +358,10 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
                                     uint32_t W, float S2, bool dirty, int nupd, double dsum, int dcnt) {
     const int par = 0;  // levels >= 2 free into the single list of their level
     const int lane = lane_id();
-    for (int o = 1; o < seg; o <<= 1) {
-        dsum += __shfl_xor(dsum, o);
-        dcnt += __shfl_xor(dcnt, o);
-        nupd += __shfl_xor(nupd, o);
+    if (seg == 8) {
+        dsum = group8_sum(dsum);
+        dcnt = group8_sum(dcnt);
+        nupd = group8_sum(nupd);
     }
     const bool leader = (lane % seg) == 0;
     double vsum = 0.0;
@@ -391,10 +387,10 @@ __device__ inline int finish_packed(const DevMap& m, bool live, uint32_t id, uin
     // only level 2 (seg = 8) can merge: pool the segment's 8 voxels into the single level-3 voxel
     uint32_t Wc = W;
     float sd = W ? (float)W * D : 0.f, s2 = W ? S2 : 0.f;
-    for (int o = 1; o < seg; o <<= 1) {
-        Wc += (uint32_t)__shfl_xor((int)Wc, o);
-        sd += __shfl_xor(sd, o);
-        s2 += __shfl_xor(s2, o);
+    if (seg == 8) {
+        Wc = group8_sum(Wc);
+        sd = group8_sum(sd);
+        s2 = group8_sum(s2);
     }
     if (leader) {
         float Dc = Wc > 0 ? sd / (float)Wc : 0.f;
