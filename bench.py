@@ -134,8 +134,12 @@ def compare_arrays(ref, got, flips=False, tau=None):
     common, ia, ib = np.intersect1d(ca, cb, return_indices=True)
     same = la[ia] == lb[ib]
     ia, ib = ia[same], ib[same]
-    sa = np.concatenate([np.arange(oa[i], oa[i + 1]) for i in ia]) if len(ia) else np.zeros(0, int)
-    sb = np.concatenate([np.arange(ob[i], ob[i + 1]) for i in ib]) if len(ib) else np.zeros(0, int)
+    def voxels(off, idx):  # the voxel rows of blocks idx, block after block
+        n = (off[idx + 1] - off[idx]).astype(np.int64)
+        starts = np.repeat(off[idx].astype(np.int64) - np.concatenate([[0], np.cumsum(n)[:-1]]), n)
+        return starts + np.arange(int(n.sum()), dtype=np.int64)
+
+    sa, sb = voxels(oa, ia), voxels(ob, ib)
     obs = (Wa[sa] > 0) & (Wb[sb] > 0)
     d = np.abs(Da[sa] - Db[sb])[obs]
     out = {"blocks_compared": int(len(ia)), "blocks_level_differs": int((~same).sum()),
@@ -253,6 +257,52 @@ def run_room(args, torch, np, mrh, configs, room_sequence):
     return dict(depths=depths, cam=cam, poses=poses, scene=scene, W=W, H=H, census=census, wall=wall,
                 gpu_ms=gpu_ms, prof=prof, avg_launch_s=avg_launch_s, bytes_per_launch=bytes_per_launch,
                 tot=tot, precision=precision, fmap=fmap, frame_ms=frame_ms, arrays=arrays)
+
+
+ROTATED_COPIES = 5
+
+
+def run_room_rotated(room, torch, np, mrh, configs, copies=ROTATED_COPIES):
+    """The room sequence fused into `copies` separate maps frame by frame in turn (map 0, 1, ..., then
+    the next frame), so that each map's touched state has left the 256 MB Infinity Cache by the time
+    its next frame comes (copies x ~250 MB of state): the update's roofline with its state in HBM,
+    in FP32 and in FP16."""
+    dev = torch.from_numpy(room["depths"]).cuda()
+    K, poses, n = room["cam"].K, room["poses"], len(room["poses"])
+    out = {"copies": copies}
+    for st in ("f32", "f16"):
+        maps = [mrh.Map(**dict(configs.ROOM, storage=st)) for _ in range(copies)]
+
+        def step():
+            for m in maps:
+                m.reset()
+            for k in range(n):
+                for m in maps:
+                    m.integrate_depth(dev[k], K, poses[k])
+
+        step()
+        t = timed(step, 2, torch)
+        for m in maps:
+            m.profile(True)
+        step()
+        profs = [m.profile_collect() for m in maps]
+        for m in maps:
+            m.profile(False)
+            m.close()
+        k_ms = sum(p["integrate_depth"][0] for p in profs)
+        k_n = sum(p["integrate_depth"][1] for p in profs)
+        a_ms = sum(p["alloc_depth"][0] for p in profs)
+        byts = algorithmic_bytes_integrate(room["census"], room["W"], room["H"], s=STATE_BYTES[st]) / n
+        avg_s = k_ms / k_n / 1e3
+        achieved = byts / avg_s / 1e9
+        out[st] = {"ms_per_frame": round(t * 1e3 / (n * copies), 4),
+                   "m_points_per_s": round(sum(f["valid_points"] for f in room["census"]) * copies / t / 1e6, 1),
+                   "integrate_avg_launch_us": round(avg_s * 1e6, 3), "alloc_avg_launch_us": round(a_ms / k_n * 1e3, 3),
+                   "roofline": {"kernel": "k_integrate_depth", "bound": "hbm", "achieved": round(achieved, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                "bytes_per_launch": int(byts)}}
+    out["f16_speedup_vs_f32"] = round(out["f32"]["ms_per_frame"] / out["f16"]["ms_per_frame"], 3)
+    return out
 
 
 RGBD_STREAMS = [(320, 240), (384, 288), (416, 312), (480, 360), (512, 384), (560, 420), (608, 456), (640, 480)]
@@ -394,7 +444,22 @@ def run_street(args, torch, np, mrh, configs):
     m.profile(False)
     _, tot = m.sync()
     chk = m.check()
+    ref = map_arrays(m)
     m.close()
+    precision = {}
+    for st in ("f16", "bf16"):
+        pm = mrh.Map(**dict(cfg, storage=st))
+
+        def pstep():
+            pm.reset()
+            pm.integrate_points_sequence(dev, poses)
+
+        pstep()
+        tp = timed(pstep, 2, torch)
+        precision[st] = {"ms_per_scan": round(tp * 1e3 / n, 4), "speedup_vs_f32": round(t / tp, 3),
+                         "vs_f32_gpu": compare_arrays(ref, map_arrays(pm))}
+        pm.close()
+    del ref
     stream = run_street_streaming(np, mrh, cfg, dev, poses, tot["blocks"])
     valid = sum(f["valid_points"] for f in census)
     obs = sum(f["observations"] for f in census)
@@ -423,6 +488,7 @@ def run_street(args, torch, np, mrh, configs):
         "map_check": {"consistent": chk["consistent"], "mean_probe": round(chk["mean_probe"], 3),
                       "max_probe": chk["max_probe"], "table_load": round(chk["table_keys"] / cfg["hash_slots"], 4)},
         "errors": tot["error_flags"],
+        "precision": precision,
         "streaming": stream})
 
 
@@ -667,7 +733,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
-    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh", "color"],
+    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh", "color", "rotated"],
                     help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -699,6 +765,10 @@ def main():
         fm.sync()
         room = dict(depths=depths, cam=cam, poses=poses, scene=scene, fmap=fm)
         print(json.dumps({"mesh": run_mesh(room, torch, np, mrh, configs)}), flush=True)
+        return
+    if args.only == "rotated":
+        room = run_room(args, torch, np, mrh, configs, room_sequence)
+        print(json.dumps({"room_rotated": run_room_rotated(room, torch, np, mrh, configs)}), flush=True)
         return
     if args.only == "color":
         depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
@@ -751,6 +821,7 @@ def main():
         result["batched"] = run_batched(args, torch, np, mrh, configs)
         result["query"] = run_query(room, torch, np, mrh)
         result["mesh"] = run_mesh(room, torch, np, mrh, configs)
+        result["room_rotated"] = run_room_rotated(room, torch, np, mrh, configs)
         result["color"] = run_color(room, torch, np, mrh, configs)
         result["quadtree"] = run_quadtree(room, torch, np, mrh)
         result["sweep"] = run_sweep(room, torch, np, mrh, configs)
