@@ -89,8 +89,8 @@ struct DevMap {
     void* S2[4];
     float* C[4];  // per level, colour RGB float32 x 3 per voxel (maps created with colour; else null)
     // LiDAR per-frame accumulators, parallel to the heaps (zero between frames):
-    // saturated (+tau) observation counts, band observation counts, and fixed-point sums of
-    // (d - D) and (d - D)^2 relative to the voxel's mean at the start of the frame
+    // saturated (+tau) observation counts, band observation counts, and the exact integer sums of
+    // the band observations' fixed-point values q = rint(d 2^24) and of q^2
     uint32_t* acc_sat[4];
     uint32_t* acc_band[4];
     unsigned long long* acc_s1[4];

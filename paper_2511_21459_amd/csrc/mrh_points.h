@@ -7,10 +7,11 @@
 //   points_ray_chunk    8 rays: their recorded (ray, block) pairs in parallel; inside each block a
 //                       walk over the block's own voxel lattice; each crossed voxel gets
 //                       clip((p - x) . n, -tau, tau).
-//                       Saturated observations (+tau) only bump an integer count; the others add to
-//                       fixed-point sums of (d - D) and (d - D)^2, D being the voxel's mean at the
-//                       start of the scan, so the accumulation is exact and order-independent.  A
-//                       block's first touch in the scan queues it on its level's list.
+//                       Saturated observations (+tau) only bump an integer count; the others add
+//                       their fixed-point value q = rint(d 2^24) and its square q^2 to exact integer
+//                       sums, so the accumulation is order-independent and needs no read of the
+//                       voxel's state; the update forms the sums of (d - D) and (d - D)^2 from them.
+//                       A block's first touch in the scan queues it on its level's list.
 //   points_update_task  one queued level-0 or level-1 block (a wave), or 8 level-2 / 64 level-3
 //                       blocks per wave: each voxel's scan statistics merge into its state (W' =
 //                       W + n, D' = D + s1 / W', S2' = S2 + s2 - s1^2 / W', the batch form of Eq. 3
@@ -21,8 +22,8 @@
 
 namespace mrh {
 
-constexpr double kS1Scale = 16777216.0;         // 2^24 per metre
-constexpr double kS2Scale = 281474976710656.0;  // 2^48 per square metre
+constexpr double kS1Scale = 16777216.0;         // 2^24 per metre: q = rint(d 2^24), |q| <= tau 2^24
+constexpr double kS2Scale = 281474976710656.0;  // 2^48 per square metre: the sum of q^2
 
 struct ScanParams {
     int32_t parity;  // the frame's parity (selects the double-buffered per-frame counts)
@@ -169,19 +170,17 @@ __device__ inline void sat_table_flush(const DevMap& m, unsigned long long* tab)
 }
 
 // Accumulate one observation d of the voxel at heap position `at` of `level`; `near` routes a
-// saturated one through the workgroup table.
-template <int ST>
-__device__ inline void accumulate(const DevMap& m, int level, size_t at, bool fresh, double d, bool near,
-                                  unsigned long long* tab) {
+// saturated one through the workgroup table.  A band observation adds 1, q and q^2 (q its
+// fixed-point value): exact integers, fire-and-forget atomics with no dependent load.
+__device__ inline void accumulate(const DevMap& m, int level, size_t at, double d, bool near, unsigned long long* tab) {
     if (d >= m.tau) {
         if (!(near && sat_table_add(tab, level, at))) atomicAdd(&m.acc_sat[level][at], 1u);
         return;
     }
-    const double Dp = fresh ? 0.0 : (double)Store<ST>::getD(m, level, at);
-    const double r = d - Dp;
+    const long long q = (long long)__builtin_rint(d * kS1Scale);
     atomicAdd(&m.acc_band[level][at], 1u);
-    atomicAdd(&m.acc_s1[level][at], (unsigned long long)(long long)__builtin_rint(r * kS1Scale));
-    atomicAdd(&m.acc_s2[level][at], (unsigned long long)__builtin_rint((r * r) * kS2Scale));
+    atomicAdd(&m.acc_s1[level][at], (unsigned long long)q);
+    atomicAdd(&m.acc_s2[level][at], (unsigned long long)(q * q));
 }
 
 // The block walk restricted to one block: the segment is clipped to the block's box, the walk
@@ -267,7 +266,6 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
     const bool has = !(info & kNoBlockBit);
     unsigned long long groups = 0ull;  // the update's lane groups this ray touches in the block
     if (has) {
-        const bool fresh = (info & kNewBit) != 0;
         const int side = 8 >> level;
         const size_t base = (size_t)(info & kSlotMask) * (size_t)(side * side * side);
         const double nu = m.nu[level];
@@ -288,7 +286,7 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
             }
             const uint32_t mo = morton3(bw.c0, bw.c1, bw.c2);
             groups |= 1ull << (level == 0 ? mo >> 3 : (level == 1 ? mo : 0u));
-            accumulate<ST>(m, level, base + (size_t)mo, fresh, d, near, tab);
+            accumulate(m, level, base + (size_t)mo, d, near, tab);
             if (s == 3 * side || !bw.next()) break;
         }
     }
@@ -364,14 +362,19 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
     sat_table_flush(m, tab);
 }
 
-// Batch form of Eq. 3 and Eq. 5 for n observations with sums s1, s2 of (d - D) and (d - D)^2.
+// Batch form of Eq. 3 and Eq. 5 for the scan's observations of one voxel: nsat at +tau, and nband
+// in the band with sums s1q of q and s2q of q^2 (q = rint(d 2^24)).  With T and Q those sums in
+// metres, the band's sums of (d - D) and (d - D)^2 are T - n D and Q - 2 D T + n D^2.
 __device__ inline void apply_stats(const DevMap& m, uint32_t nsat, uint32_t nband, unsigned long long s1q,
                                    unsigned long long s2q, float& D, uint32_t& W, float& S2) {
     const uint32_t nobs = nsat + nband;
     const double Dp = (double)D;
     const double ts = m.tau - Dp;
-    const double s1 = (double)nsat * ts + (double)(long long)s1q / kS1Scale;
-    const double s2 = (double)nsat * (ts * ts) + (double)s2q / kS2Scale;
+    const double nb = (double)nband;
+    const double T = (double)(long long)s1q / kS1Scale, Q = (double)s2q / kS2Scale;
+    const double b2 = (Q - 2.0 * Dp * T) + nb * (Dp * Dp);
+    const double s1 = (double)nsat * ts + (T - nb * Dp);
+    const double s2 = (double)nsat * (ts * ts) + (b2 > 0.0 ? b2 : 0.0);
     const double Wn = (double)W + (double)nobs;
     const double S2n = (double)S2 + s2 - s1 * s1 / Wn;
     D = (float)(Dp + s1 / Wn);
