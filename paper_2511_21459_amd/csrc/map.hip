@@ -139,7 +139,7 @@ static void free_all(mrh_map* m) {
     if (d.btouch) (void)hipFree(d.btouch);
     for (int p = 0; p < 2; ++p)
         if (d.pend0[p]) (void)hipFree(d.pend0[p]);
-    if (d.rkeys) (void)hipFree(d.rkeys);
+    if (d.rslots) (void)hipFree(d.rslots);
     if (d.rcount) (void)hipFree(d.rcount);
     if (m->tile_max) (void)hipFree(m->tile_max);
     for (int n = 0; n < 4; ++n)

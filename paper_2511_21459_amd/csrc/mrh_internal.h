@@ -98,9 +98,10 @@ struct DevMap {
     // per block: the lane groups rays touched this frame, bit g = the voxels lane g of the update
     // owns (level 0: Morton positions 8g .. 8g+7, level 1: position g; levels 2, 3: bit 0)
     unsigned long long* btouch;
-    // LiDAR: the block keys each ray's walk visits, in walk order (rcap_k per ray, written by the
-    // allocation launch), and their count per ray (may exceed rcap_k)
-    unsigned long long* rkeys;
+    // LiDAR: the hash slots of the block keys each ray's walk visits, in walk order (rcap_k per ray,
+    // written by the allocation launch; kInvalidId for a key the full table could not take), and
+    // their count per ray (may exceed rcap_k)
+    uint32_t* rslots;
     uint32_t* rcount;
     int32_t rcap_k;
     uint4* vis[4];     // per level: the blocks the update visits this frame, (id, info, key lo, key hi)
@@ -190,20 +191,23 @@ enum InsertResult { INS_FOUND = 0, INS_NEW = 1, INS_FULL = 2 };
 // Lock-free linear-probing insert from slot `start` (the first EMPTY slot a read-only probe met).
 // Keys are only ever written by this CAS, so the returned old value decides every race.  The CAS
 // at `start` is issued without re-reading the slot (the probe saw it empty; the CAS's old value
-// says whether it still was), which saves a round trip on every new key.
+// says whether it still was), which saves a round trip on every new key.  *slot receives the slot
+// holding the key (inserted or found).
 __device__ inline int probe_insert(const DevMap& m, unsigned long long key, uint32_t start, uint32_t* slot) {
     uint32_t h = start;
     for (int p = 0; p < m.max_probe; ++p) {
         const unsigned long long k =
             p == 0 ? kEmptyKey : __hip_atomic_load(&m.hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == key) return INS_FOUND;
+        if (k == key) {
+            *slot = h;
+            return INS_FOUND;
+        }
         if (k == kEmptyKey) {
             const unsigned long long old = atomicCAS(&m.hkeys[h], kEmptyKey, key);
-            if (old == kEmptyKey) {
+            if (old == kEmptyKey || old == key) {
                 *slot = h;
-                return INS_NEW;
+                return old == key ? INS_FOUND : INS_NEW;
             }
-            if (old == key) return INS_FOUND;
         }
         h = (h + 1) & m.hmask;
     }

@@ -54,7 +54,7 @@ constexpr int kAllocRaysPerWave = 4;
 constexpr int kAllocRaysPerGroup = 4 * kAllocRaysPerWave;
 
 // Allocation for rays chunk * kAllocRaysPerGroup ..: the block walk of each ray, the wave-
-// deduplicated insert of the keys, and the record of each ray's keys in walk order.  A ray's walk
+// deduplicated insert of the keys, and the record of the hash slot of each ray's keys in walk order.  A ray's walk
 // is a chain of lookups, so it advances kAllocRound blocks at a time: the ray's lane runs that many
 // DDA steps (arithmetic only) and leaves the keys in LDS, and then every lane of the wave claims one
 // key (ray = lane / kAllocRound, step = lane % kAllocRound): one round of probes and inserts for the
@@ -83,7 +83,7 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
     // the ray and walk step whose key this lane claims in each round
     const int ray = lane / kAllocRound, k = lane % kAllocRound;
     const int64_t ri = r0 + ray;
-    unsigned long long* rk = m.rkeys + (size_t)(ri < sp.n ? ri : 0) * (size_t)m.rcap_k;
+    uint32_t* rs = m.rslots + (size_t)(ri < sp.n ? ri : 0) * (size_t)m.rcap_k;
     while (__ballot(active)) {
         uint32_t cnt = 0;
         if (mine) {
@@ -105,8 +105,10 @@ __device__ inline void points_alloc_chunk(const DevMap& m, const ScanParams& sp,
         const unsigned long long key = skeys[wv][lane];
         const uint32_t rcnt = (uint32_t)__shfl((int)cnt, ray), rsteps = (uint32_t)__shfl((int)steps, ray);
         const bool has = (uint32_t)k < rcnt;
-        insert_keys(m, has, key);
-        if (has && rsteps + (uint32_t)k < (uint32_t)m.rcap_k) rk[rsteps + (uint32_t)k] = key;
+        uint32_t slot = kInvalidId;
+        const bool is_new = claim_keys(m, has, key, &slot);
+        register_new(m, is_new, key, slot);
+        if (has && rsteps + (uint32_t)k < (uint32_t)m.rcap_k) rs[rsteps + (uint32_t)k] = slot;
         steps += cnt;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -252,15 +254,15 @@ struct BoxWalk {
 };
 
 // The observations of one ray (segment a..e, surface point p, direction nn) inside the block
-// `key` that its walk visits: the block walk restricted to the block's own voxel lattice.
+// `key` (block id `id`, kInvalidId when it has none) that its walk visits: the block walk restricted
+// to the block's own voxel lattice.
 template <int ST>
 __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const double a[3], const double e[3],
-                                 const double p[3], const double nn[3], unsigned long long key,
+                                 const double p[3], const double nn[3], unsigned long long key, uint32_t id,
                                  unsigned long long* tab) {
     int32_t bx, by, bz;
     unpack_key(key, bx, by, bz);
     const int64_t b[3] = {bx, by, bz};
-    const uint32_t id = find_block(m, key);
     const uint32_t info = id == kInvalidId ? kNoBlockBit : m.binfo[id];
     const int level = (int)((info >> kLevelShift) & 3u);
     const bool has = !(info & kNoBlockBit);
@@ -326,6 +328,23 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
     const uint32_t total = (uint32_t)__shfl((int)incl, 63);
     const uint32_t excl = incl - c;
     double a[3], e[3], p[3], nn[3];
+    // each ray's segment, once, by its own lane; the lanes of its (ray, block) pairs read it from LDS
+    __shared__ double seg[4][kRaysPerWave][12];
+    const int wv = (int)(threadIdx.x >> 6);
+    if (c > 0) {
+        point_segment(m, sp, own, a, e, p, nn);  // valid: the ray has recorded blocks
+        for (int k = 0; k < 3; ++k) {
+            seg[wv][lane][k] = a[k];
+            seg[wv][lane][3 + k] = e[k];
+            seg[wv][lane][6 + k] = p[k];
+            seg[wv][lane][9 + k] = nn[k];
+        }
+    }
+    // LDS operations of one wave complete in order; the fences keep the compiler from moving the
+    // reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (uint32_t base = 0; base < total; base += 64) {
         const uint32_t q = base + (uint32_t)lane;
         // owner: the largest lane j with excl_j <= q (excl is non-decreasing over the lanes)
@@ -337,25 +356,35 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
         const uint32_t ej = (uint32_t)__shfl((int)excl, j);
         if (q < total) {
             const int64_t i = r0 + j;
-            point_segment(m, sp, i, a, e, p, nn);  // valid: the ray has recorded blocks
-            ray_block<ST>(m, sp, a, e, p, nn, m.rkeys[(size_t)i * K + (q - ej)], tab);
+            double sa[3], se[3], sp3[3], sn[3];
+            for (int k = 0; k < 3; ++k) {
+                sa[k] = seg[wv][j][k];
+                se[k] = seg[wv][j][3 + k];
+                sp3[k] = seg[wv][j][6 + k];
+                sn[k] = seg[wv][j][9 + k];
+            }
+            const uint32_t slot = m.rslots[(size_t)i * K + (q - ej)];
+            const bool ok = slot != kInvalidId;
+            const unsigned long long key = ok ? m.hkeys[slot] : 0ull;
+            const uint32_t id = ok ? m.hvals[slot] : kInvalidId;
+            ray_block<ST>(m, sp, sa, se, sp3, sn, key, id, tab);
         }
     }
     if (cnt > K) {
         point_segment(m, sp, own, a, e, p, nn);
         // the walk state waits in LDS while a block is traversed (registers would hold both)
-        __shared__ Walk wsave[256];
+        __shared__ Walk wsave[4][kRaysPerWave];  // lanes below kRaysPerWave own the rays
         Walk w;
         w.init(a, e, m.invB);
         bool more = true;
         for (uint32_t s = 0; s < K && more; ++s) more = w.next();
         while (more) {
             const unsigned long long key = pack_key(w.c0, w.c1, w.c2);
-            wsave[threadIdx.x] = w;
+            wsave[wv][lane] = w;
             __asm__ volatile("" ::: "memory");
-            ray_block<ST>(m, sp, a, e, p, nn, key, tab);
+            ray_block<ST>(m, sp, a, e, p, nn, key, find_block(m, key), tab);
             __asm__ volatile("" ::: "memory");
-            w = wsave[threadIdx.x];
+            w = wsave[wv][lane];
             more = w.next();
         }
     }

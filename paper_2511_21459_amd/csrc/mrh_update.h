@@ -606,38 +606,43 @@ __device__ inline void register_new(const DevMap& m, bool is_new, unsigned long 
 // nothing; the missing ones are deduplicated across the wave (register-only ballots) and then one
 // leader per distinct key does the CAS insert, all leaders at once, so that a wave with several
 // new keys waits for one insert, not one after another.  Returns true on the lane that inserted a
-// new key (its hash slot in *slot).
+// new key; *slot receives, on every lane with a key, the hash slot holding it (kInvalidId when the
+// table was full).
 __device__ inline bool claim_keys(const DevMap& m, bool has_key, unsigned long long key, uint32_t* slot) {
     const int lane = lane_id();
-    uint32_t stop = kInvalidId;
+    uint32_t stop = kInvalidId, found = kInvalidId;
     bool need = false;
-    if (has_key) need = probe_find(m, key, &stop) == kInvalidId;
+    if (has_key) {
+        found = probe_find(m, key, &stop);
+        need = found == kInvalidId;
+    }
     bool leader = false;
+    int src = lane;  // the lane whose insert decides this lane's key
     unsigned long long pending = __ballot(need);
     while (pending) {
         const int first = __ffsll((long long)pending) - 1;
         const unsigned long long lkey = shfl_u64(key, first);
-        pending &= ~__ballot(need && key == lkey);
+        const bool same = need && key == lkey;
+        pending &= ~__ballot(same);
+        if (same) src = first;
         leader |= lane == first;
     }
     bool is_new = false;
+    uint32_t got = kInvalidId;
     if (leader) {
-        const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, slot);
+        const int r = stop == kInvalidId ? INS_FULL : probe_insert(m, key, stop, &got);
         if (r == INS_NEW) {
             is_new = true;
         } else if (r == INS_FULL) {
+            got = kInvalidId;
             atomicOr(&m.ctr->error_flags.v, kErrTableFull);
             stat_add(m, S_FAILED, 1ull);
         }
     }
+    const uint32_t from_leader = (uint32_t)__shfl((int)got, src);
+    *slot = need ? from_leader : found;
     return is_new;
 }
 
-// Wave-cooperative insert of one key per lane (has_key): claim, then register the new blocks.
-__device__ inline void insert_keys(const DevMap& m, bool has_key, unsigned long long key) {
-    uint32_t slot = 0;
-    const bool is_new = claim_keys(m, has_key, key, &slot);
-    register_new(m, is_new, key, slot);
-}
 
 }  // namespace mrh

@@ -77,12 +77,12 @@ mrh_status ensure_lidar(mrh_map* map, int64_t n) {
     }
     if (st == MRH_OK && n > map->rcap_n) {
         st = check_hip(map, hipStreamSynchronize(map->stream), "ray buffers");
-        if (d.rkeys) (void)hipFree(d.rkeys);
+        if (d.rslots) (void)hipFree(d.rslots);
         if (d.rcount) (void)hipFree(d.rcount);
-        d.rkeys = nullptr;
+        d.rslots = nullptr;
         d.rcount = nullptr;
         map->rcap_n = 0;
-        alloc((void**)&d.rkeys, (size_t)n * (size_t)d.rcap_k * 8, "ray block keys");
+        alloc((void**)&d.rslots, (size_t)n * (size_t)d.rcap_k * 4, "ray block slots");
         alloc((void**)&d.rcount, (size_t)n * 4, "ray block counts");
         if (st == MRH_OK) map->rcap_n = n;
     }
