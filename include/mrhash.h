@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-#define MRH_ABI_VERSION 1
+#define MRH_ABI_VERSION 2
 
 typedef int32_t mrh_status;
 enum {
@@ -343,14 +343,17 @@ void mrh_batch_destroy(mrh_batch* batch);
 mrh_status mrh_batch_integrate(mrh_batch* batch, const mrh_frame* frames);
 
 /* Launch shape of the batched kernels: params[0] = workgroups of the update launch, params[1] =
- * cull workgroups per depth map, params[2] = 1 to replay a captured graph, 0 to launch directly. */
-mrh_status mrh_batch_set_launch(mrh_batch* batch, const int32_t params[3]);
-mrh_status mrh_batch_get_launch(const mrh_batch* batch, int32_t params[3]);
+ * cull workgroups per depth map, params[2] = 1 to replay a captured graph, 0 to launch directly,
+ * params[3] = waves per workgroup of the update launch (1, 2 or 4; a wave takes one task at a time,
+ * so this sets how many tasks share a workgroup's start-up and statistics flush). */
+mrh_status mrh_batch_set_launch(mrh_batch* batch, const int32_t params[4]);
+mrh_status mrh_batch_get_launch(const mrh_batch* batch, int32_t params[4]);
 
-/* Autotuner: for every candidate launch shape, reset all maps and time `reps` calls of
- * mrh_batch_integrate(frames) with HIP events; keep the fastest shape (written to best[3]) and
- * leave every map reset.  Meant for start-up, before the real stream of frames. */
-mrh_status mrh_batch_autotune(mrh_batch* batch, const mrh_frame* frames, int32_t reps, int32_t best[3]);
+/* Autotuner: for every candidate launch shape (update workgroups x cull workgroups x waves per
+ * update workgroup), reset all maps and time `reps` calls of mrh_batch_integrate(frames) with HIP
+ * events; keep the fastest shape (written to best[4]) and leave every map reset.  Meant for
+ * start-up, before the real stream of frames. */
+mrh_status mrh_batch_autotune(mrh_batch* batch, const mrh_frame* frames, int32_t reps, int32_t best[4]);
 
 /* ---- Capacity-driven streaming (Sec. 3.3) -------------------------------------------------
  * Voxel blocks move between the GPU heaps and a host store owned by the map.  Streaming out is

@@ -487,21 +487,21 @@ class Batch:
         if st != 0:
             raise MrhError(st, "mrh_batch_integrate", _lib.load().mrh_last_error(self.maps[0]._h).decode())
 
-    def set_launch(self, update_wgs: int, cull_wgs: int, graph: bool = True):
-        p = (ctypes.c_int32 * 3)(update_wgs, cull_wgs, int(graph))
+    def set_launch(self, update_wgs: int, cull_wgs: int, graph: bool = True, update_waves: int = 4):
+        p = (ctypes.c_int32 * 4)(update_wgs, cull_wgs, int(graph), update_waves)
         st = _lib.load().mrh_batch_set_launch(self._h, p)
         if st != 0:
             raise MrhError(st, "mrh_batch_set_launch")
 
     def get_launch(self):
-        p = (ctypes.c_int32 * 3)()
+        p = (ctypes.c_int32 * 4)()
         _lib.load().mrh_batch_get_launch(self._h, p)
         return tuple(p)
 
     def autotune(self, frames, reps: int = 3):
         """Time every candidate launch shape on `frames` (maps are reset before and after)."""
         arr = self._frames(frames)
-        best = (ctypes.c_int32 * 3)()
+        best = (ctypes.c_int32 * 4)()
         st = _lib.load().mrh_batch_autotune(self._h, arr, int(reps), best)
         if st != 0:
             raise MrhError(st, "mrh_batch_autotune", _lib.load().mrh_last_error(self.maps[0]._h).decode())

@@ -171,7 +171,7 @@ struct mrh_batch {
     hipEvent_t copied[2] = {nullptr, nullptr};
     int buf = 0;
     std::vector<uint32_t> dm_seen;  // each map's descriptor version when d_maps was last uploaded
-    int32_t update_wgs = 1024, cull_wgs = 32, use_graph = 1;
+    int32_t update_wgs = 1024, cull_wgs = 32, use_graph = 1, update_waves = 4;
     hipGraphExec_t exec = nullptr;
     std::vector<int64_t> graph_sig;  // launch geometry the graph was captured with
 };
@@ -201,13 +201,13 @@ static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32
         }
     }
     // at least one workgroup per map: workgroup i carries map i's update-side hand-off
-    const dim3 ug((unsigned)(b->update_wgs > n ? b->update_wgs : n));
+    const dim3 ug((unsigned)(b->update_wgs > n ? b->update_wgs : n)), ub((unsigned)(64 * b->update_waves));
     auto update = [&](auto kind) {
         constexpr int K = decltype(kind)::value;
         switch (b->storage) {
-            case MRH_STORE_F16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F16, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
-            case MRH_STORE_BF16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_BF16, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
-            default: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F32, K>), ug, dim3(256), 0, s, b->d_maps, b->d_ents, n);
+            case MRH_STORE_F16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F16, K>), ug, ub, 0, s, b->d_maps, b->d_ents, n); break;
+            case MRH_STORE_BF16: hipLaunchKernelGGL((k_batch_update<MRH_STORE_BF16, K>), ug, ub, 0, s, b->d_maps, b->d_ents, n); break;
+            default: hipLaunchKernelGGL((k_batch_update<MRH_STORE_F32, K>), ug, ub, 0, s, b->d_maps, b->d_ents, n);
         }
     };
     if (depth_maps) update(std::integral_constant<int, MRH_FRAME_DEPTH>());
@@ -269,20 +269,24 @@ void mrh_batch_destroy(mrh_batch* b) {
     delete b;
 }
 
-mrh_status mrh_batch_set_launch(mrh_batch* b, const int32_t params[3]) {
-    if (!b || !params || params[0] < 1 || params[0] > 65536 || params[1] < 1 || params[1] > 4096) return MRH_ERR_INVALID_ARG;
-    if (params[0] != b->update_wgs || params[1] != b->cull_wgs) drop_graph(b);
+mrh_status mrh_batch_set_launch(mrh_batch* b, const int32_t params[4]) {
+    if (!b || !params || params[0] < 1 || params[0] > 65536 || params[1] < 1 || params[1] > 4096 ||
+        (params[3] != 1 && params[3] != 2 && params[3] != 4))
+        return MRH_ERR_INVALID_ARG;
+    if (params[0] != b->update_wgs || params[1] != b->cull_wgs || params[3] != b->update_waves) drop_graph(b);
     b->update_wgs = params[0];
     b->cull_wgs = params[1];
     b->use_graph = params[2] != 0;
+    b->update_waves = params[3];
     return MRH_OK;
 }
 
-mrh_status mrh_batch_get_launch(const mrh_batch* b, int32_t params[3]) {
+mrh_status mrh_batch_get_launch(const mrh_batch* b, int32_t params[4]) {
     if (!b || !params) return MRH_ERR_INVALID_ARG;
     params[0] = b->update_wgs;
     params[1] = b->cull_wgs;
     params[2] = b->use_graph;
+    params[3] = b->update_waves;
     return MRH_OK;
 }
 
@@ -321,6 +325,7 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
     std::vector<int64_t> sig;
     sig.push_back(b->update_wgs);
     sig.push_back(b->cull_wgs);
+    sig.push_back(b->update_waves);
     uint32_t alloc_wgs = 0, ray_wgs = 0;
     int depth_maps = 0, point_maps = 0;
     for (int i = 0; i < n; ++i) {
@@ -394,33 +399,38 @@ mrh_status mrh_batch_integrate(mrh_batch* b, const mrh_frame* frames) {
     return st;
 }
 
-mrh_status mrh_batch_autotune(mrh_batch* b, const mrh_frame* frames, int32_t reps, int32_t best[3]) {
+mrh_status mrh_batch_autotune(mrh_batch* b, const mrh_frame* frames, int32_t reps, int32_t best[4]) {
     if (!b || !frames || reps < 1 || !best) return MRH_ERR_INVALID_ARG;
     static const int32_t kUpdate[] = {256, 512, 1024, 2048, 4096};
     static const int32_t kCull[] = {16, 64};
+    static const int32_t kWaves[] = {1, 2, 4};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MRH_ERR_HIP;
     float best_ms = 1e30f;
-    int32_t keep[3] = {b->update_wgs, b->cull_wgs, b->use_graph};
+    int32_t keep[4] = {b->update_wgs, b->cull_wgs, b->use_graph, b->update_waves};
     mrh_status st = MRH_OK;
     for (int32_t u : kUpdate) {
         for (int32_t c : kCull) {
-            const int32_t p[3] = {u, c, 1};
-            mrh_batch_set_launch(b, p);
-            for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
-            if (st == MRH_OK) st = mrh_batch_integrate(b, frames);  // capture outside the timing
-            for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
-            if (st != MRH_OK) break;
-            (void)hipEventRecord(e0, b->stream);
-            for (int r = 0; r < reps && st == MRH_OK; ++r) st = mrh_batch_integrate(b, frames);
-            (void)hipEventRecord(e1, b->stream);
-            if (st != MRH_OK || hipEventSynchronize(e1) != hipSuccess) break;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                keep[0] = u, keep[1] = c, keep[2] = 1;
+            for (int32_t wv : kWaves) {
+                // the same total of waves per update launch for every workgroup size
+                const int32_t p[4] = {u * 4 / wv, c, 1, wv};
+                mrh_batch_set_launch(b, p);
+                for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
+                if (st == MRH_OK) st = mrh_batch_integrate(b, frames);  // capture outside the timing
+                for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
+                if (st != MRH_OK) break;
+                (void)hipEventRecord(e0, b->stream);
+                for (int r = 0; r < reps && st == MRH_OK; ++r) st = mrh_batch_integrate(b, frames);
+                (void)hipEventRecord(e1, b->stream);
+                if (st != MRH_OK || hipEventSynchronize(e1) != hipSuccess) break;
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    keep[0] = p[0], keep[1] = c, keep[2] = 1, keep[3] = wv;
+                }
             }
+            if (st != MRH_OK) break;
         }
         if (st != MRH_OK) break;
     }
@@ -429,7 +439,7 @@ mrh_status mrh_batch_autotune(mrh_batch* b, const mrh_frame* frames, int32_t rep
     if (st == MRH_OK) st = mrh_batch_set_launch(b, keep);
     for (int i = 0; i < b->n && st == MRH_OK; ++i) st = mrh_map_reset(b->maps[i]);
     if (st == MRH_OK) st = check_hip(b->maps[0], hipStreamSynchronize(b->stream), "autotune");
-    for (int k = 0; k < 3; ++k) best[k] = keep[k];
+    for (int k = 0; k < 4; ++k) best[k] = keep[k];
     return st;
 }
 

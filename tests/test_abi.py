@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mrh_abi_version() == 1
+    assert lib.mrh_abi_version() == 2
 
 
 def test_eq4_hash_vectors(lib):

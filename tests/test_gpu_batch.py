@@ -72,13 +72,16 @@ def _same(a, b):
     assert np.array_equal(a.S2, b.S2)
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_single_maps(mrh, graph):
-    announce(f"batch of 5 maps (3 RGB-D, 2 LiDAR), graph={graph}")
+@pytest.mark.parametrize("graph,waves", [(True, 4), (False, 4), (True, 1), (True, 2)])
+def test_batch_equals_single_maps(mrh, graph, waves):
+    """Every map of the batch equals the map fused alone, whatever the graph replay and the waves
+    per update workgroup."""
+    announce(f"batch of 5 maps (3 RGB-D, 2 LiDAR), graph={graph}, {waves} waves per update workgroup")
     cfgs, frames = _streams()
     maps = [mrh.Map(**c) for c in cfgs]
     b = mrh.Batch(maps)
-    b.set_launch(512, 16, graph)
+    b.set_launch(512 * 4 // waves, 16, graph, waves)
+    assert b.get_launch() == (512 * 4 // waves, 16, int(graph), waves)
     for fr in frames:
         b.integrate(fr)
     for i, c in enumerate(cfgs):
@@ -153,7 +156,8 @@ def test_batch_autotune_resets_maps(mrh):
     maps = [mrh.Map(**c) for c in cfgs]
     b = mrh.Batch(maps)
     best = b.autotune(frames[0], reps=2)
-    assert best[0] in (256, 512, 1024, 2048, 4096) and best[1] in (16, 64) and best[2] == 1
+    assert best[3] in (1, 2, 4) and best[0] * best[3] // 4 in (256, 512, 1024, 2048, 4096)
+    assert best[1] in (16, 64) and best[2] == 1
     assert b.get_launch() == best
     for m in maps:
         assert m.counts() == (0, 0)
