@@ -1,9 +1,9 @@
 // LiDAR fusion work units (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3 and Eq. 5; Sec. 3.2.1),
 // shared by the single-map kernels (points.hip) and the batched kernels (batch.hip).
 //
-//   points_alloc_chunk  16 rays: validity, segment [o, p + tau n] (carving) or the band
+//   points_alloc_chunk  32 rays: validity, segment [o, p + tau n] (carving) or the band
 //                       [p - tau n, p + tau n], walk over the block lattice, wave-deduplicated
-//                       insert, and the record of each ray's block keys in walk order
+//                       insert, and the record of the hash slots of each ray's blocks in walk order
 //   points_ray_chunk    8 rays: their recorded (ray, block) pairs in parallel; inside each block a
 //                       walk over the block's own voxel lattice; each crossed voxel gets
 //                       clip((p - x) . n, -tau, tau).
@@ -50,7 +50,7 @@ __device__ inline bool point_segment(const DevMap& m, const ScanParams& sp, int6
 
 // Rays per wave of the allocation launch (each ray's block walk is a serial chain of lookups, so
 // waves carry few rays and many waves are in flight), and per 256-thread workgroup.
-constexpr int kAllocRaysPerWave = 4;
+constexpr int kAllocRaysPerWave = 8;
 constexpr int kAllocRaysPerGroup = 4 * kAllocRaysPerWave;
 
 // Allocation for rays chunk * kAllocRaysPerGroup ..: the block walk of each ray, the wave-
