@@ -48,13 +48,18 @@ def cpu_model():
     return "unknown"
 
 
+# the sources k_integrate_depth is compiled from: its translation unit and the headers it includes
+KERNEL_SOURCES = ("include/mrhash.h", "paper_2511_21459_amd/csrc/mrh_internal.h",
+                  "paper_2511_21459_amd/csrc/mrh_store.h", "paper_2511_21459_amd/csrc/mrh_update.h",
+                  "paper_2511_21459_amd/csrc/mrh_depth.h", "paper_2511_21459_amd/csrc/depth.hip")
+
+
 def kernel_source_hash():
-    csrc = os.path.join(ROOT, "paper_2511_21459_amd", "csrc")
+    """SHA-256 over the sources of k_integrate_depth (name, NUL, contents, in that order)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

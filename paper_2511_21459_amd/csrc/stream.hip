@@ -16,11 +16,14 @@
 // the map's stream, where the free stacks are in their settled state (a frame's level-0 pops are
 // taken off by its own update launch; slots freed by its merges wait on the pending lists, which
 // are left alone).
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <new>
 #include <unordered_map>
-#include <unordered_set>
 #include <vector>
 
 #include "mrh_depth.h"
@@ -219,12 +222,76 @@ __global__ __launch_bounds__(256) void k_stream_in(const DevMap* __restrict__ pm
     }
 }
 
-// One stored block: its level, variance sums and planes in the storage format.
+// One stored block: its level, variance sums and the index of its planes in its level's slab.
 struct HostBlock {
     int level;
-    double vsum;
+    uint32_t at;    // index of its planes in its level's slab
+    uint32_t bpos;  // position of its key in its bucket's key list
     uint32_t vcnt;
-    std::vector<uint8_t> bytes;  // D plane, W plane, S2 plane (Morton order, storage format)
+    double vsum;
+};
+
+// The stored planes of one level (D plane, W plane, S2 plane of a block, Morton order, storage
+// format; a fixed size per level), in chunks of about 4 MiB with a free list, so that storing a
+// block costs a copy rather than an allocation and the store grows without moving what it holds.
+// Chunks are anonymous mappings populated when they are made (before the blocks leave the GPU),
+// so the copies into them take no page faults.
+struct Slab {
+    static constexpr size_t kChunkBytes = (size_t)4 << 20;
+    struct Chunk {
+        uint8_t* p = nullptr;
+        size_t len = 0;
+        Chunk(size_t n) : len(n) {
+            void* q = mmap(nullptr, n, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_POPULATE, -1, 0);
+            if (q == MAP_FAILED) throw std::bad_alloc();
+            p = static_cast<uint8_t*>(q);
+        }
+        ~Chunk() { munmap(p, len); }
+        Chunk(const Chunk&) = delete;
+        Chunk& operator=(const Chunk&) = delete;
+    };
+    std::vector<std::unique_ptr<Chunk>> chunks;
+    std::vector<uint32_t> free;
+    uint32_t fresh = 0;  // blocks handed out from the chunks so far, free or not
+    uint32_t per = 0;    // blocks per chunk
+    size_t bytes = 0;    // per block
+    void set_bytes(size_t b) {
+        if (b == bytes) return;
+        clear();
+        bytes = b;
+        per = (uint32_t)((kChunkBytes + b - 1) / b);
+    }
+    uint8_t* at(uint32_t i) const { return chunks[i / per]->p + (size_t)(i % per) * bytes; }
+    uint32_t put(const uint8_t* src) {
+        uint32_t i;
+        if (!free.empty()) {
+            i = free.back();
+            free.pop_back();
+        } else {
+            if (fresh == chunks.size() * (size_t)per) chunks.emplace_back(new Chunk((size_t)per * bytes));
+            i = fresh++;
+        }
+        std::memcpy(at(i), src, bytes);
+        return i;
+    }
+    // room for n more blocks without allocating in put(); false when the host is out of memory
+    bool reserve(uint32_t n) {
+        try {
+            while ((size_t)free.size() + chunks.size() * (size_t)per - fresh < n)
+                chunks.emplace_back(new Chunk((size_t)per * bytes));
+            free.reserve(free.size() + n);
+        } catch (const std::bad_alloc&) {
+            return false;
+        }
+        return true;
+    }
+    const uint8_t* get(uint32_t i) const { return at(i); }
+    void release(uint32_t i) { free.push_back(i); }
+    void clear() {
+        chunks.clear();
+        free.clear();
+        fresh = 0;
+    }
 };
 
 bool make_region(const mrh_map* map, const mrh_region* rg, Region& r) {
@@ -325,7 +392,8 @@ inline unsigned long long bucket_of(unsigned long long key) {
 
 struct mrh_stream_state {
     std::unordered_map<unsigned long long, HostBlock> store;
-    std::unordered_map<unsigned long long, std::unordered_set<unsigned long long>> buckets;  // bucket -> keys
+    Slab slabs[4];
+    std::unordered_map<unsigned long long, std::vector<unsigned long long>> buckets;  // bucket -> keys
     uint32_t* ids = nullptr;
     size_t ids_cap = 0;
     uint32_t* counts = nullptr;
@@ -339,6 +407,8 @@ struct mrh_stream_state {
     size_t vcnt_cap = 0;
     uint32_t* result = nullptr;
     size_t result_cap = 0;
+    uint8_t* stage = nullptr;  // pinned host staging of the payloads copied in and out
+    size_t stage_cap = 0;
 };
 
 namespace mrh {
@@ -353,6 +423,7 @@ void stream_free(mrh_map* map) {
     void* ptrs[] = {s->ids, s->counts, s->payload, s->keys, s->vsum, s->vcnt, s->result};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (s->stage) (void)hipHostFree(s->stage);
     delete s;
     map->stream_st = nullptr;
 }
@@ -361,6 +432,7 @@ void stream_clear(mrh_map* map) {
     if (map->stream_st) {
         map->stream_st->store.clear();
         map->stream_st->buckets.clear();
+        for (Slab& sl : map->stream_st->slabs) sl.clear();
     }
     map->gone = 0;
 }
@@ -372,6 +444,22 @@ static mrh_status read_counters(mrh_map* map, DevCounters& h) {
 }
 
 // Upload blocks (keys, levels, plane words, optional sums) and run the insert kernel per level.
+// The pinned staging buffer, grown to at least `bytes` (its contents are not kept).
+static mrh_status grow_stage(mrh_map* map, mrh_stream_state* S, size_t bytes) {
+    if (bytes <= S->stage_cap) return MRH_OK;
+    if (S->stage) {
+        mrh_status st = check_hip(map, hipHostFree(S->stage), "stream staging");
+        S->stage = nullptr;
+        S->stage_cap = 0;
+        if (st != MRH_OK) return st;
+    }
+    const size_t cap = bytes + bytes / 4;
+    mrh_status st = check_hip(map, hipHostMalloc((void**)&S->stage, cap, hipHostMallocDefault), "stream staging");
+    if (st == MRH_OK) S->stage_cap = cap;
+    else S->stage = nullptr;
+    return st;
+}
+
 static mrh_status stream_insert(mrh_map* map, const std::vector<unsigned long long>& keys, const std::vector<int>& levels,
                                 const std::vector<const uint8_t*>& words, const std::vector<double>& vsum,
                                 const std::vector<uint32_t>& vcnt, int sums, std::vector<uint32_t>& outcome) {
@@ -392,18 +480,18 @@ static mrh_status stream_insert(mrh_map* map, const std::vector<unsigned long lo
         if (st == MRH_OK) st = grow(map, &S->vsum, S->vsum_cap, cnt, "stream sums");
         if (st == MRH_OK) st = grow(map, &S->vcnt, S->vcnt_cap, cnt, "stream counts");
         if (st == MRH_OK) st = grow(map, &S->result, S->result_cap, cnt, "stream results");
+        if (st == MRH_OK) st = grow_stage(map, S, cnt * wpb);
         if (st != MRH_OK) return st;
-        std::vector<uint8_t> hw(cnt * wpb);
         std::vector<unsigned long long> hk(cnt);
         std::vector<double> hs(cnt, 0.0);
         std::vector<uint32_t> hc(cnt, 0u);
         for (size_t q = 0; q < cnt; ++q) {
             const size_t i = sel[q];
-            std::memcpy(&hw[q * wpb], words[i], wpb);
+            std::memcpy(S->stage + q * wpb, words[i], wpb);
             hk[q] = keys[i];
             if (sums) hs[q] = vsum[i], hc[q] = vcnt[i];
         }
-        st = check_hip(map, hipMemcpyAsync(S->payload, hw.data(), hw.size(), hipMemcpyHostToDevice, map->stream), "stream in");
+        st = check_hip(map, hipMemcpyAsync(S->payload, S->stage, cnt * wpb, hipMemcpyHostToDevice, map->stream), "stream in");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(S->keys, hk.data(), cnt * 8, hipMemcpyHostToDevice, map->stream), "stream in");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(S->vsum, hs.data(), cnt * 8, hipMemcpyHostToDevice, map->stream), "stream in");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(S->vcnt, hc.data(), cnt * 4, hipMemcpyHostToDevice, map->stream), "stream in");
@@ -465,6 +553,11 @@ mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double thresho
     if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(cnt, S->counts, 16, hipMemcpyDeviceToHost, map->stream), "stream");
     if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "stream");
     if (st != MRH_OK) return st;
+    try {
+        S->store.reserve(S->store.size() + (size_t)cnt[0] + cnt[1] + cnt[2] + cnt[3]);
+    } catch (const std::bad_alloc&) {
+        return set_error(map, MRH_ERR_OOM, "host store: out of memory");
+    }
     const int pb = plane_bytes(map->cfg.storage);
     for (int lv = 0; lv < map->cfg.levels; ++lv) {
         const uint32_t n = cnt[lv];
@@ -474,27 +567,38 @@ mrh_status mrh_stream_out(mrh_map* map, const mrh_region* region, double thresho
         if (st == MRH_OK) st = grow(map, &S->keys, S->keys_cap, n, "stream keys");
         if (st == MRH_OK) st = grow(map, &S->vsum, S->vsum_cap, n, "stream sums");
         if (st == MRH_OK) st = grow(map, &S->vcnt, S->vcnt_cap, n, "stream counts");
+        if (st == MRH_OK) st = grow_stage(map, S, (size_t)n * wpb);
         if (st != MRH_OK) return st;
+        // host room first: the launch below takes the blocks off the GPU
+        Slab& sl = S->slabs[lv];
+        sl.set_bytes(wpb);
+        if (!sl.reserve(n)) return set_error(map, MRH_ERR_OOM, "host store: out of memory for %u blocks", n);
         hipLaunchKernelGGL(k_stream_out, dim3((n + 3) / 4), dim3(256), 0, map->stream, map->dmd, lv,
                            S->ids + (size_t)lv * nb, n, S->payload, S->keys, S->vsum, S->vcnt);
-        std::vector<uint8_t> hw((size_t)n * wpb);
         std::vector<unsigned long long> hk(n);
         std::vector<double> hs(n);
         std::vector<uint32_t> hc(n);
         st = check_hip(map, hipGetLastError(), "stream out");
-        if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(hw.data(), S->payload, hw.size(), hipMemcpyDeviceToHost, map->stream), "stream out");
+        if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(S->stage, S->payload, (size_t)n * wpb, hipMemcpyDeviceToHost, map->stream), "stream out");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(hk.data(), S->keys, (size_t)n * 8, hipMemcpyDeviceToHost, map->stream), "stream out");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(hs.data(), S->vsum, (size_t)n * 8, hipMemcpyDeviceToHost, map->stream), "stream out");
         if (st == MRH_OK) st = check_hip(map, hipMemcpyAsync(hc.data(), S->vcnt, (size_t)n * 4, hipMemcpyDeviceToHost, map->stream), "stream out");
         if (st == MRH_OK) st = check_hip(map, hipStreamSynchronize(map->stream), "stream out");
         if (st != MRH_OK) return st;
         for (uint32_t q = 0; q < n; ++q) {
-            HostBlock& hb = S->store[hk[q]];
-            S->buckets[bucket_of(hk[q])].insert(hk[q]);
+            auto ins = S->store.try_emplace(hk[q]);
+            HostBlock& hb = ins.first->second;
+            if (!ins.second) {
+                S->slabs[hb.level].release(hb.at);  // a stored copy the GPU block replaces
+            } else {
+                std::vector<unsigned long long>& bv = S->buckets[bucket_of(hk[q])];
+                hb.bpos = (uint32_t)bv.size();
+                bv.push_back(hk[q]);
+            }
             hb.level = lv;
+            hb.at = sl.put(S->stage + (size_t)q * wpb);
             hb.vsum = hs[q];
             hb.vcnt = hc[q];
-            hb.bytes.assign(hw.begin() + (size_t)q * wpb, hw.begin() + (size_t)(q + 1) * wpb);
         }
         map->gone += n;
         *n_out += n;
@@ -528,7 +632,7 @@ mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in) 
             const HostBlock& hb = S->store.at(key);
             keys.push_back(key);
             levels.push_back(hb.level);
-            words.push_back(hb.bytes.data());
+            words.push_back(S->slabs[hb.level].get(hb.at));
             vsum.push_back(hb.vsum);
             vcnt.push_back(hb.vcnt);
         }
@@ -552,10 +656,20 @@ mrh_status mrh_stream_in(mrh_map* map, const mrh_region* region, int64_t* n_in) 
     for (size_t i = 0; i < keys.size(); ++i) {
         // restored blocks leave the store; a key present on the GPU keeps its stored copy
         if (outcome[i] == 1) {
-            S->store.erase(keys[i]);
+            auto it = S->store.find(keys[i]);
+            const HostBlock hb = it->second;
+            S->store.erase(it);
+            S->slabs[hb.level].release(hb.at);
+            // take the key out of its bucket: the bucket's last key moves into its place
             auto b = S->buckets.find(bucket_of(keys[i]));
-            b->second.erase(keys[i]);
-            if (b->second.empty()) S->buckets.erase(b);
+            std::vector<unsigned long long>& bv = b->second;
+            const unsigned long long last = bv.back();
+            bv.pop_back();
+            if (last != keys[i]) {
+                bv[hb.bpos] = last;
+                S->store.find(last)->second.bpos = hb.bpos;
+            }
+            if (bv.empty()) S->buckets.erase(b);
             ++*n_in;
         }
     }
@@ -594,7 +708,7 @@ mrh_status mrh_store_extract(mrh_map* map, int32_t* keys, uint8_t* levels, int64
             const int64_t o = off + a + ms * (b + ms * c);
             float d, s2;
             uint32_t w;
-            host_decode(st, hb.bytes.data(), nvb, p, tau_f, tau2_f, d, w, s2);
+            host_decode(st, map->stream_st->slabs[hb.level].get(hb.at), nvb, p, tau_f, tau2_f, d, w, s2);
             if (D) D[o] = d;
             if (W) W[o] = w;
             if (S2) S2[o] = s2;
@@ -663,7 +777,7 @@ mrh_status mrh_store_info(mrh_map* map, int64_t* n_blocks, int64_t* n_voxels, in
         for (const auto& kv : map->stream_st->store) {
             ++nb;
             nv += (int64_t)side_of(kv.second.level) * side_of(kv.second.level) * side_of(kv.second.level);
-            by += (int64_t)kv.second.bytes.size() + 24;
+            by += (int64_t)map->stream_st->slabs[kv.second.level].bytes + 24;
         }
     if (n_blocks) *n_blocks = nb;
     if (n_voxels) *n_voxels = nv;
