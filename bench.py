@@ -527,22 +527,63 @@ def run_street_streaming(np, mrh, cfg, dev, poses, blocks_plain):
             "consistent": chk["consistent"], "errors": tot["error_flags"]}
 
 
+def morton_order(np, p, cell):
+    """Permutation that orders points by the Morton code of their cell of side `cell` (21 bits per
+    axis): points close in space become close in the order."""
+    c = np.floor((p - p.min(axis=0)) / cell).astype(np.uint64)
+    c = np.minimum(c, np.uint64((1 << 21) - 1))
+
+    def spread(v):  # insert two zero bits between consecutive bits of a 21-bit value
+        v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+        v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+        return v
+
+    code = spread(c[:, 0]) | (spread(c[:, 1]) << np.uint64(1)) | (spread(c[:, 2]) << np.uint64(2))
+    return np.argsort(code, kind="stable")
+
+
+# bytes a query reads and writes per point: the point (12 B), the result (4 B SDF + 1 B valid), 8
+# table probes of 8 B and 8 corners' D and W (8 B each)
+QUERY_BYTES_PER_POINT = 97
+
+
 def run_query(room, torch, np, mrh):
+    """1M points near the room's surfaces (1.5 cm normal noise) queried forward and with the adjoint,
+    in random order and, the same points, in Morton order of their 1 cm cell (a spatially coherent
+    batch, such as points along rays or on a grid); the results are the same point for point."""
     from workloads import surface_query_points
 
     fmap = room["fmap"]
-    pts = torch.from_numpy(surface_query_points(room["scene"], 1_000_000, sigma=0.015, seed=100)).cuda()
-    gs = torch.ones(pts.shape[0], device="cuda")
+    host = surface_query_points(room["scene"], 1_000_000, sigma=0.015, seed=100)
+    perm = morton_order(np, host.astype(np.float64), 0.01)
     T = np.eye(4)
     T[:3, 3] = [0.01, -0.01, 0.005]
-    fmap.query(pts, T=T)
-    t_f = timed(lambda: fmap.query(pts, T=T), 5, torch)
-    fmap.query_backward(pts, gs, T=T)
-    t_b = timed(lambda: fmap.query_backward(pts, gs, T=T), 5, torch)
-    _, valid, _ = fmap.query(pts, T=T)
-    return {"points": int(pts.shape[0]), "valid_frac": round(float(valid.float().mean()), 4),
-            "forward_m_queries_per_s": round(pts.shape[0] / t_f / 1e6, 1),
-            "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1)}
+    out = {"points": int(host.shape[0])}
+    res = {}
+    for name, arr in (("random", host), ("morton", np.ascontiguousarray(host[perm]))):
+        pts = torch.from_numpy(arr).cuda()
+        gs = torch.ones(pts.shape[0], device="cuda")
+        fmap.query(pts, T=T)
+        t_f = timed(lambda: fmap.query(pts, T=T), 5, torch)
+        fmap.query_backward(pts, gs, T=T)
+        t_b = timed(lambda: fmap.query_backward(pts, gs, T=T), 5, torch)
+        sdf, valid, _ = fmap.query(pts, T=T)
+        res[name] = (sdf.cpu().numpy(), valid.cpu().numpy())
+        rec = {"forward_m_queries_per_s": round(pts.shape[0] / t_f / 1e6, 1),
+               "backward_m_queries_per_s": round(pts.shape[0] / t_b / 1e6, 1),
+               "forward_gb_per_s": round(QUERY_BYTES_PER_POINT * pts.shape[0] / t_f / 1e9, 1)}
+        if name == "random":
+            out["valid_frac"] = round(float(valid.float().mean()), 4)
+            out.update(rec)
+        else:
+            out["morton_order"] = rec
+    same = (np.array_equal(res["random"][1][perm], res["morton"][1])
+            and np.array_equal(res["random"][0][perm], res["morton"][0]))
+    out["morton_order"]["same_results"] = bool(same)
+    return out
 
 
 def run_color(room, torch, np, mrh, configs):
@@ -738,7 +779,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain-copy calibration kernel")
-    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh", "color", "rotated"],
+    ap.add_argument("--only", choices=["street", "batched", "sweep", "mesh", "color", "rotated", "query"],
                     help="run one secondary workload alone and print its record (for kernel profiles)")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -763,13 +804,14 @@ def main():
     if args.only == "batched":
         print(json.dumps({"batched": run_batched(args, torch, np, mrh, configs)}), flush=True)
         return
-    if args.only == "mesh":
+    if args.only in ("mesh", "query"):
         depths, cam, poses, scene = room_sequence(n_frames=100, frames=range(args.frames))
         fm = mrh.Map(**configs.ROOM)
         fm.integrate_depth_sequence(torch.from_numpy(depths).cuda(), cam.K, np.ascontiguousarray(poses))
         fm.sync()
         room = dict(depths=depths, cam=cam, poses=poses, scene=scene, fmap=fm)
-        print(json.dumps({"mesh": run_mesh(room, torch, np, mrh, configs)}), flush=True)
+        rec = run_mesh(room, torch, np, mrh, configs) if args.only == "mesh" else run_query(room, torch, np, mrh)
+        print(json.dumps({args.only: rec}), flush=True)
         return
     if args.only == "rotated":
         room = run_room(args, torch, np, mrh, configs, room_sequence)
