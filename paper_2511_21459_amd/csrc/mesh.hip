@@ -181,8 +181,35 @@ template <int ST>
 __device__ __forceinline__ bool voxel_value(const DevMap& m, uint32_t info, int i, int j, int k, float& v) {
     const int n = (int)((info >> kLevelShift) & 3u);
     const size_t at = ((size_t)(info & kSlotMask) << (3 * (3 - n))) + (size_t)morton_of(i, j, k);
-    if (Store<ST>::getW(m, n, at) == 0u) return false;
-    v = Store<ST>::getD(m, n, at);
+    // both reads issued together (the TSDF read does not wait for the weight)
+    const uint32_t w = Store<ST>::getW(m, n, at);
+    const float d = Store<ST>::getD(m, n, at);
+    if (w == 0u) return false;
+    v = d;
+    return true;
+}
+
+// Where lattice_value reads a single voxel (position P on a voxel centre of its block): that
+// voxel's level and heap position, and true; false when P is outside the neighbourhood, in no
+// block, or between voxel centres.
+__device__ __forceinline__ bool lattice_voxel(const uint32_t* nbw, int P0, int P1, int P2, size_t& at, int& level) {
+    const int hh[3] = {P0 >> 4, P1 >> 4, P2 >> 4};
+    if (hh[0] < -1 || hh[0] > 1 || hh[1] < -1 || hh[1] > 1 || hh[2] < -1 || hh[2] > 1) return false;
+    const uint32_t hinfo = nbw[nb_index(hh[0], hh[1], hh[2])];
+    if (hinfo & kNoBlockBit) return false;
+    const int n = (int)((hinfo >> kLevelShift) & 3u);
+    const int sh = n + 1, half = 1 << n;
+    const int P[3] = {P0, P1, P2};
+    int i0[3], r = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int q = P[a] - 16 * hh[a] - half;
+        i0[a] = q >> sh;
+        r |= q - (i0[a] << sh);
+    }
+    if (r != 0) return false;
+    at = ((size_t)(hinfo & kSlotMask) << (3 * (3 - n))) + (size_t)morton_of(i0[0], i0[1], i0[2]);
+    level = n;
     return true;
 }
 
@@ -209,13 +236,18 @@ __device__ __forceinline__ bool lattice_value(const DevMap& m, const uint32_t* n
     }
     if ((r[0] | r[1] | r[2]) == 0) return voxel_value<ST>(m, hinfo, i0[0], i0[1], i0[2], out);
     const float f[3] = {(float)r[0] * inv_s, (float)r[1] * inv_s, (float)r[2] * inv_s};
-    float wsum = 0.f, num = 0.f;
-    bool any = false;
+    // the corners' heap positions first, then all their reads at once, then the weighted sum
+    size_t at[8];
+    int lvl[8];
+    float wt[8];
+    uint32_t live = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int dd[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        const float w = (dd[0] ? f[0] : 1.f - f[0]) * (dd[1] ? f[1] : 1.f - f[1]) * (dd[2] ? f[2] : 1.f - f[2]);
-        if (!(w > 0.f)) continue;
+        wt[c] = (dd[0] ? f[0] : 1.f - f[0]) * (dd[1] ? f[1] : 1.f - f[1]) * (dd[2] ? f[2] : 1.f - f[2]);
+        at[c] = 0;
+        lvl[c] = 0;
+        if (!(wt[c] > 0.f)) continue;
         int p2[3], ob[3];
         bool inside = true;
 #pragma unroll
@@ -227,13 +259,30 @@ __device__ __forceinline__ bool lattice_value(const DevMap& m, const uint32_t* n
         if (!inside) continue;
         const uint32_t info = nbw[nb_index(ob[0], ob[1], ob[2])];
         if (info & kNoBlockBit) continue;
-        const int s2 = (int)((info >> kLevelShift) & 3u) + 1;
-        float v;
-        if (!voxel_value<ST>(m, info, (p2[0] - 16 * ob[0]) >> s2, (p2[1] - 16 * ob[1]) >> s2,
-                             (p2[2] - 16 * ob[2]) >> s2, v))
-            continue;
-        wsum += w;
-        num += w * v;
+        const int n2 = (int)((info >> kLevelShift) & 3u), s2 = n2 + 1;
+        at[c] = ((size_t)(info & kSlotMask) << (3 * (3 - n2))) +
+                (size_t)morton_of((p2[0] - 16 * ob[0]) >> s2, (p2[1] - 16 * ob[1]) >> s2, (p2[2] - 16 * ob[2]) >> s2);
+        lvl[c] = n2;
+        live |= 1u << c;
+    }
+    uint32_t W[8];
+    float D[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        W[c] = 0u;
+        D[c] = 0.f;
+        if (live & (1u << c)) {
+            W[c] = Store<ST>::getW(m, lvl[c], at[c]);
+            D[c] = Store<ST>::getD(m, lvl[c], at[c]);
+        }
+    }
+    float wsum = 0.f, num = 0.f;
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!(live & (1u << c)) || W[c] == 0u) continue;  // zero-weight corners drop out
+        wsum += wt[c];
+        num += wt[c] * D[c];
         any = true;
     }
     if (!any) return false;
@@ -470,23 +519,93 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict_
         const int ma = ms + 1, na = ma * ma * ma, half = 1 << n;
         const float inv_ma = 1.0f / (float)ma;
         const size_t own = (size_t)(info & kSlotMask) * (size_t)nvox;
-        for (int v = lane; v < na; v += 64) {
-            // v = i + ma (j + ma k): quotients by ma through the reciprocal (v < 729, so the
-            // half-step offset keeps every quotient exact)
-            const int q1 = (int)(((float)v + 0.5f) * inv_ma), k = (int)(((float)q1 + 0.5f) * inv_ma);
-            const int i = v - ma * q1, j = q1 - ma * k;
-            float val = __builtin_nanf("");
-            if (i < ms && j < ms && k < ms) {
-                const size_t at = own + (size_t)morton_of(i, j, k);
-                if (Store<ST>::getW(m, n, at) != 0u) val = Store<ST>::getD(m, n, at);
-            } else if ((i < ms || nbl[0] >= 0) && (j < ms || nbl[1] >= 0) && (k < ms || nbl[2] >= 0)) {
-                const int P0 = i < ms ? (2 * i + 1) * half : 16 + (1 << nbl[0]);
-                const int P1 = j < ms ? (2 * j + 1) * half : 16 + (1 << nbl[1]);
-                const int P2 = k < ms ? (2 * k + 1) * half : 16 + (1 << nbl[2]);
-                float w;
-                if (lattice_value<ST>(m, nbw, P0, P1, P2, w)) val = w;
+        // the block's own voxels, read in heap (Morton) order, coalesced: every weight and TSDF
+        // read is issued before any is used
+        float dq[8];
+        uint32_t wq[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int p = lane + 64 * t;
+            dq[t] = 0.f;
+            wq[t] = 0u;
+            if (p < nvox) {
+                wq[t] = Store<ST>::getW(m, n, own + (size_t)p);
+                dq[t] = Store<ST>::getD(m, n, own + (size_t)p);
             }
-            sD[v] = val;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int p = lane + 64 * t;
+            if (p < nvox) {
+                int i, j, k;
+                demorton3(p, i, j, k);
+                sD[i + ma * (j + ma * k)] = wq[t] != 0u ? dq[t] : __builtin_nanf("");
+            }
+        }
+        // the upper-face lattice points (na - nvox <= 217 of them, at most 4 per lane): the faces
+        // i = m (ma^2 points), then j = m with i < m (m ma), then k = m with i, j < m (m^2).  A point
+        // on a voxel centre of its block is read directly, all such reads of a lane issued
+        // together; a point between voxel centres (a coarser neighbour) is interpolated.
+        const int nface = na - nvox;
+        int pv[4];
+        size_t pat[4];
+        int plv[4], pk[4];
+        int pP[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int bq = lane + 64 * u;
+            pk[u] = 0;  // 0 no point, 1 invalid, 2 voxel read, 3 interpolated
+            pv[u] = 0;
+            pat[u] = 0;
+            plv[u] = 0;
+            pP[u][0] = pP[u][1] = pP[u][2] = 0;
+            if (bq >= nface) continue;
+            int i, j, k;
+            if (bq < ma * ma) {
+                i = ms;
+                k = (int)(((float)bq + 0.5f) * inv_ma);
+                j = bq - ma * k;
+            } else if ((bq -= ma * ma) < ms * ma) {
+                j = ms;
+                k = bq >> (3 - n);
+                i = bq & (ms - 1);
+            } else {
+                bq -= ms * ma;
+                k = ms;
+                j = bq >> (3 - n);
+                i = bq & (ms - 1);
+            }
+            pv[u] = i + ma * (j + ma * k);
+            pk[u] = 1;
+            if (!((i < ms || nbl[0] >= 0) && (j < ms || nbl[1] >= 0) && (k < ms || nbl[2] >= 0))) continue;
+            pP[u][0] = i < ms ? (2 * i + 1) * half : 16 + (1 << nbl[0]);
+            pP[u][1] = j < ms ? (2 * j + 1) * half : 16 + (1 << nbl[1]);
+            pP[u][2] = k < ms ? (2 * k + 1) * half : 16 + (1 << nbl[2]);
+            pk[u] = 3;
+            if (lattice_voxel(nbw, pP[u][0], pP[u][1], pP[u][2], pat[u], plv[u])) pk[u] = 2;
+        }
+        uint32_t pw[4];
+        float pd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pw[u] = 0u;
+            pd[u] = 0.f;
+            if (pk[u] == 2) {
+                pw[u] = Store<ST>::getW(m, plv[u], pat[u]);
+                pd[u] = Store<ST>::getD(m, plv[u], pat[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (pk[u] == 0) continue;
+            float val = __builtin_nanf("");
+            if (pk[u] == 2) {
+                if (pw[u] != 0u) val = pd[u];
+            } else if (pk[u] == 3) {
+                float w;
+                if (lattice_value<ST>(m, nbw, pP[u][0], pP[u][1], pP[u][2], w)) val = w;
+            }
+            sD[pv[u]] = val;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
