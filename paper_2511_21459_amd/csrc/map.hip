@@ -133,7 +133,7 @@ static void free_all(mrh_map* m) {
     stream_free(m);
     DevMap& d = m->dm;
     void* ptrs[] = {d.hkeys, d.hvals, d.bkey, d.binfo, d.bvsum, d.bvcnt, m->ctr, m->partials, m->pose_out, m->dmd,
-                    m->count_dev};
+                    m->count_dev, m->mesh_order};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (d.btouch) (void)hipFree(d.btouch);

@@ -464,8 +464,33 @@ __device__ inline unsigned long long wave_excl_scan(unsigned long long v, unsign
     return x - v;
 }
 
+// The blocks to mesh, grouped by level so that the waves of a workgroup (which meet at barriers)
+// do work of one size: block ids of level l are appended to order[l * stride ...], counts[l] holding
+// their number (counts start at zero).  Blocks without voxels (no heap slot, streamed out) are left
+// out.  One atomic per level present per wave.
+__global__ __launch_bounds__(256) void k_mesh_order(const DevMap* __restrict__ pm, uint32_t n_blocks, uint32_t stride,
+                                                    uint32_t* __restrict__ order, uint32_t* __restrict__ counts) {
+    const DevMap& m = *pm;
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    int level = -1;
+    if (id < n_blocks) {
+        const uint32_t info = m.binfo[id];
+        if (!(info & kNoBlockBit)) level = (int)((info >> kLevelShift) & 3u);
+    }
+    for (int l = 0; l < 4; ++l) {
+        const unsigned long long mask = __ballot(level == l);
+        if (!mask) continue;
+        const int first = __ffsll((long long)mask) - 1;
+        uint32_t at = 0;
+        if (lane_id() == first) at = atomicAdd(&counts[l], (uint32_t)__popcll(mask));
+        at = (uint32_t)__shfl((int)at, first) + (uint32_t)rank_in_mask(mask);
+        if (level == l) order[(size_t)l * stride + at] = id;
+    }
+}
+
 template <int ST>
-__global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict__ pm, uint32_t n_blocks, float collapse,
+__global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict__ pm, const uint32_t* __restrict__ order,
+                                              const uint32_t* __restrict__ counts, uint32_t stride, float collapse,
                                               MeshOut o) {
     const DevMap& m = *pm;
     __shared__ MeshLds L;
@@ -478,10 +503,24 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict_
         uint32_t* dst = reinterpret_cast<uint32_t*>(&L.tab);
         for (int w = threadIdx.x; w < (int)(sizeof(McPacked) / 4); w += kMeshThreads) dst[w] = src[w];
     }
-    const uint32_t id = blockIdx.x * kMeshWaves + (uint32_t)wv;
+    // this wave's block: workgroups take the levels' lists in turn, kMeshWaves blocks each
+    uint32_t id = kInvalidId;
+    {
+        const uint32_t w = blockIdx.x;
+        uint32_t first = 0;
+        for (int l = 0; l < 4; ++l) {
+            const uint32_t c = counts[l], g = (c + kMeshWaves - 1) / kMeshWaves;
+            if (w < first + g) {
+                const uint32_t k = (w - first) * kMeshWaves + (uint32_t)wv;
+                if (k < c) id = order[(size_t)l * stride + k];
+                break;
+            }
+            first += g;
+        }
+    }
     uint32_t info = kNoBlockBit;
     unsigned long long key = 0;
-    if (id < n_blocks) {
+    if (id != kInvalidId) {
         info = m.binfo[id];
         key = m.bkey[id];
     }
@@ -621,7 +660,10 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict_
             L.rows[wv][r] = bits;
         }
     }
-    __syncthreads();
+    // the rows are this wave's own: a wave barrier (not a workgroup one) lets each wave go on
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const float snap_units = collapse * (float)(2 << n);  // collapse * nu_n in half units
     const int lg = 3 - n;                                 // log2 of the block side
     // pass 1: the surface cubes (all 8 corners valid, both signs), one row of cubes along x per
@@ -723,13 +765,30 @@ extern "C" mrh_status mrh_extract_mesh(mrh_map* map, double collapse, float* ver
     o.count = map->count_dev;
     o.h = 0.5 * map->cfg.voxel;
     if (nb) {
-        const unsigned grid = (nb + kMeshWaves - 1) / kMeshWaves;
+        // block ids by level: 4 regions of nb entries, then the 4 counts
+        const size_t need = (size_t)4 * nb + 4;
+        if (need > map->mesh_order_cap) {
+            if (map->mesh_order) (void)hipFree(map->mesh_order);
+            map->mesh_order = nullptr;
+            map->mesh_order_cap = 0;
+            st = check_hip(map, hipMalloc((void**)&map->mesh_order, need * sizeof(uint32_t)), "mesh order");
+            if (st != MRH_OK) return st;
+            map->mesh_order_cap = need;
+        }
+        uint32_t* order = map->mesh_order;
+        uint32_t* counts = order + (size_t)4 * nb;
+        st = check_hip(map, hipMemsetAsync(counts, 0, 16, map->stream), "mesh");
+        if (st != MRH_OK) return st;
+        // enough workgroups for every level's list rounded up to whole workgroups
+        const unsigned grid = (nb + kMeshWaves - 1) / kMeshWaves + 3;
         const float cf = (float)collapse;
         launch(map, K_MESH, [&] {
+            hipLaunchKernelGGL(k_mesh_order, dim3((nb + 255) / 256), dim3(256), 0, map->stream, map->dmd, nb, nb, order,
+                               counts);
             switch (map->cfg.storage) {
-                case MRH_STORE_F16: hipLaunchKernelGGL(k_mesh<MRH_STORE_F16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o); break;
-                case MRH_STORE_BF16: hipLaunchKernelGGL(k_mesh<MRH_STORE_BF16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o); break;
-                default: hipLaunchKernelGGL(k_mesh<MRH_STORE_F32>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, nb, cf, o);
+                case MRH_STORE_F16: hipLaunchKernelGGL(k_mesh<MRH_STORE_F16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, order, counts, nb, cf, o); break;
+                case MRH_STORE_BF16: hipLaunchKernelGGL(k_mesh<MRH_STORE_BF16>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, order, counts, nb, cf, o); break;
+                default: hipLaunchKernelGGL(k_mesh<MRH_STORE_F32>, dim3(grid), dim3(kMeshThreads), 0, map->stream, map->dmd, order, counts, nb, cf, o);
             }
         });
         st = check_hip(map, hipGetLastError(), "mesh");

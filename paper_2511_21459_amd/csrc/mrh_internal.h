@@ -478,6 +478,8 @@ struct mrh_map {
     double* partials = nullptr;  // query-backward per-workgroup FP64 partial sums
     double* pose_out = nullptr;  // 6 doubles, final reduction
     unsigned long long* count_dev = nullptr;  // one device counter for the extraction calls
+    uint32_t* mesh_order = nullptr;  // the mesh launch's block ids by level (4 regions) and 4 counts
+    size_t mesh_order_cap = 0;
     int32_t partials_cap = 0;
     bool lidar_ready = false;    // accumulators allocated
     int64_t rcap_n = 0;          // rays the per-ray block-key buffers hold
