@@ -465,27 +465,38 @@ __device__ inline unsigned long long wave_excl_scan(unsigned long long v, unsign
 }
 
 // The blocks to mesh, grouped by level so that the waves of a workgroup (which meet at barriers)
-// do work of one size: block ids of level l are appended to order[l * stride ...], counts[l] holding
-// their number (counts start at zero).  Blocks without voxels (no heap slot, streamed out) are left
-// out.  One atomic per level present per wave.
+// do work of one size: block ids of level l are appended to order[l * stride ...], counts[32 l]
+// holding their number (counts start at zero; one 128-byte line per level, so that the levels'
+// atomics do not queue behind each other).  Blocks without voxels (no heap slot, streamed out) are
+// left out.  Positions are taken in LDS per workgroup, then one atomic per level per workgroup.
+constexpr int kOrderLine = 32;  // counter stride in uint32 (128 bytes)
+
 __global__ __launch_bounds__(256) void k_mesh_order(const DevMap* __restrict__ pm, uint32_t n_blocks, uint32_t stride,
                                                     uint32_t* __restrict__ order, uint32_t* __restrict__ counts) {
     const DevMap& m = *pm;
+    __shared__ uint32_t lcnt[4], lbase[4];
+    if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
+    __syncthreads();
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
     int level = -1;
     if (id < n_blocks) {
         const uint32_t info = m.binfo[id];
         if (!(info & kNoBlockBit)) level = (int)((info >> kLevelShift) & 3u);
     }
+    uint32_t local = 0;
     for (int l = 0; l < 4; ++l) {
         const unsigned long long mask = __ballot(level == l);
         if (!mask) continue;
         const int first = __ffsll((long long)mask) - 1;
         uint32_t at = 0;
-        if (lane_id() == first) at = atomicAdd(&counts[l], (uint32_t)__popcll(mask));
+        if (lane_id() == first) at = atomicAdd(&lcnt[l], (uint32_t)__popcll(mask));
         at = (uint32_t)__shfl((int)at, first) + (uint32_t)rank_in_mask(mask);
-        if (level == l) order[(size_t)l * stride + at] = id;
+        if (level == l) local = at;
     }
+    __syncthreads();
+    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&counts[kOrderLine * threadIdx.x], lcnt[threadIdx.x]);
+    __syncthreads();
+    if (level >= 0) order[(size_t)level * stride + lbase[level] + local] = id;
 }
 
 template <int ST>
@@ -509,7 +520,7 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(const DevMap* __restrict_
         const uint32_t w = blockIdx.x;
         uint32_t first = 0;
         for (int l = 0; l < 4; ++l) {
-            const uint32_t c = counts[l], g = (c + kMeshWaves - 1) / kMeshWaves;
+            const uint32_t c = counts[kOrderLine * l], g = (c + kMeshWaves - 1) / kMeshWaves;
             if (w < first + g) {
                 const uint32_t k = (w - first) * kMeshWaves + (uint32_t)wv;
                 if (k < c) id = order[(size_t)l * stride + k];
@@ -765,8 +776,8 @@ extern "C" mrh_status mrh_extract_mesh(mrh_map* map, double collapse, float* ver
     o.count = map->count_dev;
     o.h = 0.5 * map->cfg.voxel;
     if (nb) {
-        // block ids by level: 4 regions of nb entries, then the 4 counts
-        const size_t need = (size_t)4 * nb + 4;
+        // block ids by level: 4 regions of nb entries, then the 4 counts, one 128-byte line each
+        const size_t need = (size_t)4 * nb + 4 * kOrderLine;
         if (need > map->mesh_order_cap) {
             if (map->mesh_order) (void)hipFree(map->mesh_order);
             map->mesh_order = nullptr;
@@ -777,7 +788,7 @@ extern "C" mrh_status mrh_extract_mesh(mrh_map* map, double collapse, float* ver
         }
         uint32_t* order = map->mesh_order;
         uint32_t* counts = order + (size_t)4 * nb;
-        st = check_hip(map, hipMemsetAsync(counts, 0, 16, map->stream), "mesh");
+        st = check_hip(map, hipMemsetAsync(counts, 0, 4 * kOrderLine * sizeof(uint32_t), map->stream), "mesh");
         if (st != MRH_OK) return st;
         // enough workgroups for every level's list rounded up to whole workgroups
         const unsigned grid = (nb + kMeshWaves - 1) / kMeshWaves + 3;
