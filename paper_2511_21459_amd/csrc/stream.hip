@@ -241,7 +241,7 @@ struct Slab {
     struct Chunk {
         uint8_t* p = nullptr;
         size_t len = 0;
-        Chunk(size_t n) : len(n) {
+        explicit Chunk(size_t n) : len(n) {
             void* q = mmap(nullptr, n, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_POPULATE, -1, 0);
             if (q == MAP_FAILED) throw std::bad_alloc();
             p = static_cast<uint8_t*>(q);
@@ -268,7 +268,7 @@ struct Slab {
             i = free.back();
             free.pop_back();
         } else {
-            if (fresh == chunks.size() * (size_t)per) chunks.emplace_back(new Chunk((size_t)per * bytes));
+            if (fresh == chunks.size() * (size_t)per) chunks.push_back(std::make_unique<Chunk>((size_t)per * bytes));
             i = fresh++;
         }
         std::memcpy(at(i), src, bytes);
@@ -278,7 +278,7 @@ struct Slab {
     bool reserve(uint32_t n) {
         try {
             while ((size_t)free.size() + chunks.size() * (size_t)per - fresh < n)
-                chunks.emplace_back(new Chunk((size_t)per * bytes));
+                chunks.push_back(std::make_unique<Chunk>((size_t)per * bytes));
             free.reserve(free.size() + n);
         } catch (const std::bad_alloc&) {
             return false;
