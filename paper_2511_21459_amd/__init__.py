@@ -373,17 +373,16 @@ class Quadtree:
         p = _dev(rgb, torch.uint8, name="rgb")
         L = _lib.load()
         n = ctypes.c_int64()
-        args = (self._h, p, rgb.shape[1], rgb.shape[0], float(threshold), int(min_size))
-        st = L.mrh_quadtree_build(*args, None, None, 0, ctypes.byref(n))
-        if st != 0:
-            raise MrhError(st, "mrh_quadtree_build")
-        leaves = torch.empty((n.value, 4), dtype=torch.int32, device=rgb.device)
-        con = torch.empty(n.value, dtype=torch.float32, device=rgb.device)
-        st = L.mrh_quadtree_build(*args, ctypes.c_void_p(leaves.data_ptr()), ctypes.c_void_p(con.data_ptr()), n.value,
+        # one build into buffers sized for the worst case (every leaf holds at least one pixel)
+        cap = int(rgb.shape[0]) * int(rgb.shape[1])
+        leaves = torch.empty((cap, 4), dtype=torch.int32, device=rgb.device)
+        con = torch.empty(cap, dtype=torch.float32, device=rgb.device)
+        st = L.mrh_quadtree_build(self._h, p, rgb.shape[1], rgb.shape[0], float(threshold), int(min_size),
+                                  ctypes.c_void_p(leaves.data_ptr()), ctypes.c_void_p(con.data_ptr()), cap,
                                   ctypes.byref(n))
         if st != 0:
             raise MrhError(st, "mrh_quadtree_build")
-        return leaves, con
+        return leaves[: n.value].clone(), con[: n.value].clone()
 
 
 def convert(values, storage: str, decode: bool = False):

@@ -32,9 +32,17 @@ struct QtNode {
 
 // Row pass: inclusive prefix sums along x of each channel and of its square, written at (y + 1,
 // x + 1) of (H + 1) x (W + 1) planes whose row 0 and column 0 are zero.  One workgroup per row.
+// Workgroup 0 also sets up the breadth-first build: the root node in the first queue, one node at
+// level 0, none at the other levels and no leaves (counts: kMaxLevels level counts, then the u64
+// leaf count).
 __global__ __launch_bounds__(256) void k_sat_rows(const uint8_t* __restrict__ rgb, int32_t W, int32_t H,
-                                                  uint32_t* __restrict__ S, unsigned long long* __restrict__ Q) {
+                                                  uint32_t* __restrict__ S, unsigned long long* __restrict__ Q,
+                                                  QtNode* __restrict__ queue0, uint32_t* __restrict__ counts) {
     const int32_t y = blockIdx.x;
+    if (y == 0) {
+        if (threadIdx.x == 0) queue0[0] = QtNode{0, 0, W, H};
+        if (threadIdx.x < kMaxLevels + 2) counts[threadIdx.x] = threadIdx.x == 0 ? 1u : 0u;
+    }
     const size_t pitch = (size_t)W + 1, plane = pitch * ((size_t)H + 1);
     const int per = (W + 255) / 256;
     const int x0 = threadIdx.x * per, x1 = min(W, x0 + per);
@@ -81,8 +89,8 @@ __global__ __launch_bounds__(256) void k_sat_rows(const uint8_t* __restrict__ rg
 
 // Column pass: running sums down each column, in chunks of kColChunk rows so that the image's
 // height is covered by many threads (consecutive threads take consecutive columns, so every row
-// access is coalesced): the chunks' column sums, their exclusive prefix down each column, then the
-// running sums within each chunk from its prefix.
+// access is coalesced): the chunks' column sums, then the running sums within each chunk, started
+// from the sum of the chunks above it (read together, independent loads).
 constexpr int kColChunk = 16;
 
 __global__ __launch_bounds__(64) void k_sat_cols_part(int32_t W, int32_t H, const uint32_t* __restrict__ S,
@@ -105,26 +113,6 @@ __global__ __launch_bounds__(64) void k_sat_cols_part(int32_t W, int32_t H, cons
     }
 }
 
-__global__ __launch_bounds__(64) void k_sat_cols_scan(int32_t W, int32_t nchunks, uint32_t* __restrict__ TS,
-                                                      unsigned long long* __restrict__ TQ) {
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x > W) return;
-    const size_t pitch = (size_t)W + 1;
-    for (int c = 0; c < 3; ++c) {
-        uint32_t s = 0;
-        unsigned long long q = 0;
-        for (int32_t k = 0; k < nchunks; ++k) {
-            const size_t at = ((size_t)k * 3 + c) * pitch + x;
-            const uint32_t ts = TS[at];
-            const unsigned long long tq = TQ[at];
-            TS[at] = s;
-            TQ[at] = q;
-            s += ts;
-            q += tq;
-        }
-    }
-}
-
 __global__ __launch_bounds__(64) void k_sat_cols_apply(int32_t W, int32_t H, uint32_t* __restrict__ S,
                                                        unsigned long long* __restrict__ Q, const uint32_t* __restrict__ TS,
                                                        const unsigned long long* __restrict__ TQ) {
@@ -137,8 +125,12 @@ __global__ __launch_bounds__(64) void k_sat_cols_apply(int32_t W, int32_t H, uin
             S[c * plane + x] = 0u;
             Q[c * plane + x] = 0ull;
         }
-        uint32_t s = TS[((size_t)k * 3 + c) * pitch + x];
-        unsigned long long q = TQ[((size_t)k * 3 + c) * pitch + x];
+        uint32_t s = 0;
+        unsigned long long q = 0;
+        for (int32_t j = 0; j < k; ++j) {
+            s += TS[((size_t)j * 3 + c) * pitch + x];
+            q += TQ[((size_t)j * 3 + c) * pitch + x];
+        }
         for (int32_t y = y0; y <= y1; ++y) {
             const size_t at = c * plane + (size_t)y * pitch + x;
             s += S[at];
@@ -288,18 +280,13 @@ mrh_status mrh_quadtree_build(mrh_quadtree* q, const uint8_t* rgb_dev, int32_t w
         cap < 0 || !(threshold == threshold))
         return MRH_ERR_INVALID_ARG;
     hipStream_t s = q->stream;
-    hipLaunchKernelGGL(k_sat_rows, dim3(height), dim3(256), 0, s, rgb_dev, width, height, q->S, q->Q);
+    // the summed-area tables; the row pass also puts the root in the first queue and clears the counts
+    hipLaunchKernelGGL(k_sat_rows, dim3(height), dim3(256), 0, s, rgb_dev, width, height, q->S, q->Q, q->queue[0],
+                       q->counts);
     const int32_t chunks = (height + kColChunk - 1) / kColChunk;
     const dim3 cg((unsigned)((width + 1 + 63) / 64), (unsigned)chunks);
     hipLaunchKernelGGL(k_sat_cols_part, cg, dim3(64), 0, s, width, height, q->S, q->Q, q->TS, q->TQ);
-    hipLaunchKernelGGL(k_sat_cols_scan, dim3((unsigned)((width + 1 + 63) / 64)), dim3(64), 0, s, width, chunks, q->TS, q->TQ);
     hipLaunchKernelGGL(k_sat_cols_apply, cg, dim3(64), 0, s, width, height, q->S, q->Q, q->TS, q->TQ);
-    // the root, level 0 of one node, zero nodes at the other levels and no leaves yet
-    const QtNode root{0, 0, width, height};
-    uint32_t init[kMaxLevels + 2] = {1};
-    if (hipMemcpyAsync(q->queue[0], &root, sizeof(root), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(q->counts, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess)
-        return MRH_ERR_HIP;
     // levels: a node's shorter side halves at each split, so the tree is at most
     // log2(min(width, height)) + 2 levels deep
     int depth = 1;
