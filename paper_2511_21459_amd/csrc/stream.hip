@@ -443,7 +443,6 @@ static mrh_status read_counters(mrh_map* map, DevCounters& h) {
     return st;
 }
 
-// Upload blocks (keys, levels, plane words, optional sums) and run the insert kernel per level.
 // The pinned staging buffer, grown to at least `bytes` (its contents are not kept).
 static mrh_status grow_stage(mrh_map* map, mrh_stream_state* S, size_t bytes) {
     if (bytes <= S->stage_cap) return MRH_OK;
@@ -460,6 +459,7 @@ static mrh_status grow_stage(mrh_map* map, mrh_stream_state* S, size_t bytes) {
     return st;
 }
 
+// Upload blocks (keys, levels, plane words, optional sums) and run the insert kernel per level.
 static mrh_status stream_insert(mrh_map* map, const std::vector<unsigned long long>& keys, const std::vector<int>& levels,
                                 const std::vector<const uint8_t*>& words, const std::vector<double>& vsum,
                                 const std::vector<uint32_t>& vcnt, int sums, std::vector<uint32_t>& outcome) {
