@@ -21,11 +21,13 @@
 // outside.  Vertex collapse: a surface point closer than collapse * nu_n to an end of its edge is
 // moved onto that end, and triangles with two vertices on one point are dropped.
 //
-// Launch: one wave per block, four blocks per workgroup.  The wave caches the 27 blocks
-// around its block (ids and levels, one probe per lane) and its block's TSDF (NaN where W = 0) in
-// LDS; cubes whose corners all lie in the block read LDS only, the others evaluate the interpolant
-// through the cached neighbours.  A first pass counts each cube's triangles, one atomic per
-// workgroup reserves the output range, a second pass recomputes the surface cubes and writes.
+// Launch: one wave per block, four blocks of one level per workgroup (a small kernel lists the
+// block ids by level first, so that the waves of a workgroup, which meet at barriers, do work of
+// one size).  The wave caches the 27 blocks around its block (ids and levels, one probe per lane)
+// and stages its cubes' corner lattice in LDS: its own voxels (TSDF, NaN where W = 0) read
+// coalesced in heap order, then the upper-face corners from the cached neighbours, each lane's
+// reads issued together.  A first pass counts each cube's triangles, one atomic per workgroup
+// reserves the output range, a second pass recomputes the surface cubes and writes.
 #include <cmath>
 
 #include "mrh_store.h"
