@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ m
     __shared__ unsigned long long tab[kSatSlots];
     const int i = entry_of(ents, n, blockIdx.x, true);
     if (i < 0) return;  // uniform across the workgroup
-    points_ray_chunk<ST>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
+    points_ray_chunk<ST, true>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
 }
 
 template <int ST, int KIND>

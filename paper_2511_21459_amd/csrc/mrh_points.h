@@ -256,7 +256,7 @@ struct BoxWalk {
 // The observations of one ray (segment a..e, surface point p, direction nn) inside the block
 // `key` (block id `id`, kInvalidId when it has none) that its walk visits: the block walk restricted
 // to the block's own voxel lattice.
-template <int ST>
+template <int ST, bool QUEUE>
 __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const double a[3], const double e[3],
                                  const double p[3], const double nn[3], unsigned long long key, uint32_t id,
                                  unsigned long long* tab) {
@@ -292,14 +292,51 @@ __device__ inline void ray_block(const DevMap& m, const ScanParams& sp, const do
             if (s == 3 * side || !bw.next()) break;
         }
     }
-    // mark the groups; the ray that sets the block's first bit this scan queues it for the update
-    // (exactly one: the walk observes at least one voxel, so groups != 0)
-    bool first = false;
-    if (has) {
-        const unsigned long long cur = m.btouch[id];
-        if ((cur & groups) != groups) first = atomicOr(&m.btouch[id], groups) == 0ull;
+    // mark the groups.  With QUEUE, the ray that sets the block's first bit this scan queues it for
+    // the update (exactly one: the walk observes at least one voxel, so groups != 0); without, the
+    // OR returns nothing and queue_touched queues the touched blocks after the launch.
+    if (QUEUE) {
+        bool first = false;
+        if (has) {
+            const unsigned long long cur = m.btouch[id];
+            if ((cur & groups) != groups) first = atomicOr(&m.btouch[id], groups) == 0ull;
+        }
+        if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key, sp.parity);
+    } else if (has) {
+        // most rays through a block find their groups already marked: reading first keeps the
+        // same-address atomics (thousands per block near the sensor) off the memory side
+        if ((m.btouch[id] & groups) != groups) atomicOr(&m.btouch[id], groups);
     }
-    if (__ballot(first)) queue_block(m, first ? level : -1, id, info, key, sp.parity);
+}
+
+// The blocks the scan's rays touched (non-zero touch mask), queued per level for the update: block
+// ids first .. first + count - 1 of this workgroup's range, positions taken in LDS and one atomic
+// per level per workgroup (every thread of the workgroup calls).
+constexpr int kTouchPerThread = 8;
+
+__device__ inline void queue_touched(const DevMap& m, uint32_t first, uint32_t count, int par) {
+    __shared__ uint32_t lcnt[4], lbase[4];
+    if (threadIdx.x < 4) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int lvl[kTouchPerThread];
+    uint32_t pos[kTouchPerThread];
+    for (int r = 0; r < kTouchPerThread; ++r) {
+        const uint32_t k = (uint32_t)r * blockDim.x + threadIdx.x;  // consecutive threads, consecutive ids
+        lvl[r] = -1;
+        pos[r] = 0;
+        if (k < count && m.btouch[first + k] != 0ull) {
+            lvl[r] = (int)((m.binfo[first + k] >> kLevelShift) & 3u);
+            pos[r] = atomicAdd(&lcnt[lvl[r]], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && lcnt[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&m.ctr->vis_n[par][threadIdx.x].v, lcnt[threadIdx.x]);
+    __syncthreads();
+    for (int r = 0; r < kTouchPerThread; ++r) {
+        if (lvl[r] < 0) continue;
+        const uint32_t id = first + (uint32_t)r * blockDim.x + threadIdx.x;
+        m.vis[lvl[r]][lbase[lvl[r]] + pos[r]] = make_entry(id, m.binfo[id], m.bkey[id]);
+    }
 }
 
 // Rays per wave of the ray launch, and per 256-thread workgroup.
@@ -311,7 +348,7 @@ constexpr int kRaysPerGroup = 4 * kRaysPerWave;
 // lookups, so the (ray, block) pairs that the allocation launch recorded are processed in parallel
 // instead: each wave takes its kRaysPerWave rays' pairs 64 at a time, lane l the l-th pair of the
 // batch.  The blocks of a ray beyond the recorded rcap_k are walked afterwards by the ray's lane.
-template <int ST>
+template <int ST, bool QUEUE>
 __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, uint32_t chunk, unsigned long long* tab) {
     sat_table_clear(tab);
     const int lane = lane_id();
@@ -367,7 +404,7 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
             const bool ok = slot != kInvalidId;
             const unsigned long long key = ok ? m.hkeys[slot] : 0ull;
             const uint32_t id = ok ? m.hvals[slot] : kInvalidId;
-            ray_block<ST>(m, sp, sa, se, sp3, sn, key, id, tab);
+            ray_block<ST, QUEUE>(m, sp, sa, se, sp3, sn, key, id, tab);
         }
     }
     if (cnt > K) {
@@ -382,7 +419,7 @@ __device__ inline void points_ray_chunk(const DevMap& m, const ScanParams& sp, u
             const unsigned long long key = pack_key(w.c0, w.c1, w.c2);
             wsave[wv][lane] = w;
             __asm__ volatile("" ::: "memory");
-            ray_block<ST>(m, sp, a, e, p, nn, key, find_block(m, key), tab);
+            ray_block<ST, QUEUE>(m, sp, a, e, p, nn, key, find_block(m, key), tab);
             __asm__ volatile("" ::: "memory");
             w = wsave[wv][lane];
             more = w.next();

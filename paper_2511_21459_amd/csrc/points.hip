@@ -18,7 +18,17 @@ __global__ __launch_bounds__(256) void k_alloc_points(const DevMap* __restrict__
 template <int ST>
 __global__ __launch_bounds__(256) void k_rays(const DevMap* __restrict__ pm, ScanParams sp) {
     __shared__ unsigned long long tab[kSatSlots];
-    points_ray_chunk<ST>(*pm, sp, blockIdx.x, tab);
+    points_ray_chunk<ST, false>(*pm, sp, blockIdx.x, tab);
+}
+
+// After the ray launch: the touched blocks onto the update queues (workgroup w takes block ids
+// w * 256 * kTouchPerThread onwards).
+__global__ __launch_bounds__(256) void k_touch_queue(const DevMap* __restrict__ pm, int par) {
+    const DevMap& m = *pm;
+    const uint32_t nb = min(m.ctr->n_blocks, m.max_blocks);
+    const uint32_t per = blockDim.x * (uint32_t)kTouchPerThread;
+    for (uint32_t first = blockIdx.x * per; first < nb; first += gridDim.x * per)
+        queue_touched(m, first, min(per, nb - first), par);
 }
 
 template <int ST>
@@ -118,6 +128,7 @@ extern "C" mrh_status mrh_integrate_points(mrh_map* map, const float* xyz_dev, i
                 case MRH_STORE_BF16: hipLaunchKernelGGL(k_rays<MRH_STORE_BF16>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp); break;
                 default: hipLaunchKernelGGL(k_rays<MRH_STORE_F32>, dim3(rgrid), dim3(256), 0, map->stream, map->dmd, sp);
             }
+            hipLaunchKernelGGL(k_touch_queue, dim3(1024), dim3(256), 0, map->stream, map->dmd, par);
         });
     }
     launch(map, K_APPLY_POINTS, [&] {
