@@ -311,9 +311,9 @@ mrh_status mrh_profile_enable(mrh_map* map, int32_t on);
 mrh_status mrh_profile_collect(mrh_map* map, double* ms, int64_t* launches, int32_t n_kernels);
 
 /* ---- Batched fusion of many independent maps ------------------------------------------------
- * One call fuses one frame into each map of the batch with at most four launches in total
- * (allocation and culling of every map, LiDAR traversal of the LiDAR maps, and one update launch
- * per frame kind present), captured once into a HIP graph and replayed on later calls with the same
+ * One call fuses one frame into each map of the batch with at most five launches in total
+ * (allocation and culling of every map, LiDAR traversal of the LiDAR maps and the queueing of the
+ * blocks it touched, and one update launch per frame kind present), captured once into a HIP graph and replayed on later calls with the same
  * frame kinds and sizes; each frame's hand-offs run inside these launches as in the single-map
  * calls.  Per-map
  * results are identical to calling mrh_integrate_depth / mrh_integrate_points map by map. */

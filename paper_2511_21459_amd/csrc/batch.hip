@@ -1,4 +1,4 @@
-// Batched fusion of many independent maps: one frame per map per call, at most four launches in
+// Batched fusion of many independent maps: one frame per map per call, at most five launches in
 // total, each covering every map (of its kind) through device-side tables (the per-map work is exactly that of the
 // single-map path, frame hand-offs included), captured once into a HIP graph and replayed while
 // the frame sizes stay fixed.
@@ -8,6 +8,7 @@
 //                     last workgroup also runs its allocation-side hand-off
 //   k_batch_rays      LiDAR maps: one workgroup per kRaysPerGroup rays (their recorded (ray, block)
 //                     pairs in parallel: traversal and accumulation)
+//   k_batch_touch     LiDAR maps: the blocks the rays touched onto the map's update queues
 //   k_batch_update    the update tasks of every map of one frame kind (RGB-D or LiDAR: one launch
 //                     per kind present, so that each gets the registers of its own path), strided
 //                     over the concatenated task space; workgroup i also runs the update-side
@@ -78,7 +79,22 @@ __global__ __launch_bounds__(256) void k_batch_rays(const DevMap* __restrict__ m
     __shared__ unsigned long long tab[kSatSlots];
     const int i = entry_of(ents, n, blockIdx.x, true);
     if (i < 0) return;  // uniform across the workgroup
-    points_ray_chunk<ST, true>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
+    points_ray_chunk<ST, false>(maps[i], ents[i].sp, blockIdx.x - ents[i].ray_begin, tab);
+}
+
+// After the ray launch: each LiDAR map's touched blocks onto its update queues, kBatchTouchWgs
+// workgroups per table entry (those of RGB-D entries return at once).
+constexpr uint32_t kBatchTouchWgs = 64;
+
+__global__ __launch_bounds__(256) void k_batch_touch(const DevMap* __restrict__ maps, const BatchEntry* __restrict__ ents,
+                                                     int n) {
+    const int i = (int)(blockIdx.x / kBatchTouchWgs);
+    if (i >= n || ents[i].kind != MRH_FRAME_POINTS) return;  // uniform across the workgroup
+    const DevMap& m = maps[i];
+    const uint32_t nb = min(m.ctr->n_blocks, m.max_blocks);
+    const uint32_t per = blockDim.x * (uint32_t)kTouchPerThread;
+    for (uint32_t first = (blockIdx.x % kBatchTouchWgs) * per; first < nb; first += kBatchTouchWgs * per)
+        queue_touched(m, first, min(per, nb - first), ents[i].sp.parity);
 }
 
 template <int ST, int KIND>
@@ -199,6 +215,7 @@ static void enqueue_step(mrh_batch* b, hipStream_t s, uint32_t alloc_wgs, uint32
             case MRH_STORE_BF16: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_BF16>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n); break;
             default: hipLaunchKernelGGL(k_batch_rays<MRH_STORE_F32>, dim3(ray_wgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
         }
+        hipLaunchKernelGGL(k_batch_touch, dim3((unsigned)n * kBatchTouchWgs), dim3(256), 0, s, b->d_maps, b->d_ents, n);
     }
     // at least one workgroup per map: workgroup i carries map i's update-side hand-off
     const dim3 ug((unsigned)(b->update_wgs > n ? b->update_wgs : n)), ub((unsigned)(64 * b->update_waves));

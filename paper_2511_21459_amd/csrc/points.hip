@@ -1,8 +1,9 @@
 // LiDAR fusion of one map (Sec. 3.1 "3D Point Cloud", Eq. 1; Eq. 3, Eq. 5; Sec. 3.2.1).
 //
-// One scan is three launches on the map's stream: k_alloc_points (its last workgroup also runs the
-// allocation-side frame hand-off), k_rays and k_apply_points (update tasks over the per-level queues
-// of touched blocks; workgroup 0 also runs the update-side hand-off).
+// One scan is four launches on the map's stream: k_alloc_points (its last workgroup also runs the
+// allocation-side frame hand-off), k_rays, k_touch_queue (the touched blocks onto the per-level
+// update queues) and k_apply_points (update tasks over those queues; workgroup 0 also runs the
+// update-side hand-off).
 #include <cmath>
 
 #include "mrh_points.h"
