@@ -484,7 +484,7 @@ def run_street(args, torch, np, mrh, configs):
         "kernels_ms_per_scan": {k: round(v[0] / n, 4) for k, v in prof.items()},
         "distinct_voxels_per_step": distinct, "queued_blocks_per_step": queued,
         "candidate_keys_per_step": sum(f["candidate_keys"] for f in census),
-        "roofline": {"kernel": "scan (k_alloc_points + k_rays + k_apply_points)", "bound": "hbm",
+        "roofline": {"kernel": "scan (k_alloc_points + k_rays + k_touch_queue + k_apply_points)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_scan": int(scan_bytes / n), "kernel_ms_per_scan": round(scan_s * 1e3 / n, 4)},
