@@ -287,7 +287,7 @@ enum {
     MRH_KERNEL_INTEGRATE_DEPTH = 2, /* RGB-D projective update, variance, merge */
     MRH_KERNEL_FINALIZE = 3,        /* reserved: the frame hand-off runs inside the other launches; stays 0 */
     MRH_KERNEL_ALLOC_POINTS = 4,    /* LiDAR allocation */
-    MRH_KERNEL_RAYS = 5,            /* LiDAR ray traversal and accumulation */
+    MRH_KERNEL_RAYS = 5,            /* LiDAR ray traversal and accumulation, then queueing of touched blocks */
     MRH_KERNEL_APPLY_POINTS = 6,    /* LiDAR state update, variance, merge */
     MRH_KERNEL_QUERY = 7,
     MRH_KERNEL_QUERY_BACKWARD = 8,
@@ -297,7 +297,7 @@ enum {
     MRH_KERNEL_BATCH_UPDATE = 12,   /* batched: update tasks of every map */
     MRH_KERNEL_BATCH_FINALIZE = 13, /* reserved, as MRH_KERNEL_FINALIZE; stays 0 */
     MRH_KERNEL_BATCH_GRAPH = 14,    /* batched: one replay of the captured step */
-    MRH_KERNEL_MESH = 15,           /* multi-resolution Marching Cubes */
+    MRH_KERNEL_MESH = 15,           /* multi-resolution Marching Cubes (with its block ordering by level) */
     MRH_KERNEL_COLOR = 16,          /* colour integration of an RGB-D frame */
     MRH_KERNEL_COUNT = 17
 };
