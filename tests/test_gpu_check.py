@@ -78,3 +78,45 @@ def test_check_after_streaming(mrh):
     assert c2["blocks"] == c0["blocks"] + n_out
     assert c2["table_keys"] == c0["table_keys"] and c2["live_blocks"] == c0["live_blocks"]
     assert c2["free_slots"] == c0["free_slots"]
+
+
+def test_extract_blocks_buffer_too_small(mrh):
+    """mrh_extract_blocks refuses buffers smaller than the map (MRH_ERR_BUFFER_TOO_SMALL, -5) before
+    writing anything, with both counts still set; exact sizes succeed and match the count call."""
+    import ctypes
+
+    from workloads import sphere_plane_frame
+
+    announce("extract: buffer-too-small path, sphere-plane frame")
+    depth, cam, T = sphere_plane_frame(seed=0)
+    g = mrh.Map(**configs.SPHERE_PLANE)
+    g.integrate_depth(_dev(depth), cam.K, T)
+    g.sync()
+    nb, nv = g.counts()
+    assert nb > 100 and nv == nb * 512
+    L = mrh._lib.load()
+    keys = torch.empty((nb, 3), dtype=torch.int32, device="cuda")
+    levels = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    offs = torch.empty(nb + 1, dtype=torch.int64, device="cuda")
+    D = torch.empty(nv, dtype=torch.float32, device="cuda")
+    W = torch.empty(nv, dtype=torch.int32, device="cuda")
+    S2 = torch.empty(nv, dtype=torch.float32, device="cuda")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    a, b = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    # one block short
+    st = L.mrh_extract_blocks(g._h, ptr(keys), ptr(levels), None, None, None, None, nb - 1, 0, ctypes.byref(a),
+                              ctypes.byref(b))
+    assert st == -5 and (a.value, b.value) == (nb, nv)
+    # one voxel short (the block capacity is enough)
+    a.value = b.value = -1
+    st = L.mrh_extract_blocks(g._h, ptr(keys), ptr(levels), ptr(offs), ptr(D), ptr(W), ptr(S2), nb, nv - 1,
+                              ctypes.byref(a), ctypes.byref(b))
+    assert st == -5 and (a.value, b.value) == (nb, nv)
+    assert "extract needs" in L.mrh_last_error(g._h).decode()
+    # exact sizes
+    st = L.mrh_extract_blocks(g._h, ptr(keys), ptr(levels), ptr(offs), ptr(D), ptr(W), ptr(S2), nb, nv,
+                              ctypes.byref(a), ctypes.byref(b))
+    assert st == 0 and (a.value, b.value) == (nb, nv)
+    assert int(offs[-1].item()) == nv
+    e = g.extract()
+    assert torch.equal(e["keys"], keys) and torch.equal(e["W"], W)
