@@ -127,14 +127,28 @@ __global__ __launch_bounds__(64) void k_sat_cols_apply(int32_t W, int32_t H, uin
         }
         uint32_t s = 0;
         unsigned long long q = 0;
+#pragma unroll 8
         for (int32_t j = 0; j < k; ++j) {
             s += TS[((size_t)j * 3 + c) * pitch + x];
             q += TQ[((size_t)j * 3 + c) * pitch + x];
         }
-        for (int32_t y = y0; y <= y1; ++y) {
+        // the chunk's rows read first (independent loads), then the running sums written
+        uint32_t rs[kColChunk];
+        unsigned long long rq[kColChunk];
+#pragma unroll
+        for (int32_t r = 0; r < kColChunk; ++r) {
+            const int32_t y = y0 + r;
             const size_t at = c * plane + (size_t)y * pitch + x;
-            s += S[at];
-            q += Q[at];
+            rs[r] = y <= y1 ? S[at] : 0u;
+            rq[r] = y <= y1 ? Q[at] : 0ull;
+        }
+#pragma unroll
+        for (int32_t r = 0; r < kColChunk; ++r) {
+            const int32_t y = y0 + r;
+            if (y > y1) break;
+            const size_t at = c * plane + (size_t)y * pitch + x;
+            s += rs[r];
+            q += rq[r];
             S[at] = s;
             Q[at] = q;
         }
