@@ -103,10 +103,12 @@ __global__ __launch_bounds__(64) void k_sat_cols_part(int32_t W, int32_t H, cons
     for (int c = 0; c < 3; ++c) {
         uint32_t s = 0;
         unsigned long long q = 0;
-        for (int32_t y = y0; y <= y1; ++y) {
+#pragma unroll
+        for (int32_t r = 0; r < kColChunk; ++r) {
+            const int32_t y = y0 + r;
             const size_t at = c * plane + (size_t)y * pitch + x;
-            s += S[at];
-            q += Q[at];
+            s += y <= y1 ? S[at] : 0u;
+            q += y <= y1 ? Q[at] : 0ull;
         }
         TS[((size_t)k * 3 + c) * pitch + x] = s;
         TQ[((size_t)k * 3 + c) * pitch + x] = q;
